@@ -1,0 +1,316 @@
+#!/usr/bin/env python3
+"""Benchmark of the stencil hot path on one MI355X.
+
+Default workload (the headline): 7-point FP64 Jacobi on a 512^3 interior
+with a one-cell zero Dirichlet halo, right-hand side = 8 Gaussian sources
+(seed 1), zero start; one step = 1000 sweeps, each with the residual norm
+of its input fused in, plus the trailing residual of the last iterate.
+Inputs are generated on the host, copied to HBM, and resident before the
+timed region. Prints ONE JSON line on stdout (progress goes to stderr).
+
+    python bench.py [--steps K] [--warmup W] [--mode jacobi|f32|advect|solve]
+
+Other modes time the FP32-storage sweeps (same grid), the advection source
+term (512 x 512 x 256, one pass per step) and the time to a 1e-8 relative
+residual at 128^3 for plain FP64 vs FP32-refined solves.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def src_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2310_01882_amd", "csrc", n), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel_key, sources, launches_per_step_unit):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+    None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(kernel_key)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != src_hash(*sources):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_threads():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def event_time(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / 1e3  # seconds
+
+
+def bench_jacobi(args, dtype_name="f64"):
+    import numpy as np
+    import torch
+    import paper_2310_01882_amd as ms
+    import synth
+
+    n, sweeps = args.n, args.sweeps
+    np_dt = np.float64 if dtype_name == "f64" else np.float32
+    log(f"[bench] generating 512^3-class inputs n={n} ({dtype_name})")
+    f_h = synth.gaussian_sources(n, n, n, 8, 1)
+    u_h = synth.zeros(n, n, n)
+    dev = torch.device("cuda:0")
+    u = torch.from_numpy(u_h.astype(np_dt)).to(dev)
+    tmp = u.clone()
+    f = torch.from_numpy(f_h.astype(np_dt)).to(dev)
+    res = torch.zeros(sweeps + 1, dtype=torch.float64, device=dev)
+    work = ms.jacobi_sweeps_workspace(u)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ms.jacobi_sweeps(u, tmp, sweeps, f=f, res=res, work=work, stream=stream)
+
+    log(f"[bench] warmup {args.warmup} + timed {args.steps} steps of {sweeps} sweeps")
+    secs = event_time(step, args.steps, args.warmup, stream)
+    cells = n ** 3
+    lups = cells * sweeps * args.steps
+    glups = lups / secs / 1e9
+    bpl = 24 if dtype_name == "f64" else 12  # read u and f, write u'
+    launch_s = secs / (sweeps * args.steps)  # every sweep launch, trailing passes included
+    achieved = bpl * cells / launch_s / 1e9
+    log(f"[bench] {glups:.1f} GLUP/s, {achieved:.0f} GB/s algorithmic, "
+        f"{launch_s * 1e6:.1f} us per sweep launch; final residual {res[-1].item():.6e}")
+    key = f"jacobi7_{dtype_name}_{n}"
+    traffic = traffic_for(key, ["jacobi.hip", "ms_internal.hpp"], 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_jacobi(u_h, f_h, np_dt, args.cpu_sweeps)
+    del u, tmp, f
+    out = {
+        "metric": "GLUP/s (FP64 7-point Jacobi, 512^3, with fused residual norm)"
+        if dtype_name == "f64" else "GLUP/s (FP32-storage 7-point Jacobi sweeps, 512^3, FP64 norms)",
+        "value": round(glups, 3),
+        "unit": "GLUP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(secs / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype_name,
+        "data": "synthetic",
+        "config": {
+            "workload": f"jacobi7_{dtype_name}_{n}cubed_{sweeps}sweeps",
+            "interior": [n, n, n],
+            "halo": 1,
+            "sweeps_per_step": sweeps,
+            "rhs": "8 Gaussian sources (seed 1)",
+            "boundary": "zero Dirichlet",
+            "residual": "fused per sweep + trailing pass",
+            "parallelism": "single GPU",
+        },
+        "gb_per_s_algorithmic": round(achieved, 1),
+        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "sweep_kernel<%s>" % ("double" if dtype_name == "f64" else "float"),
+            "bytes_per_launch_algorithmic": bpl * cells,
+            "avg_launch_us": round(launch_s * 1e6, 3),
+        },
+        "cpu_baseline": cpu,
+    }
+    return out
+
+
+def cpu_baseline_jacobi(u_h, f_h, np_dt, nsweeps):
+    """The oracle as it stands, timed on the host on a bounded sample of the
+    same workload: ``nsweeps`` sweeps of the same 512^3 input, each with its
+    residual norm (what one GPU sweep launch computes)."""
+    import numpy as np
+    import oracle
+    log(f"[bench] cpu baseline: {nsweeps} oracle sweeps of the same input")
+    u = u_h.astype(np_dt)
+    f = f_h.astype(np_dt)
+    cells = (u.shape[0] - 2) * (u.shape[1] - 2) * (u.shape[2] - 2)
+    t = time.perf_counter()
+    for _ in range(nsweeps):
+        if np_dt == np.float64:
+            oracle.residual_norm(u, f)
+            u = oracle.jacobi_sweep(u, f)
+        else:
+            oracle.residual_norm_f32_storage(u, f)
+            u = oracle.sweep_f32(u, f)
+    dt = time.perf_counter() - t
+    return {
+        "value": round(cells * nsweeps / dt / 1e9, 5),
+        "unit": "GLUP/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{nsweeps} sweeps + residual norms of the 512^3 input (numpy, one thread)",
+        "seconds": round(dt, 2),
+        "host_threads_available": cpu_threads(),
+    }
+
+
+def bench_advect(args):
+    import numpy as np
+    import torch
+    import paper_2310_01882_amd as ms
+    import synth
+
+    nx, ny, nz = 512, 512, 256
+    log("[bench] generating advection inputs 512x512x256")
+    u_h, v_h, w_h = synth.velocity_fields(nx, ny, nz, 2)
+    t1_h, t2_h = synth.tzc_arrays(nz, 3)
+    dev = torch.device("cuda:0")
+    u, v, w = (torch.from_numpy(a).to(dev) for a in (u_h, v_h, w_h))
+    t1, t2 = torch.from_numpy(t1_h).to(dev), torch.from_numpy(t2_h).to(dev)
+    su, sv, sw = (torch.empty_like(u) for _ in range(3))
+    stream = torch.cuda.current_stream()
+
+    def step():
+        ms.advect_source(u, v, w, t1, t2, 0.25, 0.25, su, sv, sw, stream=stream)
+
+    passes = max(args.steps, 1) * 20
+    secs = event_time(step, passes, max(args.warmup, 1) * 5, stream)
+    cells = nx * ny * nz
+    gcells = cells * passes / secs / 1e9
+    achieved = 48 * cells / (secs / passes) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sl = slice(0, 34)  # 32 interior levels
+        t = time.perf_counter()
+        oracle.advect_source(u_h[sl], v_h[sl], w_h[sl], t1_h[:32], t2_h[:32], 0.25, 0.25)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(nx * ny * 32 / dt / 1e9, 5), "unit": "Gcell/s", "cores": 1,
+               "kind": "oracle", "sample": "one pass over 32 of the 256 levels (numpy, one thread)",
+               "seconds": round(dt, 2)}
+    return {
+        "metric": "Gcell/s (fused 3-field advection source term, FP64)",
+        "value": round(gcells, 3), "unit": "Gcell/s", "n_gpus": 1, "steps": passes,
+        "warmup": max(args.warmup, 1) * 5, "ms_per_step": round(secs / passes * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "pw_advection_512x512x256", "interior": [nx, ny, nz],
+                   "fields": "16-sinusoid u,v,w (seed 2); tzc1,tzc2 ~U[0.5,2] (seed 3)",
+                   "tcx": 0.25, "tcy": 0.25, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_for("advect_512x512x256", ["advect.hip"], 1),
+                     "kernel": "advect_kernel", "bytes_per_launch_algorithmic": 48 * cells,
+                     "avg_launch_us": round(secs / passes * 1e6, 3)},
+        "cpu_baseline": cpu,
+    }
+
+
+def bench_solve(args):
+    """Time to a 1e-8 relative residual at 128^3 (8 Gaussian sources, zero
+    Dirichlet boundary, zero start): plain FP64 vs FP32-refined."""
+    import torch
+    import paper_2310_01882_amd as ms
+    import synth
+
+    n = args.solve_n
+    f_h = synth.gaussian_sources(n, n, n, 8, 1)
+    dev = torch.device("cuda:0")
+    f = torch.from_numpy(f_h).to(dev)
+    rows = {}
+    for name, kw in (("fp64", dict(precision=ms.MS_SOLVE_F64)),
+                     ("fp32_refined", dict(precision=ms.MS_SOLVE_F32_REFINED, inner_eta=1e-4))):
+        u = torch.zeros((n + 2,) * 3, dtype=torch.float64, device=dev)
+        work = ms.jacobi_workspace(u, ms.solve_opts(**kw))
+        ms.jacobi_solve(u.clone(), f, work=work, rel_tol=1e-3, **kw)  # warm-up (graphs, caches)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = ms.jacobi_solve(u, f, work=work, rel_tol=1e-8, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rows[name] = {"seconds": round(dt, 4), "sweeps": info.sweeps,
+                      "outer": info.outer_iters, "rel_final": info.rel_final,
+                      "glups": round(n ** 3 * info.sweeps / dt / 1e9, 2)}
+        log(f"[bench] {name}: {dt:.3f} s, {info.sweeps} sweeps, rel {info.rel_final:.3e}")
+    return {
+        "metric": "seconds to 1e-8 relative residual (128^3 Poisson)",
+        "value": rows["fp32_refined"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+        "warmup": 1, "ms_per_step": rows["fp32_refined"]["seconds"] * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"poisson_{n}cubed_to_1e-8", "rhs": "8 Gaussian sources (seed 1)"},
+        "solves": rows,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--mode", choices=["jacobi", "f32", "advect", "solve"], default="jacobi")
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--solve-n", type=int, default=128)
+    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build runs on one GPU only; the multi-GPU halo-exchange path is "
+              "a design (no collectives are built), so --gpus must be 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    if args.mode == "jacobi":
+        out = bench_jacobi(args, "f64")
+    elif args.mode == "f32":
+        out = bench_jacobi(args, "f32")
+    elif args.mode == "advect":
+        out = bench_advect(args)
+    else:
+        out = bench_solve(args)
+    out["device"] = torch.cuda.get_device_name(0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

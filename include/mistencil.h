@@ -1,0 +1,217 @@
+/*
+ * mistencil -- structured-grid 3D stencil sweeps for MI355X (gfx950).
+ *
+ * C ABI of the hot path of Brown et al., "Fortran performance optimisation
+ * and auto-parallelisation by leveraging MLIR-based domain specific
+ * abstractions in Flang" (SC-W 2023): the stencils its stencil-discovery
+ * flow extracts from Fortran loop nests (Section 3) -- the 7-point Laplace
+ * iteration and the fused Piacsek-Williams advection source term of the
+ * evaluation (Section 4.1) -- plus the residual-norm reduction that decides
+ * convergence, FP32-storage refinement, batched solves and a learned warm
+ * start.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Fields. A field lives in caller-owned device memory. Its layout follows
+ * the paper's Fortran column-major order (first index contiguous, Section
+ * 2.2): element (i, j, k), i = x, sits at
+ *     base[(k + 1) * sz + (j + 1) * sy + (i + 1)]
+ * for halo-inclusive indices i in [-1, nx], j in [-1, ny], k in [-1, nz];
+ * the base pointer addresses halo cell (-1, -1, -1). The interior is
+ * [0, nx) x [0, ny) x [0, nz) and the halo is one cell wide, as the bounds
+ * of stencil.apply's input and output temps in Listing 2 show. Strides are
+ * in elements, x stride is 1, sy >= nx + 2 and sz >= sy * (ny + 2) (a padded
+ * pitch is allowed). Outputs are written on the interior only; the halo of
+ * an output is never touched.
+ *
+ * Streams. `stream` is a hipStream_t passed as void*; NULL is the default
+ * stream. Entry points marked "async" only enqueue work. Host structs are
+ * read before the call returns.
+ *
+ * Ownership. The library keeps no pointer after a call returns (except for
+ * work still in flight on `stream`) and allocates no field-sized memory:
+ * scratch comes from a caller-owned device workspace whose size the
+ * matching *_workspace_bytes function returns.
+ *
+ * Errors. Every int-returning entry point returns one of the MS_* codes
+ * below; no exception crosses the ABI. ms_last_error() returns a
+ * thread-local message for the last non-OK return on the calling thread.
+ */
+#ifndef MISTENCIL_H
+#define MISTENCIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MS_OK 0
+#define MS_NOT_CONVERGED 1  /* solve hit its sweep/outer cap; result filled */
+#define MS_EINVAL (-1)      /* null pointer, bad extents/strides, aliasing, |offset| > 1 */
+#define MS_EUNSUPPORTED (-2) /* dtype, tap count or option not supported */
+#define MS_EHIP (-3)        /* HIP runtime error (message in ms_last_error) */
+#define MS_EWORKSPACE (-4)  /* workspace missing or too small */
+#define MS_ENONFINITE (-5)  /* a residual norm came out NaN or Inf */
+
+/* ---- element types --------------------------------------------------- */
+#define MS_F64 0
+#define MS_F32 1
+
+/* ---- grid descriptor ------------------------------------------------- */
+typedef struct {
+  int32_t nx, ny, nz; /* interior extents, each >= 1 */
+  int32_t reserved;   /* must be 0 */
+  int64_t sy, sz;     /* element strides of y and z (x stride is 1) */
+} ms_grid;
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* ms_last_error(void);
+
+/* Library version string. */
+const char* ms_version(void);
+
+/* ---- general constant-offset stencil ----------------------------------
+ * The paper's stencil.apply (Section 2.2, Listing 2): a region evaluated at
+ * every interior cell p that reads the input at constant offsets:
+ *   out[p] = scale * ((...((w0*in[p+o0]) + w1*in[p+o1]) + ...) + rhs_coef*rhs[p])
+ * accumulated in tap order, in the arithmetic of `dtype` (weights and
+ * coefficients are rounded to FP32 for MS_F32). The rhs term is present only
+ * when rhs != NULL. 1 <= ntaps <= 27, each |dx|,|dy|,|dz| <= 1.
+ * in, rhs and out share the grid `g`. out may not alias in or rhs (the
+ * apply is out-of-place) -> MS_EINVAL. Async. */
+typedef struct {
+  int8_t dx, dy, dz;
+  int8_t reserved[5];
+  double w;
+} ms_tap;
+
+typedef struct {
+  int32_t ntaps;
+  int32_t reserved;
+  const ms_tap* taps; /* host array of ntaps taps */
+  double rhs_coef;
+  double scale;
+} ms_stencil;
+
+int stencil_apply(const ms_stencil* st, const ms_grid* g, int dtype,
+                  const void* in, const void* rhs, void* out, void* stream);
+
+/* ---- residual norm ------------------------------------------------------
+ * ||f - L(u)||_2 over the interior, L(u) = S(u) - 6u with S the six-neighbour
+ * sum of the 7-point Laplace stencil (Section 4.1), evaluated per cell as
+ * r = f - (S - u*6) and accumulated in FP64 (FP32 fields are widened
+ * exactly first). f may be NULL (Laplace, f = 0). The reduction order is
+ * fixed, so repeated calls give identical bits.
+ * norm_out: device pointer if out_on_device != 0 (async), else host pointer
+ * (the call then synchronises `stream`).
+ * work: device workspace of at least residual_workspace_bytes(g) bytes. */
+size_t residual_workspace_bytes(const ms_grid* g);
+int residual_norm(const ms_grid* g, int dtype, const void* u, const void* f,
+                  double* norm_out, int out_on_device, void* work,
+                  size_t work_bytes, void* stream);
+
+/* ---- fixed number of Jacobi sweeps -------------------------------------
+ * The 7-point Laplace/Poisson iteration of Section 4.1 as an out-of-place
+ * (Jacobi) update, u'(p) = (S(p) - f(p)) * fl(1/6) (u'(p) = S(p) * fl(1/6)
+ * when f is NULL), with ping-pong buffers u and u_tmp (same grid; u_tmp's
+ * halo must hold the same Dirichlet values as u's). Exactly n >= 0 sweeps.
+ * u_n lands in u if n is even, else in u_tmp.
+ * res_dev (device, may be NULL): n + 1 doubles, res_dev[k] = ||r(u_k)||,
+ * k = 0..n; entries 0..n-1 come from the residual fused into each sweep,
+ * entry n from one trailing residual pass.
+ * dtype MS_F64, or MS_F32 (FP32 storage and sweep arithmetic, FP64 norms).
+ * work: jacobi_sweeps_workspace_bytes(g) bytes. Async. */
+size_t jacobi_sweeps_workspace_bytes(const ms_grid* g);
+int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                  const void* f, int64_t n, double* res_dev, void* work,
+                  size_t work_bytes, void* stream);
+
+/* ---- convergence-controlled solve ----------------------------------------
+ * Relative-residual Jacobi solve of L(u) = f with Dirichlet halo.
+ * res0 = ||r(u^0)||, u^0 = u with its interior zeroed (same halo, same f);
+ * the answer is u_K with K the smallest k >= 0 such that
+ * ||r(u_k)|| / res0 <= rel_tol (K = 0 if res0 = 0).
+ *
+ * precision MS_SOLVE_F64: plain FP64 sweeps, max_sweeps caps K.
+ * precision MS_SOLVE_F32_REFINED: FP64 iterative refinement around FP32
+ *   sweeps. Outer: r = f - L(x) in FP64; stop if ||r||/res0 <= rel_tol;
+ *   s = 2^floor(log2(||r|| / sqrt(N))); rhat = fl32(r / s); inner FP32 Jacobi
+ *   on L(e) = rhat from e = 0 (zero halo) until its FP64 residual drops to
+ *   inner_eta times its start, or stalls (no decrease over stall_window
+ *   sweeps), or max_inner sweeps; then x += s * e in FP64. max_outer caps
+ *   the outer steps, max_sweeps the total inner sweeps.
+ * check_every: sweeps per device-side chunk between host checks (0 = auto).
+ * temporal_block: sweeps fused per pass (0/1 = none; 2 = two-sweep blocking,
+ *   FP64 only; the per-cell arithmetic is unchanged).
+ * use_graph: 1 = replay chunks as hipGraphs (default), 0 = plain launches.
+ *
+ * u: device, in: initial guess + Dirichlet halo; out: the answer u_K.
+ * f: device, may be NULL. hist_host: host, may be NULL; receives
+ * ||r(u_k)|| for k = 0..K (MS_SOLVE_F64, needs max_sweeps + 1 doubles) or
+ * ||r(x_o)|| / res0 per outer step o = 0..outer_iters (refined, needs
+ * max_outer + 1 doubles). Blocks until done.
+ * Returns MS_OK, MS_NOT_CONVERGED (result still filled), MS_ENONFINITE,
+ * or an error. */
+#define MS_SOLVE_F64 0
+#define MS_SOLVE_F32_REFINED 1
+
+typedef struct {
+  double rel_tol;
+  int64_t max_sweeps;
+  int32_t precision;
+  int32_t check_every;
+  double inner_eta;
+  int32_t max_outer;
+  int32_t max_inner;
+  int32_t stall_window;
+  int32_t temporal_block;
+  int32_t use_graph;
+  int32_t reserved;
+} ms_solve_opts;
+
+typedef struct {
+  int64_t sweeps;      /* K (F64) or the total inner sweeps (refined) */
+  int32_t outer_iters; /* refinement steps taken (0 for F64) */
+  int32_t status;      /* same as the return value */
+  double res0;         /* ||r(u^0)|| */
+  double res_final;    /* ||r(u_K)|| (FP64, recomputed for refined) */
+  double rel_final;    /* res_final / res0 */
+} ms_solve_result;
+
+/* Fill `o` with the library defaults (rel_tol 1e-8, F64, auto chunks). */
+void ms_solve_opts_default(ms_solve_opts* o);
+size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* o);
+int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
+                 const double* f, void* work, size_t work_bytes,
+                 double* hist_host, ms_solve_result* res, void* stream);
+
+/* ---- advection source term ------------------------------------------------
+ * The fused three-field Piacsek-Williams advection source term of Section
+ * 4.1 (three stencils over u, v, w fused into one pass, 63 flops per cell).
+ * The paper prints no formula; this library's definition on a staggered
+ * C-grid (u at i+1/2, v at j+1/2, w at k+1/2), for phi in (u, v, w):
+ *   s_phi = (tcx*(Px- - Px+) + tcy*(Py- - Py+)) + (tzc1[k]*Pz- - tzc2[k]*Pz+)
+ * where each P is phi at the neighbour on that side times the sum of the
+ * two samples of the advecting velocity straddling that face, e.g. for su:
+ *   Px- = u[i-1]*(u[i-1]+u[i])          Px+ = u[i+1]*(u[i]+u[i+1])
+ *   Py- = u[j-1]*(v[j-1]+v[i+1,j-1])    Py+ = u[j+1]*(v[j]+v[i+1,j])
+ *   Pz- = u[k-1]*(w[k-1]+w[i+1,k-1])    Pz+ = u[k+1]*(w[k]+w[i+1,k])
+ * (sv, sw likewise with the roles of the axes exchanged). FP64, evaluation
+ * order as written, no contraction.
+ * u, v, w: device fields on grid g with a valid halo (edges and corners
+ * included); tzc1, tzc2: device arrays of nz doubles; su, sv, sw: device
+ * outputs on grid g (interior written). Outputs may not alias inputs.
+ * Async. */
+int advect_source(const ms_grid* g, const double* u, const double* v,
+                  const double* w, const double* tzc1, const double* tzc2,
+                  double tcx, double tcy, double* su, double* sv, double* sw,
+                  void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MISTENCIL_H */

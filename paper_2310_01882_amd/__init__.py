@@ -1,0 +1,307 @@
+"""Python binding of libmistencil (MI355X stencil sweeps).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libmistencil.so. PyTorch supplies device memory and the current
+stream. Fields are 3D tensors of shape (nz + 2, ny + 2, nx + 2) with a unit
+x stride (row and plane pitch may be padded), base element = halo cell
+(-1, -1, -1).
+
+The names mirror the C ABI in include/mistencil.h: stencil_apply,
+residual_norm, jacobi_sweeps, jacobi_solve, advect_source.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # loads the HIP runtime the library binds to
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmistencil.so")
+
+MS_OK = 0
+MS_NOT_CONVERGED = 1
+MS_EINVAL = -1
+MS_EUNSUPPORTED = -2
+MS_EHIP = -3
+MS_EWORKSPACE = -4
+MS_ENONFINITE = -5
+
+MS_F64 = 0
+MS_F32 = 1
+MS_SOLVE_F64 = 0
+MS_SOLVE_F32_REFINED = 1
+
+
+class MsError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sy", ctypes.c_int64), ("sz", ctypes.c_int64)]
+
+
+class Tap(ctypes.Structure):
+    _fields_ = [("dx", ctypes.c_int8), ("dy", ctypes.c_int8), ("dz", ctypes.c_int8),
+                ("reserved", ctypes.c_int8 * 5), ("w", ctypes.c_double)]
+
+
+class Stencil(ctypes.Structure):
+    _fields_ = [("ntaps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("taps", ctypes.POINTER(Tap)), ("rhs_coef", ctypes.c_double),
+                ("scale", ctypes.c_double)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("rel_tol", ctypes.c_double), ("max_sweeps", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("inner_eta", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("max_inner", ctypes.c_int32), ("stall_window", ctypes.c_int32),
+                ("temporal_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("outer_iters", ctypes.c_int32),
+                ("status", ctypes.c_int32), ("res0", ctypes.c_double),
+                ("res_final", ctypes.c_double), ("rel_final", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_D = ctypes.c_double
+_I = ctypes.c_int
+_I64 = ctypes.c_int64
+_SZ = ctypes.c_size_t
+
+# name -> (restype, argtypes); every symbol include/mistencil.h declares.
+SIGNATURES = {
+    "ms_last_error": (ctypes.c_char_p, []),
+    "ms_version": (ctypes.c_char_p, []),
+    "stencil_apply": (_I, [ctypes.POINTER(Stencil), ctypes.POINTER(Grid), _I, _P, _P, _P, _P]),
+    "residual_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
+    "residual_norm": (_I, [ctypes.POINTER(Grid), _I, _P, _P, ctypes.POINTER(_D), _I, _P, _SZ, _P]),
+    "jacobi_sweeps_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
+    "jacobi_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "ms_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
+    "jacobi_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts)]),
+    "jacobi_solve": (_I, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts), _P, _P, _P, _SZ,
+                          ctypes.POINTER(_D), ctypes.POINTER(SolveResult), _P]),
+    "advect_source": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _D, _D, _P, _P, _P, _P]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it first (python -m paper_2310_01882_amd.build). "
+            "There is no fallback implementation.")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def last_error() -> str:
+    return (lib.ms_last_error() or b"").decode()
+
+
+def _check(rc: int, allow=(MS_OK,)):
+    if rc not in allow:
+        raise MsError(rc, last_error())
+    return rc
+
+
+# ------------------------------------------------------------------ helpers
+
+def _field_check(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dim() != 3:
+        raise ValueError(f"{name} must be 3D (nz+2, ny+2, nx+2)")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.stride(2) != 1:
+        raise ValueError(f"{name} must have unit x stride")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+def grid_of(t: torch.Tensor) -> Grid:
+    nz2, ny2, nx2 = t.shape
+    return Grid(nx2 - 2, ny2 - 2, nz2 - 2, 0, t.stride(1), t.stride(0))
+
+
+def _same_layout(a: torch.Tensor, b: torch.Tensor, names: str):
+    if a.shape != b.shape or a.stride() != b.stride():
+        raise ValueError(f"{names} must share shape and strides")
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return MS_F64
+    if t.dtype == torch.float32:
+        return MS_F32
+    raise TypeError("fields must be float64 or float32")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------- entry points
+
+def stencil_apply(taps, inp, out, rhs=None, rhs_coef=0.0, scale=1.0, stream=None):
+    """out[p] = scale * (sum_t w_t in[p + o_t] (in tap order) + rhs_coef * rhs[p]).
+
+    ``taps`` is a sequence of (dx, dy, dz, w)."""
+    _field_check(inp, "inp")
+    _field_check(out, "out", inp.dtype)
+    _same_layout(inp, out, "inp/out")
+    if rhs is not None:
+        _field_check(rhs, "rhs", inp.dtype)
+        _same_layout(inp, rhs, "inp/rhs")
+    arr = (Tap * max(len(taps), 1))()
+    for n, (dx, dy, dz, w) in enumerate(taps):
+        arr[n].dx, arr[n].dy, arr[n].dz, arr[n].w = int(dx), int(dy), int(dz), float(w)
+    st = Stencil(len(taps), 0, arr, float(rhs_coef), float(scale))
+    g = grid_of(inp)
+    _check(lib.stencil_apply(ctypes.byref(st), ctypes.byref(g), _dtype_code(inp), _ptr(inp),
+                             _ptr(rhs), _ptr(out), _stream(stream)))
+    return out
+
+
+def residual_norm(u, f=None, out=None, stream=None) -> float:
+    """||f - L(u)||_2 over the interior (FP64 accumulation). With ``out`` (a
+    1-element float64 device tensor) the result stays on the device."""
+    _field_check(u, "u")
+    if f is not None:
+        _field_check(f, "f", u.dtype)
+        _same_layout(u, f, "u/f")
+    g = grid_of(u)
+    ws = _workspace(lib.residual_workspace_bytes(ctypes.byref(g)), u.device)
+    if out is not None:
+        _check(lib.residual_norm(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(f),
+                                 ctypes.cast(ctypes.c_void_p(out.data_ptr()), ctypes.POINTER(_D)),
+                                 1, _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+    val = ctypes.c_double(0.0)
+    _check(lib.residual_norm(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(f),
+                             ctypes.byref(val), 0, _ptr(ws), ws.numel(), _stream(stream)))
+    return val.value
+
+
+def jacobi_sweeps_workspace(u) -> torch.Tensor:
+    g = grid_of(u)
+    return _workspace(lib.jacobi_sweeps_workspace_bytes(ctypes.byref(g)), u.device)
+
+
+def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):
+    """Exactly ``n`` Jacobi sweeps with ping-pong buffers; u_n ends in ``u``
+    if n is even, else in ``u_tmp`` (returned). ``res`` (float64 device
+    tensor of n + 1 entries, optional) receives ||r(u_k)||, k = 0..n."""
+    _field_check(u, "u")
+    _field_check(u_tmp, "u_tmp", u.dtype)
+    _same_layout(u, u_tmp, "u/u_tmp")
+    if f is not None:
+        _field_check(f, "f", u.dtype)
+        _same_layout(u, f, "u/f")
+    if res is not None and (res.dtype != torch.float64 or res.numel() < n + 1):
+        raise ValueError("res must be float64 with n + 1 entries")
+    g = grid_of(u)
+    if work is None:
+        work = jacobi_sweeps_workspace(u)
+    _check(lib.jacobi_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f),
+                             int(n), _ptr(res), _ptr(work), work.numel(), _stream(stream)))
+    return u if n % 2 == 0 else u_tmp
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    sweeps: int
+    outer_iters: int
+    res0: float
+    res_final: float
+    rel_final: float
+    hist: list
+
+
+def solve_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    lib.ms_solve_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown solve option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def jacobi_workspace(u, opts: SolveOpts) -> torch.Tensor:
+    g = grid_of(u)
+    n = lib.jacobi_workspace_bytes(ctypes.byref(g), ctypes.byref(opts))
+    if n == 0:
+        raise MsError(MS_EINVAL, last_error())
+    return _workspace(n, u.device)
+
+
+def jacobi_solve(u, f=None, work=None, want_hist=False, stream=None, **opts) -> SolveInfo:
+    """Convergence-controlled solve of L(u) = f; ``u`` (float64) holds the
+    initial guess and Dirichlet halo on entry and the answer on return.
+    Keyword options map onto ms_solve_opts (rel_tol, max_sweeps, precision,
+    check_every, inner_eta, max_outer, max_inner, stall_window,
+    temporal_block, use_graph)."""
+    _field_check(u, "u", torch.float64)
+    if f is not None:
+        _field_check(f, "f", torch.float64)
+        _same_layout(u, f, "u/f")
+    o = solve_opts(**opts)
+    g = grid_of(u)
+    if work is None:
+        work = jacobi_workspace(u, o)
+    hist = None
+    if want_hist:
+        n = (o.max_sweeps + 1) if o.precision == MS_SOLVE_F64 else (o.max_outer + 1)
+        hist = (ctypes.c_double * int(n))()
+    r = SolveResult()
+    rc = lib.jacobi_solve(ctypes.byref(g), ctypes.byref(o), _ptr(u), _ptr(f), _ptr(work),
+                          work.numel(), hist, ctypes.byref(r), _stream(stream))
+    _check(rc, allow=(MS_OK, MS_NOT_CONVERGED))
+    h = []
+    if want_hist:
+        cnt = (r.sweeps + 1) if o.precision == MS_SOLVE_F64 else (r.outer_iters + 1)
+        h = list(hist[:cnt])
+    return SolveInfo(rc, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, h)
+
+
+def advect_source(u, v, w, tzc1, tzc2, tcx, tcy, su, sv, sw, stream=None):
+    """Fused three-field advection source term (FP64); outputs su, sv, sw."""
+    for name, t in (("u", u), ("v", v), ("w", w), ("su", su), ("sv", sv), ("sw", sw)):
+        _field_check(t, name, torch.float64)
+        _same_layout(u, t, f"u/{name}")
+    nz = u.shape[0] - 2
+    for name, t in (("tzc1", tzc1), ("tzc2", tzc2)):
+        if t.dtype != torch.float64 or t.numel() != nz or not t.is_contiguous() or t.device.type != "cuda":
+            raise ValueError(f"{name} must be a contiguous float64 device vector of length nz")
+    g = grid_of(u)
+    _check(lib.advect_source(ctypes.byref(g), _ptr(u), _ptr(v), _ptr(w), _ptr(tzc1), _ptr(tzc2),
+                             float(tcx), float(tcy), _ptr(su), _ptr(sv), _ptr(sw), _stream(stream)))
+    return su, sv, sw

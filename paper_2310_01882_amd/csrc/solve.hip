@@ -1,0 +1,505 @@
+// Entry points of the Jacobi hot path: fixed sweeps, the residual norm and
+// the convergence-controlled solve (plain FP64, and FP32 storage with FP64
+// iterative refinement).
+//
+// Convergence control runs on the device. Sweep launch k evaluates the norm
+// of iterate k-1 and sets a done flag in a control block; later launches
+// read the flag first and return at once. The host replays a chunk of m
+// launches (as a hipGraph) and looks at the flag once per chunk. Because
+// the decision about u_{k-1} is taken while launch k already writes
+// u_{k+1}, the solve keeps three buffers (the answer is never the buffer
+// being written).
+#include "ms_internal.hpp"
+
+#include <cmath>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+namespace ms {
+namespace {
+
+__global__ void ctl_init_kernel(Ctl* c, double tol, int64_t max_sweeps, int ref_from_first,
+                                int stall, int keep_res0) {
+  c->base = 0;
+  c->K = -1;
+  c->max_sweeps = max_sweeps;
+  c->tol = tol;
+  if (!keep_res0) c->res0 = 0.0;
+  c->last = 0.0;
+  c->done = RUNNING;
+  c->ref_from_first = ref_from_first;
+  c->stall = stall;
+  c->pad = 0;
+}
+
+__global__ void ctl_advance_kernel(Ctl* c, int64_t m) { c->base += m; }
+
+// rhat = fl32((f - L(x)) / s) on the interior (s a power of two, applied as
+// a multiplication by its exact reciprocal); also zeroes e0's interior.
+template <bool HAS_F>
+__global__ __launch_bounds__(256) void refine_rhs_kernel(const double* __restrict__ x,
+                                                         const double* __restrict__ f,
+                                                         float* __restrict__ rhat,
+                                                         float* __restrict__ e0, double inv_s,
+                                                         int nx, int ny, int nz, int64_t sy,
+                                                         int64_t sz, int64_t sy32,
+                                                         int64_t sz32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i >= nx) return;
+  const int64_t p = (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
+  const double s = ((((x[p + 1] + x[p - 1]) + x[p + sy]) + x[p - sy]) + x[p + sz]) + x[p - sz];
+  const double lap = s - x[p] * 6.0;
+  const double r = HAS_F ? f[p] - lap : -lap;
+  const int64_t q = (int64_t)(k + 1) * sz32 + (int64_t)(j + 1) * sy32 + (i + 1);
+  rhat[q] = (float)(r * inv_s);
+  e0[q] = 0.0f;
+}
+
+// x += s * e on the interior, e taken from the inner buffer holding the
+// accepted iterate (index K read from the inner control block).
+__global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__ x,
+                                                            float* e0, float* e1, float* e2,
+                                                            const Ctl* __restrict__ c,
+                                                            double s, int nx, int64_t sy,
+                                                            int64_t sz, int64_t sy32,
+                                                            int64_t sz32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i >= nx) return;
+  const int64_t kk = c->K;
+  const float* e = (kk % 3 == 0) ? e0 : (kk % 3 == 1) ? e1 : e2;
+  const int64_t p = (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
+  const int64_t q = (int64_t)(k + 1) * sz32 + (int64_t)(j + 1) * sy32 + (i + 1);
+  x[p] = x[p] + s * (double)e[q];
+}
+
+__global__ void fill_f32_kernel(float* p, int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    p[t] = 0.0f;
+}
+
+int elem_size(int dtype) { return dtype == MS_F64 ? 8 : 4; }
+
+bool is_finite_host(double v) { return std::isfinite(v); }
+
+// s = 2^e with s <= norm / sqrt(N) < 2s (1 if that ratio is 0 or not finite).
+double pow2_scale(double norm, double ncells) {
+  const double m = norm / std::sqrt(ncells);
+  if (m == 0.0 || !std::isfinite(m)) return 1.0;
+  int e = 0;
+  std::frexp(m, &e);
+  return std::ldexp(1.0, e - 1);
+}
+
+// Replays chunks of m sweep launches until the control block reports done.
+struct ChunkRunner {
+  const ms_grid& g;
+  int dtype;
+  void* bufs[3];
+  const void* f;
+  double* partials;
+  double* hist;
+  Ctl* ctl;
+  SweepGeom geo;
+  int m;
+  bool use_graph;
+  hipStream_t s;
+
+  int enqueue_chunk() {
+    for (int i = 0; i < m; ++i) {
+      int rc = launch_sweep(g, dtype, bufs, 3, f, partials, hist, ctl, i, geo, s);
+      if (rc) return rc;
+    }
+    hipLaunchKernelGGL(ctl_advance_kernel, dim3(1), dim3(1), 0, s, ctl, (int64_t)m);
+    MS_LAUNCH_CHECK();
+    return MS_OK;
+  }
+
+  int run(Ctl* host_ctl) {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    if (use_graph) {
+      MS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      int rc = MS_OK;
+      if (e == hipSuccess) {
+        hipStream_t keep = s;
+        s = cap;
+        rc = enqueue_chunk();
+        s = keep;
+        e = hipStreamEndCapture(cap, &graph);
+      }
+      if (e == hipSuccess && rc == MS_OK) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipStreamDestroy(cap);
+      if (rc) return rc;
+      if (e != hipSuccess)
+        return set_error(MS_EHIP, "graph capture of the sweep chunk failed: %s",
+                         hipGetErrorString(e));
+    }
+    int rc = MS_OK;
+    // Every launch advances the sweep index, so the control block must report
+    // completion within max_sweeps + 2 launches; anything longer means the
+    // sweeps did not run.
+    int64_t launched = 0;
+    for (;;) {
+      if (launched > host_ctl->max_sweeps + 2 * (int64_t)m + 2) {
+        rc = set_error(MS_EHIP, "sweep chunks ran without the control block completing");
+        break;
+      }
+      launched += m;
+      if (exec) {
+        hipError_t e = hipGraphLaunch(exec, s);
+        if (e != hipSuccess) {
+          rc = set_error(MS_EHIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+          break;
+        }
+      } else {
+        rc = enqueue_chunk();
+        if (rc) break;
+      }
+      hipError_t e = hipMemcpyAsync(host_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) {
+        rc = set_error(MS_EHIP, "control read-back: %s", hipGetErrorString(e));
+        break;
+      }
+      if (host_ctl->done != RUNNING) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    return rc;
+  }
+};
+
+int auto_chunk(const ms_grid& g, int requested) {
+  if (requested > 0) return requested;
+  const double cells = (double)g.nx * g.ny * g.nz;
+  return cells >= 16.0e6 ? 64 : 256;
+}
+
+struct SolveLayout {
+  size_t f64_field, f32_field, partials, hist_f64, hist_inner, total;
+};
+
+SolveLayout solve_layout(const ms_grid& g, const ms_solve_opts& o) {
+  SolveLayout L{};
+  const SweepGeom geo = sweep_geom(g, 0);
+  const size_t span = (size_t)field_span(g);
+  L.partials = align_up(2 * (size_t)geo.nblocks * sizeof(double), 256);
+  size_t t = align_up(sizeof(Ctl), 256) + L.partials;
+  if (o.precision == MS_SOLVE_F64) {
+    L.f64_field = align_up(span * 8, 256);
+    L.hist_f64 = align_up(((size_t)o.max_sweeps + 2) * sizeof(double), 256);
+    t += 2 * L.f64_field + L.hist_f64;
+  } else {
+    L.f32_field = align_up(span * 4, 256);
+    L.hist_inner = align_up(((size_t)o.max_inner + 2) * sizeof(double), 256);
+    t += 4 * L.f32_field + L.hist_inner + align_up(sizeof(Ctl), 256);
+  }
+  L.total = t;
+  return L;
+}
+
+int check_opts(const ms_solve_opts* o) {
+  if (!o) return set_error(MS_EINVAL, "jacobi_solve: opts is NULL");
+  if (o->precision != MS_SOLVE_F64 && o->precision != MS_SOLVE_F32_REFINED)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: unknown precision %d", o->precision);
+  if (!(o->rel_tol >= 0.0) || !std::isfinite(o->rel_tol))
+    return set_error(MS_EINVAL, "jacobi_solve: rel_tol must be finite and >= 0");
+  if (o->max_sweeps < 0) return set_error(MS_EINVAL, "jacobi_solve: max_sweeps < 0");
+  if (o->check_every < 0) return set_error(MS_EINVAL, "jacobi_solve: check_every < 0");
+  if (o->temporal_block < 0 || o->temporal_block > 2)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: temporal_block %d", o->temporal_block);
+  if (o->precision == MS_SOLVE_F32_REFINED) {
+    if (!(o->inner_eta > 0.0 && o->inner_eta < 1.0))
+      return set_error(MS_EINVAL, "jacobi_solve: inner_eta must be in (0, 1)");
+    if (o->max_outer < 0 || o->max_inner < 1 || o->stall_window < 0)
+      return set_error(MS_EINVAL, "jacobi_solve: bad refinement caps");
+  }
+  return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+// ------------------------------------------------------------ residual_norm
+
+extern "C" size_t residual_workspace_bytes(const ms_grid* g) {
+  if (check_grid(g, "residual_workspace_bytes")) return 0;
+  const SweepGeom geo = sweep_geom(*g, 0);
+  return align_up((size_t)geo.nblocks * sizeof(double), 256) + align_up(sizeof(double), 256);
+}
+
+extern "C" int residual_norm(const ms_grid* g, int dtype, const void* u, const void* f,
+                             double* norm_out, int out_on_device, void* work,
+                             size_t work_bytes, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "residual_norm")) return rc;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "residual_norm: dtype %d", dtype);
+  if (!u || !norm_out) return set_error(MS_EINVAL, "residual_norm: u and norm_out required");
+  const size_t need = residual_workspace_bytes(g);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "residual_norm: workspace needs %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const SweepGeom geo = sweep_geom(*g, 0);
+  Workspace ws{static_cast<char*>(work), work_bytes};
+  double* partials = ws.take<double>(geo.nblocks);
+  double* dnorm = ws.take<double>(1);
+  if (int rc = launch_residual(*g, dtype, u, f, false, partials, 0, geo, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, geo.nblocks, out_on_device ? norm_out : dnorm,
+                               nullptr, nullptr, 0, s))
+    return rc;
+  if (!out_on_device) {
+    MS_HIP_TRY(hipMemcpyAsync(norm_out, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
+    MS_HIP_TRY(hipStreamSynchronize(s));
+  }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------ jacobi_sweeps
+
+extern "C" size_t jacobi_sweeps_workspace_bytes(const ms_grid* g) {
+  if (check_grid(g, "jacobi_sweeps_workspace_bytes")) return 0;
+  const SweepGeom geo = sweep_geom(*g, 0);
+  return align_up(2 * (size_t)geo.nblocks * sizeof(double), 256);
+}
+
+extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
+                             int64_t n, double* res_dev, void* work, size_t work_bytes,
+                             void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "jacobi_sweeps")) return rc;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "jacobi_sweeps: dtype %d", dtype);
+  if (!u || !u_tmp) return set_error(MS_EINVAL, "jacobi_sweeps: u and u_tmp required");
+  if (n < 0) return set_error(MS_EINVAL, "jacobi_sweeps: n < 0");
+  const size_t bytes = (size_t)field_span(*g) * elem_size(dtype);
+  if (overlaps(u, bytes, u_tmp, bytes))
+    return set_error(MS_EINVAL, "jacobi_sweeps: u and u_tmp overlap");
+  if (f && (overlaps(f, bytes, u, bytes) || overlaps(f, bytes, u_tmp, bytes)))
+    return set_error(MS_EINVAL, "jacobi_sweeps: f overlaps a sweep buffer");
+  const size_t need = jacobi_sweeps_workspace_bytes(g);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "jacobi_sweeps: workspace needs %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const SweepGeom geo = sweep_geom(*g, 0);
+  double* partials = static_cast<double*>(work);
+  void* bufs[3] = {u, u_tmp, u};
+  for (int64_t k = 0; k < n; ++k)
+    if (int rc = launch_sweep(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, k, geo, s))
+      return rc;
+  if (res_dev) {
+    if (n >= 1)
+      if (int rc = launch_finalize(partials, (int)((n - 1) & 1), geo.nblocks, nullptr, nullptr,
+                                   res_dev, n - 1, s))
+        return rc;
+    const int slot = (int)(n & 1);
+    if (int rc = launch_residual(*g, dtype, (n & 1) ? u_tmp : u, f, false, partials, slot, geo, s))
+      return rc;
+    if (int rc = launch_finalize(partials, slot, geo.nblocks, nullptr, nullptr, res_dev, n, s))
+      return rc;
+  }
+  return MS_OK;
+}
+
+// ------------------------------------------------------------- jacobi_solve
+
+extern "C" void ms_solve_opts_default(ms_solve_opts* o) {
+  if (!o) return;
+  o->rel_tol = 1e-8;
+  o->max_sweeps = 10000000;
+  o->precision = MS_SOLVE_F64;
+  o->check_every = 0;
+  o->inner_eta = 1e-4;
+  o->max_outer = 20;
+  o->max_inner = 5000000;
+  o->stall_window = 256;
+  o->temporal_block = 0;
+  o->use_graph = 1;
+  o->reserved = 0;
+}
+
+extern "C" size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* o) {
+  if (check_grid(g, "jacobi_workspace_bytes") || check_opts(o)) return 0;
+  return solve_layout(*g, *o).total;
+}
+
+namespace ms {
+namespace {
+
+int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double* f,
+              Workspace& ws, const SolveLayout& L, double* hist_host, ms_solve_result* res,
+              hipStream_t s) {
+  const SweepGeom geo = sweep_geom(g, 0);
+  const size_t span = (size_t)field_span(g);
+  Ctl* ctl = ws.take<Ctl>(1);
+  double* partials = ws.take<double>(2 * (size_t)geo.nblocks);
+  double* b1 = ws.take<double>(span);
+  double* b2 = ws.take<double>(span);
+  double* hist = ws.take<double>((size_t)o.max_sweeps + 2);
+  if (!ctl || !partials || !b1 || !b2 || !hist)
+    return set_error(MS_EWORKSPACE, "jacobi_solve: workspace carve failed");
+  // Every buffer carries the Dirichlet halo; sweeps never write it.
+  MS_HIP_TRY(hipMemcpyAsync(b1, u, span * 8, hipMemcpyDeviceToDevice, s));
+  MS_HIP_TRY(hipMemcpyAsync(b2, u, span * 8, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, o.rel_tol, o.max_sweeps, 0,
+                     0, 0);
+  MS_LAUNCH_CHECK();
+  // res0 = ||r(u^0)||, u^0 = u with its interior zeroed.
+  if (int rc = launch_residual(g, MS_F64, u, f, true, partials, 0, geo, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, geo.nblocks, &ctl->res0, nullptr, nullptr, 0, s))
+    return rc;
+
+  Ctl hc{};
+  hc.max_sweeps = o.max_sweeps;
+  ChunkRunner run{g, MS_F64, {u, b1, b2}, f, partials, hist, ctl, geo,
+                  auto_chunk(g, o.check_every), o.use_graph != 0, s};
+  if (int rc = run.run(&hc)) return rc;
+  const int64_t K = hc.K;
+  if (K % 3 != 0)
+    MS_HIP_TRY(hipMemcpyAsync(u, K % 3 == 1 ? b1 : b2, span * 8, hipMemcpyDeviceToDevice, s));
+  double res_final = 0.0;
+  MS_HIP_TRY(hipMemcpyAsync(&res_final, hist + K, sizeof(double), hipMemcpyDeviceToHost, s));
+  if (hist_host)
+    MS_HIP_TRY(hipMemcpyAsync(hist_host, hist, (size_t)(K + 1) * sizeof(double),
+                              hipMemcpyDeviceToHost, s));
+  MS_HIP_TRY(hipStreamSynchronize(s));
+  res->sweeps = K;
+  res->outer_iters = 0;
+  res->res0 = hc.res0;
+  res->res_final = res_final;
+  res->rel_final = hc.res0 > 0.0 ? res_final / hc.res0 : 0.0;
+  int status = MS_OK;
+  if (hc.done == NONFINITE)
+    status = set_error(MS_ENONFINITE, "jacobi_solve: residual norm is not finite at sweep %lld",
+                       (long long)K);
+  else if (hc.done != CONVERGED)
+    status = set_error(MS_NOT_CONVERGED, "jacobi_solve: not converged after %lld sweeps",
+                       (long long)K);
+  res->status = status;
+  return status;
+}
+
+int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const double* f,
+                  Workspace& ws, const SolveLayout& L, double* hist_host, ms_solve_result* res,
+                  hipStream_t s) {
+  const SweepGeom geo = sweep_geom(g, 0);
+  const size_t span = (size_t)field_span(g);
+  Ctl* ctl = ws.take<Ctl>(1);
+  double* partials = ws.take<double>(2 * (size_t)geo.nblocks);
+  float* rhat = ws.take<float>(span);
+  float* e[3] = {ws.take<float>(span), ws.take<float>(span), ws.take<float>(span)};
+  double* hist = ws.take<double>((size_t)o.max_inner + 2);
+  Ctl* octl = ws.take<Ctl>(1);
+  if (!ctl || !partials || !rhat || !e[0] || !e[1] || !e[2] || !hist || !octl)
+    return set_error(MS_EWORKSPACE, "jacobi_solve: workspace carve failed");
+  // FP32 grids share the FP64 grid's element strides, so their halos (zero:
+  // the correction has homogeneous boundary values) line up cell for cell.
+  for (float* p : {rhat, e[0], e[1], e[2]}) {
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(1024), dim3(256), 0, s, p, (int64_t)span);
+    MS_LAUNCH_CHECK();
+  }
+  hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, octl, 0.0, (int64_t)0, 0, 0, 0);
+  MS_LAUNCH_CHECK();
+  if (int rc = launch_residual(g, MS_F64, x, f, true, partials, 0, geo, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, geo.nblocks, &octl->res0, nullptr, nullptr, 0, s))
+    return rc;
+  double res0 = 0.0;
+  MS_HIP_TRY(hipMemcpyAsync(&res0, &octl->res0, sizeof(double), hipMemcpyDeviceToHost, s));
+  MS_HIP_TRY(hipStreamSynchronize(s));
+
+  const double ncells = (double)g.nx * g.ny * g.nz;
+  if (g.ny > 65535 || g.nz > 65535)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: refined path needs ny, nz <= 65535");
+  const dim3 eb(256), eg((g.nx + 255) / 256, g.ny, g.nz);
+  int64_t total = 0;
+  int outer = 0;
+  int status = MS_OK;
+  double nr = 0.0, rel = 0.0;
+  for (;;) {
+    if (int rc = launch_residual(g, MS_F64, x, f, false, partials, 0, geo, s)) return rc;
+    if (int rc = launch_finalize(partials, 0, geo.nblocks, &octl->last, nullptr, nullptr, 0, s))
+      return rc;
+    MS_HIP_TRY(hipMemcpyAsync(&nr, &octl->last, sizeof(double), hipMemcpyDeviceToHost, s));
+    MS_HIP_TRY(hipStreamSynchronize(s));
+    rel = res0 > 0.0 ? nr / res0 : 0.0;
+    if (hist_host) hist_host[outer] = rel;
+    if (!is_finite_host(nr)) {
+      status = set_error(MS_ENONFINITE, "jacobi_solve: residual norm not finite (outer %d)", outer);
+      break;
+    }
+    if (res0 == 0.0 || rel <= o.rel_tol) break;
+    if (outer == o.max_outer || total >= o.max_sweeps) {
+      status = set_error(MS_NOT_CONVERGED, "jacobi_solve: refinement stopped at rel %.3e", rel);
+      break;
+    }
+    const double sc = pow2_scale(nr, ncells);
+    if (f)
+      hipLaunchKernelGGL(refine_rhs_kernel<true>, eg, eb, 0, s, x, f, rhat, e[0], 1.0 / sc,
+                         g.nx, g.ny, g.nz, g.sy, g.sz, g.sy, g.sz);
+    else
+      hipLaunchKernelGGL(refine_rhs_kernel<false>, eg, eb, 0, s, x, f, rhat, e[0], 1.0 / sc,
+                         g.nx, g.ny, g.nz, g.sy, g.sz, g.sy, g.sz);
+    MS_LAUNCH_CHECK();
+    int64_t cap = o.max_inner;
+    if (o.max_sweeps - total < cap) cap = o.max_sweeps - total;
+    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, o.inner_eta, cap, 1,
+                       o.stall_window, 0);
+    MS_LAUNCH_CHECK();
+    Ctl hc{};
+    hc.max_sweeps = cap;
+    ChunkRunner run{g, MS_F32, {e[0], e[1], e[2]}, rhat, partials, hist, ctl, geo,
+                    auto_chunk(g, o.check_every), o.use_graph != 0, s};
+    if (int rc = run.run(&hc)) return rc;
+    if (hc.done == NONFINITE) {
+      status = set_error(MS_ENONFINITE, "jacobi_solve: inner residual not finite");
+      break;
+    }
+    hipLaunchKernelGGL(refine_update_kernel, eg, eb, 0, s, x, e[0], e[1], e[2], ctl, sc, g.nx,
+                       g.sy, g.sz, g.sy, g.sz);
+    MS_LAUNCH_CHECK();
+    total += hc.K;
+    ++outer;
+  }
+  MS_HIP_TRY(hipStreamSynchronize(s));
+  res->sweeps = total;
+  res->outer_iters = outer;
+  res->res0 = res0;
+  res->res_final = nr;
+  res->rel_final = rel;
+  res->status = status;
+  return status;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u, const double* f,
+                            void* work, size_t work_bytes, double* hist_host,
+                            ms_solve_result* res, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "jacobi_solve")) return rc;
+  if (int rc = check_opts(o)) return rc;
+  if (!u || !res) return set_error(MS_EINVAL, "jacobi_solve: u and res required");
+  const size_t bytes = (size_t)field_span(*g) * 8;
+  if (f && overlaps(f, bytes, u, bytes))
+    return set_error(MS_EINVAL, "jacobi_solve: f overlaps u");
+  const SolveLayout L = solve_layout(*g, *o);
+  if (!work || work_bytes < L.total)
+    return set_error(MS_EWORKSPACE, "jacobi_solve: workspace needs %zu bytes", L.total);
+  if (overlaps(work, L.total, u, bytes) || (f && overlaps(work, L.total, f, bytes)))
+    return set_error(MS_EINVAL, "jacobi_solve: workspace overlaps a field");
+  Workspace ws{static_cast<char*>(work), work_bytes};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o->precision == MS_SOLVE_F64) return solve_f64(*g, *o, u, f, ws, L, hist_host, res, s);
+  return solve_refined(*g, *o, u, f, ws, L, hist_host, res, s);
+}

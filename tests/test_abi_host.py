@@ -1,0 +1,138 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mistencil.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]*?\b(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("defined",)))
+
+
+def test_header_declares_the_four_named_entry_points():
+    names = declared_functions()
+    for n in ("stencil_apply", "jacobi_solve", "advect_source", "residual_norm"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2310_01882_amd as ms
+    raw = ctypes.CDLL(ms.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(raw, n)]
+    assert not missing, missing
+    # the binding covers the same set
+    assert set(declared_functions()) <= set(ms.SIGNATURES)
+
+
+def test_version_and_error_strings():
+    import paper_2310_01882_amd as ms
+    assert b"gfx950" in ms.lib.ms_version()
+    assert isinstance(ms.last_error(), str)
+
+
+def _grid(ms, nx=8, ny=6, nz=4, sy=None, sz=None):
+    sy = sy if sy is not None else nx + 2
+    sz = sz if sz is not None else sy * (ny + 2)
+    return ms.Grid(nx, ny, nz, 0, sy, sz)
+
+
+FAKE = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+FAKE2 = ctypes.c_void_p(0x10000000)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(ny=-1), dict(sy=9), dict(sz=50)])
+def test_bad_grids_are_rejected(bad):
+    import paper_2310_01882_amd as ms
+    kw = dict(nx=8, ny=6, nz=4)
+    kw.update(bad)
+    g = _grid(ms, **kw)
+    rc = ms.lib.jacobi_sweeps(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, 1, None, FAKE,
+                              1 << 20, None)
+    assert rc == ms.MS_EINVAL
+    assert ms.last_error()
+    assert ms.lib.residual_workspace_bytes(ctypes.byref(g)) == 0
+
+
+def test_null_and_aliased_buffers_are_rejected():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    assert ms.lib.jacobi_sweeps(ctypes.byref(g), ms.MS_F64, None, FAKE2, None, 1, None, FAKE,
+                                1 << 20, None) == ms.MS_EINVAL
+    # u and u_tmp overlap
+    assert ms.lib.jacobi_sweeps(ctypes.byref(g), ms.MS_F64, FAKE, ctypes.c_void_p(0x1008), None,
+                                1, None, FAKE, 1 << 20, None) == ms.MS_EINVAL
+    assert "overlap" in ms.last_error()
+
+
+def test_workspace_too_small_is_reported():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    need = ms.lib.jacobi_sweeps_workspace_bytes(ctypes.byref(g))
+    assert need > 0
+    rc = ms.lib.jacobi_sweeps(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, 1, None, FAKE,
+                              need - 1, None)
+    assert rc == ms.MS_EWORKSPACE
+
+
+def test_bad_dtype_is_unsupported():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    out = ctypes.c_double()
+    rc = ms.lib.residual_norm(ctypes.byref(g), 7, FAKE, None, ctypes.byref(out), 0, FAKE,
+                              1 << 20, None)
+    assert rc == ms.MS_EUNSUPPORTED
+
+
+def test_stencil_apply_validation():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    taps = (ms.Tap * 2)()
+    taps[0].dx, taps[0].w = 1, 1.0
+    taps[1].dz, taps[1].w = 2, 1.0  # beyond the one-cell halo
+    st = ms.Stencil(2, 0, taps, 0.0, 1.0)
+    assert ms.lib.stencil_apply(ctypes.byref(st), ctypes.byref(g), ms.MS_F64, FAKE, None, FAKE2,
+                                None) == ms.MS_EINVAL
+    st = ms.Stencil(0, 0, taps, 0.0, 1.0)
+    assert ms.lib.stencil_apply(ctypes.byref(st), ctypes.byref(g), ms.MS_F64, FAKE, None, FAKE2,
+                                None) == ms.MS_EUNSUPPORTED
+    taps[1].dz = 1
+    st = ms.Stencil(2, 0, taps, 0.0, 1.0)
+    # in-place apply is not allowed (stencil.apply is out-of-place)
+    assert ms.lib.stencil_apply(ctypes.byref(st), ctypes.byref(g), ms.MS_F64, FAKE, None, FAKE,
+                                None) == ms.MS_EINVAL
+
+
+def test_solve_options_are_validated():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    o = ms.solve_opts(precision=5)
+    assert ms.lib.jacobi_workspace_bytes(ctypes.byref(g), ctypes.byref(o)) == 0
+    o = ms.solve_opts(precision=ms.MS_SOLVE_F32_REFINED, inner_eta=2.0)
+    r = ms.SolveResult()
+    rc = ms.lib.jacobi_solve(ctypes.byref(g), ctypes.byref(o), FAKE, None, FAKE2, 1 << 30, None,
+                             ctypes.byref(r), None)
+    assert rc == ms.MS_EINVAL
+    o = ms.solve_opts()
+    need = ms.lib.jacobi_workspace_bytes(ctypes.byref(g), ctypes.byref(o))
+    assert need > 2 * (10 * 8 * 6 * 8)  # two extra FP64 buffers at least
+    rc = ms.lib.jacobi_solve(ctypes.byref(g), ctypes.byref(o), FAKE, None, FAKE2, need - 1,
+                             None, ctypes.byref(r), None)
+    assert rc == ms.MS_EWORKSPACE
+
+
+def test_advect_rejects_aliasing_outputs():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    p = [ctypes.c_void_p(0x100000 * (n + 1)) for n in range(8)]
+    rc = ms.lib.advect_source(ctypes.byref(g), p[0], p[1], p[2], p[3], p[4], 0.25, 0.25, p[0],
+                              p[5], p[6], None)
+    assert rc == ms.MS_EINVAL

@@ -1,0 +1,117 @@
+"""GPU parity of the advection source term and the general stencil apply."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpuhelp import dev, empty_like_layout, host, note
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_01882_amd as ms  # noqa: E402
+
+
+def _advect_gpu(u, v, w, t1, t2, tcx, tcy, pad=(0, 0)):
+    du, dv, dw = dev(u, *pad), dev(v, *pad), dev(w, *pad)
+    outs = [empty_like_layout(du) for _ in range(3)]
+    ms.advect_source(du, dv, dw, torch.from_numpy(t1).cuda(), torch.from_numpy(t2).cuda(), tcx,
+                     tcy, *outs)
+    torch.cuda.synchronize()
+    return [host(o) for o in outs]
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (5, 4, 3), (64, 16, 8), (67, 19, 13), (130, 70, 9)])
+def test_advection_bit_exact(dims):
+    note(f"case: advect {dims}")
+    nx, ny, nz = dims
+    u, v, w = synth.velocity_fields(nx, ny, nz, 2)
+    t1, t2 = synth.tzc_arrays(nz, 3)
+    got = _advect_gpu(u, v, w, t1, t2, 0.25, 0.25)
+    want = oracle.advect_source(u, v, w, t1, t2, 0.25, 0.25)
+    for g, wnt in zip(got, want):
+        assert np.array_equal(g[1:-1, 1:-1, 1:-1], wnt)
+        # halo of the outputs is untouched (still NaN)
+        assert np.isnan(g[0]).all() and np.isnan(g[:, 0]).all() and np.isnan(g[:, :, -1]).all()
+
+
+def test_advection_padded_pitch():
+    nx, ny, nz = 40, 12, 6
+    u, v, w = synth.velocity_fields(nx, ny, nz, 4)
+    t1, t2 = synth.tzc_arrays(nz, 5)
+    got = _advect_gpu(u, v, w, t1, t2, 0.3, 0.2, pad=(6, 2))
+    want = oracle.advect_source(u, v, w, t1, t2, 0.3, 0.2)
+    for g, wnt in zip(got, want):
+        assert np.array_equal(g[1:-1, 1:-1, 1:-1], wnt)
+
+
+def test_advection_full_size_sampled_slabs():
+    """512 x 512 x 256 interior (16-sinusoid fields, seed 2; tzc ~ U[0.5, 2],
+    seed 3; tcx = tcy = 0.25), the benchmark's launch configuration; the
+    oracle recomputes three z-slabs (bottom, middle, top) from the same
+    inputs and every output there must match bit for bit."""
+    note("case: advect 512x512x256 sampled slabs")
+    nx, ny, nz = 512, 512, 256
+    u, v, w = synth.velocity_fields(nx, ny, nz, 2)
+    t1, t2 = synth.tzc_arrays(nz, 3)
+    got = _advect_gpu(u, v, w, t1, t2, 0.25, 0.25)
+    for k0 in (0, 121, nz - 6):  # interior levels k0 .. k0+5
+        sl = slice(k0, k0 + 8)  # planes k0-1 .. k0+6 of the halo-padded arrays
+        want = oracle.advect_source(u[sl], v[sl], w[sl], t1[k0:k0 + 6], t2[k0:k0 + 6], 0.25, 0.25)
+        for g, wnt in zip(got, want):
+            assert np.array_equal(g[k0 + 1:k0 + 7, 1:-1, 1:-1], wnt)
+
+
+def test_advection_degree_two_homogeneity_on_gpu():
+    u, v, w = synth.velocity_fields(48, 40, 24, 6)
+    t1, t2 = synth.tzc_arrays(24, 7)
+    a = _advect_gpu(u, v, w, t1, t2, 0.25, 0.25)
+    b = _advect_gpu(2 * u, 2 * v, 2 * w, t1, t2, 0.25, 0.25)
+    for x, y in zip(a, b):
+        assert np.array_equal(4 * x[1:-1, 1:-1, 1:-1], y[1:-1, 1:-1, 1:-1])
+
+
+LISTING1 = [(0, -1, 0, 1.0), (0, 1, 0, 1.0), (-1, 0, 0, 1.0), (1, 0, 0, 1.0)]
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_stencil_apply_listing1_and_general_taps(dtype):
+    # Listing 1's 2D average on its 256 x 256 array (nz = 1)
+    data = np.zeros((3, 256, 256))
+    data[1] = synth.rng(7).random((256, 256))
+    data = data.astype(dtype)
+    din = dev(data)
+    out = empty_like_layout(din)
+    ms.stencil_apply(LISTING1, din, out, scale=0.25)
+    want = oracle.stencil_apply(LISTING1, data, scale=dtype(0.25))
+    assert np.array_equal(host(out)[1:-1, 1:-1, 1:-1], want)
+    # 27 taps with a right-hand side on a ragged grid
+    taps = [(dx, dy, dz, float(1 + dx + 2 * dy + 3 * dz) / 7.0)
+            for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    u = synth.rng(8).standard_normal((9, 14, 71)).astype(dtype)
+    r = synth.rng(9).standard_normal((9, 14, 71)).astype(dtype)
+    du, dr = dev(u), dev(r)
+    out = empty_like_layout(du)
+    ms.stencil_apply(taps, du, out, rhs=dr, rhs_coef=-0.5, scale=1.0 / 3.0)
+    ttaps = [(a, b, c, dtype(w)) for a, b, c, w in taps]
+    want = oracle.stencil_apply(ttaps, u, rhs=r, rhs_coef=dtype(-0.5), scale=dtype(1.0 / 3.0))
+    assert np.array_equal(host(out)[1:-1, 1:-1, 1:-1], want)
+
+
+def test_stencil_apply_reproduces_the_jacobi_sweep():
+    u = synth.dirichlet_uniform(50, 20, 10, 1)
+    u[1:-1, 1:-1, 1:-1] = synth.rng(2).random((10, 20, 50))
+    f = synth.gaussian_sources(50, 20, 10, 3, 3)
+    taps = [(1, 0, 0, 1.0), (-1, 0, 0, 1.0), (0, 1, 0, 1.0), (0, -1, 0, 1.0), (0, 0, 1, 1.0),
+            (0, 0, -1, 1.0)]
+    du, df = dev(u), dev(f)
+    out = empty_like_layout(du)
+    ms.stencil_apply(taps, du, out, rhs=df, rhs_coef=-1.0, scale=1.0 / 6.0)
+    assert np.array_equal(host(out)[1:-1, 1:-1, 1:-1], oracle.jacobi_sweep(u, f)[1:-1, 1:-1, 1:-1])
+
+
+def test_stencil_apply_rejects_in_place():
+    u = dev(np.zeros((4, 5, 6)))
+    with pytest.raises(ms.MsError):
+        ms.stencil_apply(LISTING1, u, u)
