@@ -18,7 +18,6 @@ residual at 128^3 for plain FP64 vs FP32-refined solves.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -29,23 +28,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+METRIC = "GLUP/s + %HBM peak, 512\u00b3 Jacobi; time-to-1e-8 residual plain vs learned/FP32"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def src_hash(*names):
-    h = hashlib.sha256()
-    for n in names:
-        with open(os.path.join(ROOT, "paper_2310_01882_amd", "csrc", n), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
-def traffic_for(kernel_key, sources, launches_per_step_unit):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, or
+def traffic_for(kernel_key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when absent or taken on different kernel sources."""
+    from paper_2310_01882_amd.profile_summary import source_hash
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -53,7 +46,7 @@ def traffic_for(kernel_key, sources, launches_per_step_unit):
         rec = json.load(open(path)).get(kernel_key)
     except (OSError, ValueError):
         return None
-    if not rec or rec.get("source_hash") != src_hash(*sources):
+    if not rec or rec.get("source_hash") != source_hash(kernel_key):
         return None
     return rec.get("bytes_per_launch")
 
@@ -92,9 +85,11 @@ def bench_jacobi(args, dtype_name="f64"):
     f_h = synth.gaussian_sources(n, n, n, 8, 1)
     u_h = synth.zeros(n, n, n)
     dev = torch.device("cuda:0")
-    u = torch.from_numpy(u_h.astype(np_dt)).to(dev)
-    tmp = u.clone()
-    f = torch.from_numpy(f_h.astype(np_dt)).to(dev)
+    tdt = torch.float64 if dtype_name == "f64" else torch.float32
+    # aligned layout: interior rows start on 128-byte boundaries
+    u = ms.field_from(u_h, tdt)
+    tmp = ms.field_from(u_h, tdt)
+    f = ms.field_from(f_h, tdt)
     res = torch.zeros(sweeps + 1, dtype=torch.float64, device=dev)
     work = ms.jacobi_sweeps_workspace(u)
     stream = torch.cuda.current_stream()
@@ -113,14 +108,14 @@ def bench_jacobi(args, dtype_name="f64"):
     log(f"[bench] {glups:.1f} GLUP/s, {achieved:.0f} GB/s algorithmic, "
         f"{launch_s * 1e6:.1f} us per sweep launch; final residual {res[-1].item():.6e}")
     key = f"jacobi7_{dtype_name}_{n}"
-    traffic = traffic_for(key, ["jacobi.hip", "ms_internal.hpp"], 1)
+    traffic = traffic_for(key)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_jacobi(u_h, f_h, np_dt, args.cpu_sweeps)
     del u, tmp, f
     out = {
-        "metric": "GLUP/s (FP64 7-point Jacobi, 512^3, with fused residual norm)"
-        if dtype_name == "f64" else "GLUP/s (FP32-storage 7-point Jacobi sweeps, 512^3, FP64 norms)",
+        "metric": METRIC if dtype_name == "f64"
+        else "GLUP/s (FP32-storage 7-point Jacobi sweeps, 512^3, FP64 norms)",
         "value": round(glups, 3),
         "unit": "GLUP/s",
         "n_gpus": 1,
@@ -151,7 +146,7 @@ def bench_jacobi(args, dtype_name="f64"):
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "sweep_kernel<%s>" % ("double" if dtype_name == "f64" else "float"),
+            "kernel": "sweep_rt_kernel<%s> (register-tiled)" % ("double" if dtype_name == "f64" else "float"),
             "bytes_per_launch_algorithmic": bpl * cells,
             "avg_launch_us": round(launch_s * 1e6, 3),
         },
@@ -201,9 +196,9 @@ def bench_advect(args):
     u_h, v_h, w_h = synth.velocity_fields(nx, ny, nz, 2)
     t1_h, t2_h = synth.tzc_arrays(nz, 3)
     dev = torch.device("cuda:0")
-    u, v, w = (torch.from_numpy(a).to(dev) for a in (u_h, v_h, w_h))
+    u, v, w = (ms.field_from(a) for a in (u_h, v_h, w_h))
     t1, t2 = torch.from_numpy(t1_h).to(dev), torch.from_numpy(t2_h).to(dev)
-    su, sv, sw = (torch.empty_like(u) for _ in range(3))
+    su, sv, sw = (ms.alloc_field(nx, ny, nz) for _ in range(3))
     stream = torch.cuda.current_stream()
 
     def step():
@@ -235,7 +230,7 @@ def bench_advect(args):
                    "tcx": 0.25, "tcy": 0.25, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_for("advect_512x512x256", ["advect.hip"], 1),
+                     "traffic": traffic_for("advect_512x512x256"),
                      "kernel": "advect_kernel", "bytes_per_launch_algorithmic": 48 * cells,
                      "avg_launch_us": round(secs / passes * 1e6, 3)},
         "cpu_baseline": cpu,

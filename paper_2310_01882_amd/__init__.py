@@ -163,6 +163,36 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
+def alloc_field(nx: int, ny: int, nz: int, dtype=torch.float64, device="cuda",
+                fill=0.0) -> torch.Tensor:
+    """Allocate a halo-padded field whose interior rows start on 128-byte
+    boundaries: the row and plane pitch are rounded up to 128 bytes and the
+    base (halo cell (-1, -1, -1)) sits one element before a boundary, so
+    every 64-lane row access of a sweep covers whole cache lines."""
+    esz = torch.tensor([], dtype=dtype).element_size()
+    a = 128 // esz
+    sy = -(-(nx + 2) // a) * a
+    sz = sy * (ny + 2)
+    sz = -(-sz // a) * a
+    span = (nz + 1) * sz + (ny + 1) * sy + nx + 2
+    store = torch.empty(a - 1 + span, dtype=dtype, device=device)
+    t = store.as_strided((nz + 2, ny + 2, nx + 2), (sz, sy, 1), a - 1)
+    if fill is not None:
+        t.fill_(fill)
+    return t
+
+
+def field_from(arr, dtype=None, device="cuda") -> torch.Tensor:
+    """Copy a (nz+2, ny+2, nx+2) host array into an aligned device field."""
+    src = torch.as_tensor(arr)
+    if dtype is not None:
+        src = src.to(dtype)
+    nz2, ny2, nx2 = src.shape
+    t = alloc_field(nx2 - 2, ny2 - 2, nz2 - 2, src.dtype, device, fill=None)
+    t.copy_(src)
+    return t
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 

@@ -2,6 +2,7 @@
 // mistencil entry points.
 #include "ms_internal.hpp"
 
+#include <cstdlib>
 #include <cstring>
 
 namespace ms {
@@ -41,25 +42,102 @@ int check_grid(const ms_grid* g, const char* who) {
   return MS_OK;
 }
 
-SweepGeom sweep_geom(const ms_grid& g, int zc_hint) {
-  SweepGeom s;
-  s.tiles_x = (g.nx + kTileX - 1) / kTileX;
-  s.tiles_y = (g.ny + kTileY - 1) / kTileY;
+namespace {
+int env_int(const char* name) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : 0;
+}
+}  // namespace
+
+int vec_alignment(const ms_grid& g, int dtype, const void* const* ptrs, int n) {
+  const int esz = dtype == MS_F64 ? 8 : 4;
+  int v = 16 / esz;
+  for (; v > 1; v >>= 1) {
+    bool ok = (g.sy % v == 0) && (g.sz % v == 0);
+    for (int q = 0; q < n && ok; ++q) {
+      if (!ptrs[q]) continue;
+      const uintptr_t p = reinterpret_cast<uintptr_t>(ptrs[q]);
+      ok = (p % esz == 0) && ((p / esz + 1) % v == 0);
+    }
+    if (ok) break;
+  }
+  return v;
+}
+
+namespace {
+
+// Two resident blocks per CU over 256 CUs: measured on 512^3 FP64 and FP32
+// sweeps, a grid that is exactly resident once (no second round, long z
+// marches, few concurrent DRAM streams) beats deeper oversubscription.
+constexpr int64_t kTargetBlocks = 512;
+
+// Splits z so that the grid has about `want` blocks, at least 4 planes per
+// chunk, and never more than kMaxBlocks blocks.
+void split_z(SweepGeom& s, const ms_grid& g, int zc_hint, int64_t want) {
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
   int zc = zc_hint;
   if (zc <= 0) {
-    // Enough z-chunks for ~8 blocks per CU over 256 CUs, but at least 4
-    // planes per chunk so that the two re-read boundary planes stay cheap.
-    const int64_t want_blocks = 2048;
-    int64_t chunks = (want_blocks + tiles2d - 1) / tiles2d;
+    int64_t chunks = (want + tiles2d - 1) / tiles2d;
     if (chunks < 1) chunks = 1;
     zc = (int)((g.nz + chunks - 1) / chunks);
     if (zc < 4) zc = 4;
   }
   if (zc > g.nz) zc = g.nz;
+  while (tiles2d * ((g.nz + zc - 1) / zc) > kMaxBlocks && zc < g.nz) zc *= 2;
+  if (zc > g.nz) zc = g.nz;
   s.zc = zc;
   s.chunks_z = (g.nz + zc - 1) / zc;
-  s.nblocks = (int)(tiles2d * s.chunks_z);
+  const int64_t nb = tiles2d * s.chunks_z;
+  s.nblocks = nb > kMaxBlocks ? kMaxBlocks + 1 : (int)nb;  // > kMaxBlocks is rejected at launch
+}
+
+}  // namespace
+
+SweepGeom sweep_geom_lds(const ms_grid& g) {
+  SweepGeom s{};
+  s.variant = kVariantLds;
+  s.vec = 1;
+  s.wx = 1;
+  s.rows = 4;
+  s.tiles_x = (g.nx + kTileX - 1) / kTileX;
+  s.tiles_y = (g.ny + kWavesY * s.rows - 1) / (kWavesY * s.rows);
+  split_z(s, g, 0, kTargetBlocks);
+  return s;
+}
+
+SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok) {
+  SweepGeom s{};
+  const int ev = env_int("MS_SWEEP_VARIANT");
+  s.variant = (getenv("MS_SWEEP_VARIANT") && ev == 0) ? kVariantLds : kVariantRegister;
+  int rows = env_int("MS_SWEEP_ROWS");
+  if (s.variant == kVariantLds) {
+    s.vec = 1;
+    s.wx = 1;
+    s.rows = (rows == 8) ? 8 : 4;
+    s.tiles_x = (g.nx + kTileX - 1) / kTileX;
+    s.tiles_y = (g.ny + kWavesY * s.rows - 1) / (kWavesY * s.rows);
+    split_z(s, g, env_int("MS_SWEEP_ZC"), kTargetBlocks);
+    return s;
+  }
+  const int vmax = dtype == MS_F64 ? 2 : 4;
+  int vec = env_int("MS_SWEEP_VEC");
+  if (vec != 1 && vec != 2 && vec != 4) vec = dtype == MS_F64 ? 2 : 4;
+  if (vec > vmax) vec = vmax;
+  while (vec > vec_ok) vec >>= 1;
+  // Narrow grids: do not let a lane hold cells that do not exist.
+  while (vec > 1 && 64 * vec > g.nx + 64) vec >>= 1;
+  s.vec = vec;
+  int wx = env_int("MS_SWEEP_WX");
+  if (wx != 1 && wx != 2 && wx != 4) {
+    const int waves_x = (g.nx + 64 * vec - 1) / (64 * vec);
+    wx = waves_x >= 2 ? 2 : 1;
+  }
+  s.wx = wx;
+  s.rows = (rows == 2 || rows == 4 || rows == 8) ? rows : 2;
+  s.tiles_x = (g.nx + 64 * vec * wx - 1) / (64 * vec * wx);
+  const int tile_y = (kWavesY / wx) * s.rows;
+  s.tiles_y = (g.ny + tile_y - 1) / tile_y;
+  split_z(s, g, env_int("MS_SWEEP_ZC"), kTargetBlocks);
   return s;
 }
 

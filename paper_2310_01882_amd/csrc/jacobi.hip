@@ -1,20 +1,25 @@
 // 7-point Jacobi sweeps with the fused residual-norm reduction, the
 // standalone residual pass and their finalisation.
 //
-// Each block owns a 64 x 16 (x, y) tile of the interior and marches along
-// z over a chunk of planes. The current plane of the tile plus its one-cell
-// ring is staged in LDS (double-buffered: one barrier per plane); the z
-// neighbours stay in registers (previous / current / next plane) and the
-// plane after next is prefetched while the current one is computed. A wave
-// spans one 64-cell row, so every global access of the centre and of the
-// y-halo rows is a fully coalesced 512-byte (FP64) row segment.
-//
 // Per cell (the 7-point Laplace iteration of the paper's evaluation,
 // Section 4.1, as an out-of-place update, Section 2.2):
 //   S  = (((((u[i+1] + u[i-1]) + u[j+1]) + u[j-1]) + u[k+1]) + u[k-1])
 //   u' = (S - f) * fl(1/6)          (S * fl(1/6) without f)
 //   r  = f - (S - u*6)              (residual of the input field)
 // and sum r^2 (FP64) goes to one partial per block.
+//
+// Two z-marching kernels compute this; both keep the z neighbours in
+// registers (previous / current / next plane) and prefetch the plane after
+// next while the current one is computed.
+//
+// * Register-tiled (the default): every wave owns a (64*V) x R tile, lane l
+//   holding V consecutive x cells of R consecutive rows, so y neighbours are
+//   registers and x neighbours come from the adjacent lane through DPP
+//   wave shifts. The cells just outside the wave (two x-halo columns, two
+//   y-halo rows) are loaded directly. No LDS and no barrier in the march;
+//   V = 2 (FP64) makes each row access one 1 KiB dwordx4 wave load.
+// * LDS-tiled: a block stages the current plane of a 64 x 4R tile plus its
+//   ring in LDS (double-buffered, one barrier per plane).
 #include "ms_internal.hpp"
 
 // Bit-exact parity with the oracle needs every operation rounded on its own.
@@ -28,7 +33,7 @@ template <typename T>
 struct SweepK {
   T* buf[3];
   const T* f;
-  double* partials;  // [2][nblocks] (sweeps) or [slot][nblocks] (residual)
+  double* partials;  // [2][kMaxBlocks]
   double* hist;
   Ctl* ctl;
   int64_t k_off;
@@ -36,7 +41,7 @@ struct SweepK {
   int slot;  // residual-only launches: partial slot
   int nx, ny, nz;
   int64_t sy, sz;
-  int tiles_x, tiles_y, zc, nblocks;
+  int tiles_x, tiles_y, zc, nblocks, wx;
 };
 
 template <typename T>
@@ -61,31 +66,266 @@ __device__ __forceinline__ double cell_residual(double xp, double xm, double yp,
   return has_f ? f - lap : -lap;
 }
 
-// WRITE: sweep (write u' and evaluate the residual of u); else residual only.
-// ZERO_INT: read the field with its interior replaced by 0 (residual of u^0).
-template <typename T, bool HAS_F, bool WRITE, bool ZERO_INT>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepK<T> a) {
-  constexpr int R = kRowsPerThread;
-  __shared__ T lds[2][kTileY + 2][kTileX + 2];
-  __shared__ double red[kWavesY];
-  __shared__ int s_done;
-
-  const int64_t k = (a.ctl ? a.ctl->base : 0) + a.k_off;
-
-  // Block 0 finalises the previous launch's norm (written by all blocks of
-  // launch k-1, visible after the kernel boundary).
+// Work shared by every sweep launch before its tile: block 0 turns the
+// partials of launch k-1 into ||r(u_{k-1})|| and judges it; then the whole
+// block returns if the solve is already done. Returns false to exit.
+template <typename T, bool WRITE>
+__device__ __forceinline__ bool sweep_prologue(const SweepK<T>& a, int64_t k, double* red,
+                                               int* s_done) {
   if (WRITE && blockIdx.x == 0 && k >= 1 && (a.hist || a.ctl)) {
     if (!a.ctl || a.ctl->done == RUNNING) {
-      const double t = sum_partials(a.partials + ((k - 1) & 1) * (int64_t)a.nblocks,
+      const double t = sum_partials(a.partials + ((k - 1) & 1) * (int64_t)kMaxBlocks,
                                     a.nblocks, red);
       if (threadIdx.x == 0) judge(a.ctl, a.hist, k - 1, sqrt(t));
     }
   }
   if (a.ctl) {
-    if (threadIdx.x == 0) s_done = a.ctl->done;
+    if (threadIdx.x == 0) *s_done = a.ctl->done;
     __syncthreads();
-    if (s_done != RUNNING) return;  // block-uniform
+    if (*s_done != RUNNING) return false;  // block-uniform
   }
+  return true;
+}
+
+// ---------------------------------------------------------------- DPP
+
+// Lane l receives lane l-1's value (wave_shr:1); lane 0 keeps `old`.
+__device__ __forceinline__ float lane_from_left(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
+                                                    0x138, 0xf, 0xf, false));
+}
+// Lane l receives lane l+1's value (wave_shl:1); lane 63 keeps `old`.
+__device__ __forceinline__ float lane_from_right(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
+                                                    0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_left(double old, double v) {
+  const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x138, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x138, 0xf, 0xf,
+                                             false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double lane_from_right(double old, double v) {
+  const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x130, 0xf, 0xf,
+                                             false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// ------------------------------------------------------- vector access
+
+template <typename T, int V>
+struct VecT;
+template <>
+struct VecT<double, 1> { typedef double t; };
+template <>
+struct VecT<double, 2> { typedef double t __attribute__((ext_vector_type(2))); };
+template <>
+struct VecT<float, 1> { typedef float t; };
+template <>
+struct VecT<float, 2> { typedef float t __attribute__((ext_vector_type(2))); };
+template <>
+struct VecT<float, 4> { typedef float t __attribute__((ext_vector_type(4))); };
+
+template <typename T, int V>
+__device__ __forceinline__ T vget(const typename VecT<T, V>::t& x, int v) {
+  if constexpr (V == 1) return x;
+  else return x[v];
+}
+
+// Loads V consecutive elements starting at p; `n` of them exist (0..V).
+template <typename T, int V>
+__device__ __forceinline__ void load_v(T (&d)[V], const T* __restrict__ p, int n) {
+  if (n == V) {
+    typedef typename VecT<T, V>::t vt;
+    const vt x = *reinterpret_cast<const vt*>(p);
+#pragma unroll
+    for (int v = 0; v < V; ++v) d[v] = vget<T, V>(x, v);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) d[v] = v < n ? p[v] : T(0);
+  }
+}
+
+// Stores the first n of V values at p; nontemporal: the output is not read
+// again by this sweep.
+template <typename T, int V>
+__device__ __forceinline__ void store_v(T* __restrict__ p, const T (&d)[V], int n) {
+  if (n == V) {
+    typedef typename VecT<T, V>::t vt;
+    vt x;
+    if constexpr (V == 1) {
+      x = d[0];
+    } else {
+#pragma unroll
+      for (int v = 0; v < V; ++v) x[v] = d[v];
+    }
+    __builtin_nontemporal_store(x, reinterpret_cast<vt*>(p));
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (v < n) __builtin_nontemporal_store(d[v], p + v);
+  }
+}
+
+// ------------------------------------------------ register-tiled kernel
+
+template <typename T, int V, int R, bool HAS_F>
+__global__ __launch_bounds__(kThreads) void sweep_rt_kernel(SweepK<T> a) {
+  __shared__ double red[kWavesY];
+  __shared__ int s_done;
+  const int64_t k = (a.ctl ? a.ctl->base : 0) + a.k_off;
+  if (!sweep_prologue<T, true>(a, k, red, &s_done)) return;
+
+  const int tile = xcd_tile(blockIdx.x, a.nblocks);
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int tzi = rest / a.tiles_y;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wx = w % a.wx, wy = w / a.wx;
+  const int wy_n = kWavesY / a.wx;
+  const int i0 = (txi * a.wx + wx) * (kWave * V);  // first x cell of this wave
+  const int j0 = (tyi * wy_n + wy) * R;            // first row of this wave
+  const int z0 = tzi * a.zc;
+  const int z1 = min(z0 + a.zc, a.nz);
+  const int xi = i0 + lane * V;  // first x cell of this lane
+
+  const T* __restrict__ src = a.buf[k % a.nbuf];
+  T* __restrict__ dst = a.buf[(k + 1) % a.nbuf];
+  const T* __restrict__ f = a.f;
+  const int64_t sy = a.sy, sz = a.sz;
+  const int nx = a.nx, ny = a.ny;
+
+  // Elements of this lane that exist (halo included: i <= nx) and that are
+  // computed (i < nx).
+  const int nload = max(0, min(V, nx + 1 - xi));
+  const int nact = max(0, min(V, nx - xi));
+  int rload[R + 2];  // rows j0-1 .. j0+R: elements to load
+#pragma unroll
+  for (int r = -1; r <= R; ++r) rload[r + 1] = (j0 + r <= ny) ? nload : 0;
+  const int64_t base = (int64_t)(j0 + 1) * sy + (xi + 1);  // row j0, this lane, plane -1
+  const bool left_edge = lane == 0, right_edge = lane == kWave - 1;
+  const int xh_r = i0 + kWave * V;  // right x-halo column of the wave
+  const bool xh_r_ok = right_edge && xh_r <= nx;
+
+  T zp[R][V], zc[R][V], zn[R][V], fc[R][V];
+  T ht[V], hb[V];  // y-halo rows j0-1 and j0+R, current plane
+  T xl[R], xr[R];  // x-halo cells, current plane (lanes 0 / 63)
+
+  auto plane = [&](int kk) { return (int64_t)(kk + 1) * sz; };
+  auto ld_rows = [&](T(&d)[R][V], int kk) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      load_v<T, V>(d[r], src + plane(kk) + base + r * sy, rload[r + 1]);
+  };
+  auto ld_f = [&](T(&d)[R][V], int kk) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (HAS_F) {
+        load_v<T, V>(d[r], f + plane(kk) + base + r * sy, (j0 + r < ny) ? nact : 0);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[r][v] = T(0);
+      }
+    }
+  };
+  auto ld_halo = [&](T(&t)[V], T(&b)[V], T(&l)[R], T(&rr)[R], int kk) {
+    load_v<T, V>(t, src + plane(kk) + base - sy, rload[0]);
+    load_v<T, V>(b, src + plane(kk) + base + R * sy, rload[R + 1]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool rowok = j0 + r <= ny;
+      const int64_t row = plane(kk) + (int64_t)(j0 + r + 1) * sy;
+      l[r] = (left_edge && rowok) ? src[row + i0] : T(0);       // x = i0 - 1
+      rr[r] = (xh_r_ok && rowok) ? src[row + xh_r + 1] : T(0);  // x = i0 + 64V
+    }
+  };
+
+  ld_rows(zp, z0 - 1);
+  ld_rows(zc, z0);
+  ld_rows(zn, z0 + 1);
+  ld_f(fc, z0);
+  ld_halo(ht, hb, xl, xr, z0);
+
+  double acc = 0.0;
+  const T c6 = C6<T>::v();
+  for (int kk = z0; kk < z1; ++kk) {
+    const bool more = kk + 1 < z1;
+    T pf[R][V], fn[R][V], htn[V], hbn[V], xln[R], xrn[R];
+    if (more) {
+      ld_rows(pf, kk + 2);
+      ld_f(fn, kk + 1);
+      ld_halo(htn, hbn, xln, xrn, kk + 1);
+    }
+    // x neighbours across lanes (every lane executes the DPP moves)
+    T xm0[R], xpl[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      xm0[r] = lane_from_left(xl[r], zc[r][V - 1]);  // left of element 0
+      xpl[r] = lane_from_right(xr[r], zc[r][0]);     // right of element V-1
+    }
+    const int64_t pk = plane(kk);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool row_act = j0 + r < ny;
+      T out[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const T xm = v > 0 ? zc[r][v - 1] : xm0[r];
+        const T xp = v < V - 1 ? zc[r][v + 1] : xpl[r];
+        const T ym = r > 0 ? zc[r - 1][v] : ht[v];
+        const T yp = r < R - 1 ? zc[r + 1][v] : hb[v];
+        const T s = ((((xp + xm) + yp) + ym) + zn[r][v]) + zp[r][v];
+        out[v] = HAS_F ? (s - fc[r][v]) * c6 : s * c6;
+        if (row_act && v < nact) {
+          const double res = cell_residual(xp, xm, yp, ym, zn[r][v], zp[r][v], zc[r][v],
+                                           fc[r][v], HAS_F);
+          acc += res * res;
+        }
+      }
+      if (row_act) store_v<T, V>(dst + pk + base + r * sy, out, nact);
+    }
+    if (more) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          zp[r][v] = zc[r][v];
+          zc[r][v] = zn[r][v];
+          zn[r][v] = pf[r][v];
+          fc[r][v] = fn[r][v];
+        }
+        xl[r] = xln[r];
+        xr[r] = xrn[r];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        ht[v] = htn[v];
+        hb[v] = hbn[v];
+      }
+    }
+  }
+
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) a.partials[(int64_t)(k & 1) * kMaxBlocks + blockIdx.x] = tot;
+}
+
+// --------------------------------------------------- LDS-tiled kernel
+
+// WRITE: sweep (write u' and evaluate the residual of u); else residual only.
+// ZERO_INT: read the field with its interior replaced by 0 (residual of u^0).
+template <typename T, int R, bool HAS_F, bool WRITE, bool ZERO_INT>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(SweepK<T> a) {
+  constexpr int kTileY = kWavesY * R;
+  __shared__ T lds[2][kTileY + 2][kTileX + 2];
+  __shared__ double red[kWavesY];
+  __shared__ int s_done;
+
+  const int64_t k = (a.ctl ? a.ctl->base : 0) + a.k_off;
+  if (!sweep_prologue<T, WRITE>(a, k, red, &s_done)) return;
 
   const int tile = xcd_tile(blockIdx.x, a.nblocks);
   const int txi = tile % a.tiles_x;
@@ -191,7 +431,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepK<T> a) {
       if (WRITE) {
         const T s = ((((xp + xm) + yp) + ym) + zn[r]) + zp[r];
         const T v = HAS_F ? (s - fc[r]) * c6 : s * c6;
-        dst[(int64_t)(kk + 1) * sz + coff[r]] = v;
+        __builtin_nontemporal_store(v, dst + (int64_t)(kk + 1) * sz + coff[r]);
       }
       const double res = cell_residual(xp, xm, yp, ym, zn[r], zp[r], zc[r], fc[r], HAS_F);
       acc += res * res;
@@ -209,7 +449,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepK<T> a) {
   }
 
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) a.partials[(int64_t)slot * a.nblocks + blockIdx.x] = tot;
+  if (threadIdx.x == 0) a.partials[(int64_t)slot * kMaxBlocks + blockIdx.x] = tot;
 }
 
 __global__ void finalize_kernel(const double* partials, int nb, double* out, Ctl* ctl,
@@ -224,9 +464,42 @@ __global__ void finalize_kernel(const double* partials, int nb, double* out, Ctl
 }
 
 template <typename T, bool HAS_F, bool WRITE, bool ZERO_INT>
-int launch_t(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
-  hipLaunchKernelGGL((sweep_kernel<T, HAS_F, WRITE, ZERO_INT>), dim3(geo.nblocks),
-                     dim3(kThreads), 0, s, a);
+int launch_lds(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
+  const dim3 grid(geo.nblocks), block(kThreads);
+  if (geo.rows == 8)
+    hipLaunchKernelGGL((sweep_kernel<T, 8, HAS_F, WRITE, ZERO_INT>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((sweep_kernel<T, 4, HAS_F, WRITE, ZERO_INT>), grid, block, 0, s, a);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+template <typename T, int V, bool HAS_F>
+void launch_rt_v(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
+  const dim3 grid(geo.nblocks), block(kThreads);
+  switch (geo.rows) {
+    case 2:
+      hipLaunchKernelGGL((sweep_rt_kernel<T, V, 2, HAS_F>), grid, block, 0, s, a);
+      break;
+    case 8:
+      hipLaunchKernelGGL((sweep_rt_kernel<T, V, 8, HAS_F>), grid, block, 0, s, a);
+      break;
+    default:
+      hipLaunchKernelGGL((sweep_rt_kernel<T, V, 4, HAS_F>), grid, block, 0, s, a);
+      break;
+  }
+}
+
+template <typename T, bool HAS_F>
+int launch_rt(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (geo.vec == 2) launch_rt_v<T, 2, HAS_F>(a, geo, s);
+    else launch_rt_v<T, 1, HAS_F>(a, geo, s);
+  } else {
+    if (geo.vec == 4) launch_rt_v<T, 4, HAS_F>(a, geo, s);
+    else if (geo.vec == 2) launch_rt_v<T, 2, HAS_F>(a, geo, s);
+    else launch_rt_v<T, 1, HAS_F>(a, geo, s);
+  }
   MS_LAUNCH_CHECK();
   return MS_OK;
 }
@@ -238,7 +511,36 @@ SweepK<T> make_args(const ms_grid& g, const SweepGeom& geo) {
   a.sy = g.sy; a.sz = g.sz;
   a.tiles_x = geo.tiles_x; a.tiles_y = geo.tiles_y; a.zc = geo.zc;
   a.nblocks = geo.nblocks;
+  a.wx = geo.wx;
   return a;
+}
+
+template <typename T>
+int sweep_typed(const ms_grid& g, void* const bufs[3], int nbuf, const void* f,
+                double* partials, double* hist, Ctl* ctl, int64_t k_off, const SweepGeom& geo,
+                hipStream_t s) {
+  auto a = make_args<T>(g, geo);
+  for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<T*>(bufs[q]);
+  a.f = static_cast<const T*>(f);
+  a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
+  if (geo.variant == kVariantRegister)
+    return f ? launch_rt<T, true>(a, geo, s) : launch_rt<T, false>(a, geo, s);
+  return f ? launch_lds<T, true, true, false>(a, geo, s)
+           : launch_lds<T, false, true, false>(a, geo, s);
+}
+
+template <typename T>
+int residual_typed(const ms_grid& g, const void* u, const void* f, bool zero_interior,
+                   double* partials, int slot, const SweepGeom& geo, hipStream_t s) {
+  auto a = make_args<T>(g, geo);
+  a.buf[0] = const_cast<T*>(static_cast<const T*>(u));
+  a.f = static_cast<const T*>(f);
+  a.partials = partials; a.slot = slot; a.nbuf = 1;
+  if (zero_interior)
+    return f ? launch_lds<T, true, false, true>(a, geo, s)
+             : launch_lds<T, false, false, true>(a, geo, s);
+  return f ? launch_lds<T, true, false, false>(a, geo, s)
+           : launch_lds<T, false, false, false>(a, geo, s);
 }
 
 }  // namespace
@@ -246,51 +548,30 @@ SweepK<T> make_args(const ms_grid& g, const SweepGeom& geo) {
 int launch_sweep(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
                  double* partials, double* hist, Ctl* ctl, int64_t k_off,
                  const SweepGeom& geo, hipStream_t s) {
-  if (dtype == MS_F64) {
-    auto a = make_args<double>(g, geo);
-    for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<double*>(bufs[q]);
-    a.f = static_cast<const double*>(f);
-    a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
-    return f ? launch_t<double, true, true, false>(a, geo, s)
-             : launch_t<double, false, true, false>(a, geo, s);
-  }
-  auto a = make_args<float>(g, geo);
-  for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<float*>(bufs[q]);
-  a.f = static_cast<const float*>(f);
-  a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
-  return f ? launch_t<float, true, true, false>(a, geo, s)
-           : launch_t<float, false, true, false>(a, geo, s);
+  if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
+    return set_error(MS_EUNSUPPORTED, "sweep geometry with %d blocks", geo.nblocks);
+  if (dtype == MS_F64)
+    return sweep_typed<double>(g, bufs, nbuf, f, partials, hist, ctl, k_off, geo, s);
+  return sweep_typed<float>(g, bufs, nbuf, f, partials, hist, ctl, k_off, geo, s);
 }
 
 int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
-                    bool zero_interior, double* partials, int slot, const SweepGeom& geo,
-                    hipStream_t s) {
-  if (dtype == MS_F64) {
-    auto a = make_args<double>(g, geo);
-    a.buf[0] = const_cast<double*>(static_cast<const double*>(u));
-    a.f = static_cast<const double*>(f);
-    a.partials = partials; a.slot = slot; a.nbuf = 1;
-    if (zero_interior)
-      return f ? launch_t<double, true, false, true>(a, geo, s)
-               : launch_t<double, false, false, true>(a, geo, s);
-    return f ? launch_t<double, true, false, false>(a, geo, s)
-             : launch_t<double, false, false, false>(a, geo, s);
-  }
-  auto a = make_args<float>(g, geo);
-  a.buf[0] = const_cast<float*>(static_cast<const float*>(u));
-  a.f = static_cast<const float*>(f);
-  a.partials = partials; a.slot = slot; a.nbuf = 1;
-  if (zero_interior)
-    return f ? launch_t<float, true, false, true>(a, geo, s)
-             : launch_t<float, false, false, true>(a, geo, s);
-  return f ? launch_t<float, true, false, false>(a, geo, s)
-           : launch_t<float, false, false, false>(a, geo, s);
+                    bool zero_interior, double* partials, int slot, hipStream_t s) {
+  // The standalone residual always runs the LDS-tiled kernel, 4 rows/thread.
+  const SweepGeom geo = sweep_geom_lds(g);
+  if (geo.nblocks > kMaxBlocks)
+    return set_error(MS_EUNSUPPORTED, "residual geometry with %d blocks", geo.nblocks);
+  if (dtype == MS_F64)
+    return residual_typed<double>(g, u, f, zero_interior, partials, slot, geo, s);
+  return residual_typed<float>(g, u, f, zero_interior, partials, slot, geo, s);
 }
+
+int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 
 int launch_finalize(const double* partials, int slot, int nblocks, double* out_norm, Ctl* ctl,
                     double* hist, int64_t k, hipStream_t s) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(kThreads), 0, s,
-                     partials + (int64_t)slot * nblocks, nblocks, out_norm, ctl, hist, k);
+                     partials + (int64_t)slot * kMaxBlocks, nblocks, out_norm, ctl, hist, k);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

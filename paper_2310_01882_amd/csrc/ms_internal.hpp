@@ -36,8 +36,11 @@ void clear_error();
 // Validates extents and strides of a grid descriptor.
 int check_grid(const ms_grid* g, const char* who);
 
-// Number of elements spanned by a field on grid g (halo included).
-inline int64_t field_span(const ms_grid& g) { return g.sz * (int64_t)(g.nz + 2); }
+// Number of elements from the base pointer to one past the last halo cell
+// (the last plane and row carry no trailing pitch).
+inline int64_t field_span(const ms_grid& g) {
+  return (int64_t)(g.nz + 1) * g.sz + (int64_t)(g.ny + 1) * g.sy + (g.nx + 2);
+}
 
 // True if [a, a + abytes) and [b, b + bbytes) overlap.
 inline bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
@@ -80,15 +83,34 @@ constexpr int kWave = 64;   // wavefront width on CDNA
 constexpr int kTileX = 64;  // one wave spans a tile row in x
 constexpr int kWavesY = 4;  // waves per block
 constexpr int kThreads = kTileX * kWavesY;
-constexpr int kRowsPerThread = 4;
-constexpr int kTileY = kWavesY * kRowsPerThread;  // 16 rows per tile
+// Per-block partial sums live in a fixed-size table so that the workspace
+// does not depend on the launch geometry.
+constexpr int kMaxBlocks = 65536;
 
+enum SweepVariant : int { kVariantLds = 0, kVariantRegister = 1 };
+
+// Launch geometry of a z-marching sweep. Register-tiled: each wave owns a
+// (64*vec) x rows tile, wx waves side by side in x, 4/wx stacked in y.
+// LDS-tiled: a block owns a 64 x (4*rows) tile. Every block marches zc planes.
 struct SweepGeom {
+  int variant;
+  int vec;   // x cells per lane (register-tiled)
+  int wx;    // waves per block along x (register-tiled)
+  int rows;  // rows per thread
   int tiles_x, tiles_y, chunks_z, zc;
   int nblocks;
 };
 
-SweepGeom sweep_geom(const ms_grid& g, int zc_hint);
+// Largest vector width (elements per lane, up to 16 bytes) for which
+// interior cell (0, j, k) of every given field sits on a vector boundary.
+int vec_alignment(const ms_grid& g, int dtype, const void* const* ptrs, int n);
+
+// Geometry of the sweeps of one call. vec_ok caps the vector width; the
+// defaults can be overridden for tuning through MS_SWEEP_VARIANT (0 lds,
+// 1 register), MS_SWEEP_VEC, MS_SWEEP_WX, MS_SWEEP_ROWS and MS_SWEEP_ZC.
+SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok);
+// LDS-tiled geometry with 4 rows per thread (standalone residual passes).
+SweepGeom sweep_geom_lds(const ms_grid& g);
 
 // Maps hardware block ids so that consecutive tiles share an XCD: blocks are
 // dispatched round-robin over the 8 XCDs, each with its own L2.
@@ -166,11 +188,14 @@ int launch_sweep(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
                  int64_t k_off, const SweepGeom& geo, hipStream_t s);
 
 // Standalone residual: per-block partials of sum r^2 into partials[slot];
-// zero_interior evaluates u with its interior replaced by 0. When
-// `prev_k >= 0` block 0 first finalises the previous sweep's partials.
+// zero_interior evaluates u with its interior replaced by 0. It launches
+// residual_blocks(g) blocks.
 int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
-                    bool zero_interior, double* partials, int slot,
-                    const SweepGeom& geo, hipStream_t s);
+                    bool zero_interior, double* partials, int slot, hipStream_t s);
+int residual_blocks(const ms_grid& g);
+
+// Partials table: two slots of kMaxBlocks doubles.
+constexpr size_t kPartialsBytes = 2 * (size_t)kMaxBlocks * sizeof(double);
 
 // One-block finalisation: norm = sqrt(sum partials[slot]); writes *out_norm
 // (if not null) and judges iterate k against ctl (if not null).

@@ -183,24 +183,40 @@ int auto_chunk(const ms_grid& g, int requested) {
   return cells >= 16.0e6 ? 64 : 256;
 }
 
+// Fields carved from a workspace start `phase` elements past a 256-byte
+// boundary, so that their interior rows share the vector alignment of the
+// caller's field (phase = that field's element offset modulo 32).
+constexpr size_t kFieldSlack = 256;
+
+int elem_phase(const void* p, int esz) {
+  return (int)((reinterpret_cast<uintptr_t>(p) / esz) % (256 / esz));
+}
+
+// FP32 correction grids of the refined solve use their own pitch: rows and
+// planes padded to 32 elements and the base one element before a 128-byte
+// boundary, so FP32 sweeps get 16-byte lanes whatever the FP64 layout.
+ms_grid f32_grid(const ms_grid& g) {
+  ms_grid h = g;
+  h.sy = ((int64_t)g.nx + 2 + 31) / 32 * 32;
+  h.sz = (h.sy * ((int64_t)g.ny + 2) + 31) / 32 * 32;
+  return h;
+}
+
 struct SolveLayout {
-  size_t f64_field, f32_field, partials, hist_f64, hist_inner, total;
+  size_t total;
 };
 
 SolveLayout solve_layout(const ms_grid& g, const ms_solve_opts& o) {
   SolveLayout L{};
-  const SweepGeom geo = sweep_geom(g, 0);
-  const size_t span = (size_t)field_span(g);
-  L.partials = align_up(2 * (size_t)geo.nblocks * sizeof(double), 256);
-  size_t t = align_up(sizeof(Ctl), 256) + L.partials;
+  size_t t = align_up(sizeof(Ctl), 256) + align_up(kPartialsBytes, 256);
   if (o.precision == MS_SOLVE_F64) {
-    L.f64_field = align_up(span * 8, 256);
-    L.hist_f64 = align_up(((size_t)o.max_sweeps + 2) * sizeof(double), 256);
-    t += 2 * L.f64_field + L.hist_f64;
+    const size_t field = align_up((size_t)field_span(g) * 8 + kFieldSlack, 256);
+    t += 2 * field + align_up(((size_t)o.max_sweeps + 2) * sizeof(double), 256);
   } else {
-    L.f32_field = align_up(span * 4, 256);
-    L.hist_inner = align_up(((size_t)o.max_inner + 2) * sizeof(double), 256);
-    t += 4 * L.f32_field + L.hist_inner + align_up(sizeof(Ctl), 256);
+    const ms_grid h = f32_grid(g);
+    const size_t field = align_up((size_t)field_span(h) * 4 + kFieldSlack, 256);
+    t += 4 * field + align_up(((size_t)o.max_inner + 2) * sizeof(double), 256) +
+         align_up(sizeof(Ctl), 256);
   }
   L.total = t;
   return L;
@@ -234,8 +250,7 @@ using namespace ms;
 
 extern "C" size_t residual_workspace_bytes(const ms_grid* g) {
   if (check_grid(g, "residual_workspace_bytes")) return 0;
-  const SweepGeom geo = sweep_geom(*g, 0);
-  return align_up((size_t)geo.nblocks * sizeof(double), 256) + align_up(sizeof(double), 256);
+  return align_up(kPartialsBytes / 2, 256) + align_up(sizeof(double), 256);
 }
 
 extern "C" int residual_norm(const ms_grid* g, int dtype, const void* u, const void* f,
@@ -250,13 +265,12 @@ extern "C" int residual_norm(const ms_grid* g, int dtype, const void* u, const v
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "residual_norm: workspace needs %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const SweepGeom geo = sweep_geom(*g, 0);
   Workspace ws{static_cast<char*>(work), work_bytes};
-  double* partials = ws.take<double>(geo.nblocks);
+  double* partials = ws.take<double>(kMaxBlocks);
   double* dnorm = ws.take<double>(1);
-  if (int rc = launch_residual(*g, dtype, u, f, false, partials, 0, geo, s)) return rc;
-  if (int rc = launch_finalize(partials, 0, geo.nblocks, out_on_device ? norm_out : dnorm,
-                               nullptr, nullptr, 0, s))
+  if (int rc = launch_residual(*g, dtype, u, f, false, partials, 0, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, residual_blocks(*g),
+                               out_on_device ? norm_out : dnorm, nullptr, nullptr, 0, s))
     return rc;
   if (!out_on_device) {
     MS_HIP_TRY(hipMemcpyAsync(norm_out, dnorm, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -269,8 +283,7 @@ extern "C" int residual_norm(const ms_grid* g, int dtype, const void* u, const v
 
 extern "C" size_t jacobi_sweeps_workspace_bytes(const ms_grid* g) {
   if (check_grid(g, "jacobi_sweeps_workspace_bytes")) return 0;
-  const SweepGeom geo = sweep_geom(*g, 0);
-  return align_up(2 * (size_t)geo.nblocks * sizeof(double), 256);
+  return align_up(kPartialsBytes, 256);
 }
 
 extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
@@ -291,7 +304,8 @@ extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, 
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "jacobi_sweeps: workspace needs %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const SweepGeom geo = sweep_geom(*g, 0);
+  const void* ptrs[3] = {u, u_tmp, f};
+  const SweepGeom geo = sweep_geom(*g, dtype, vec_alignment(*g, dtype, ptrs, 3));
   double* partials = static_cast<double*>(work);
   void* bufs[3] = {u, u_tmp, u};
   for (int64_t k = 0; k < n; ++k)
@@ -303,9 +317,10 @@ extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, 
                                    res_dev, n - 1, s))
         return rc;
     const int slot = (int)(n & 1);
-    if (int rc = launch_residual(*g, dtype, (n & 1) ? u_tmp : u, f, false, partials, slot, geo, s))
+    if (int rc = launch_residual(*g, dtype, (n & 1) ? u_tmp : u, f, false, partials, slot, s))
       return rc;
-    if (int rc = launch_finalize(partials, slot, geo.nblocks, nullptr, nullptr, res_dev, n, s))
+    if (int rc = launch_finalize(partials, slot, residual_blocks(*g), nullptr, nullptr, res_dev,
+                                 n, s))
       return rc;
   }
   return MS_OK;
@@ -336,18 +351,24 @@ extern "C" size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* 
 namespace ms {
 namespace {
 
+template <typename T>
+T* take_field(Workspace& ws, const ms_grid& g, int phase) {
+  char* p = ws.take<char>((size_t)field_span(g) * sizeof(T) + kFieldSlack);
+  return p ? reinterpret_cast<T*>(p) + phase : nullptr;
+}
+
 int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double* f,
-              Workspace& ws, const SolveLayout& L, double* hist_host, ms_solve_result* res,
-              hipStream_t s) {
-  const SweepGeom geo = sweep_geom(g, 0);
+              Workspace& ws, double* hist_host, ms_solve_result* res, hipStream_t s) {
   const size_t span = (size_t)field_span(g);
   Ctl* ctl = ws.take<Ctl>(1);
-  double* partials = ws.take<double>(2 * (size_t)geo.nblocks);
-  double* b1 = ws.take<double>(span);
-  double* b2 = ws.take<double>(span);
+  double* partials = ws.take<double>(2 * (size_t)kMaxBlocks);
+  double* b1 = take_field<double>(ws, g, elem_phase(u, 8));
+  double* b2 = take_field<double>(ws, g, elem_phase(u, 8));
   double* hist = ws.take<double>((size_t)o.max_sweeps + 2);
   if (!ctl || !partials || !b1 || !b2 || !hist)
     return set_error(MS_EWORKSPACE, "jacobi_solve: workspace carve failed");
+  const void* ptrs[4] = {u, b1, b2, f};
+  const SweepGeom geo = sweep_geom(g, MS_F64, vec_alignment(g, MS_F64, ptrs, 4));
   // Every buffer carries the Dirichlet halo; sweeps never write it.
   MS_HIP_TRY(hipMemcpyAsync(b1, u, span * 8, hipMemcpyDeviceToDevice, s));
   MS_HIP_TRY(hipMemcpyAsync(b2, u, span * 8, hipMemcpyDeviceToDevice, s));
@@ -355,8 +376,9 @@ int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double*
                      0, 0);
   MS_LAUNCH_CHECK();
   // res0 = ||r(u^0)||, u^0 = u with its interior zeroed.
-  if (int rc = launch_residual(g, MS_F64, u, f, true, partials, 0, geo, s)) return rc;
-  if (int rc = launch_finalize(partials, 0, geo.nblocks, &ctl->res0, nullptr, nullptr, 0, s))
+  if (int rc = launch_residual(g, MS_F64, u, f, true, partials, 0, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, residual_blocks(g), &ctl->res0, nullptr, nullptr,
+                               0, s))
     return rc;
 
   Ctl hc{};
@@ -390,44 +412,49 @@ int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double*
 }
 
 int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const double* f,
-                  Workspace& ws, const SolveLayout& L, double* hist_host, ms_solve_result* res,
-                  hipStream_t s) {
-  const SweepGeom geo = sweep_geom(g, 0);
-  const size_t span = (size_t)field_span(g);
+                  Workspace& ws, double* hist_host, ms_solve_result* res, hipStream_t s) {
+  const ms_grid h = f32_grid(g);
+  const size_t span32 = (size_t)field_span(h);
   Ctl* ctl = ws.take<Ctl>(1);
-  double* partials = ws.take<double>(2 * (size_t)geo.nblocks);
-  float* rhat = ws.take<float>(span);
-  float* e[3] = {ws.take<float>(span), ws.take<float>(span), ws.take<float>(span)};
+  double* partials = ws.take<double>(2 * (size_t)kMaxBlocks);
+  // base one element before a 128-byte boundary: phase 31 of 64 floats
+  float* rhat = take_field<float>(ws, h, 31);
+  float* e[3] = {take_field<float>(ws, h, 31), take_field<float>(ws, h, 31),
+                 take_field<float>(ws, h, 31)};
   double* hist = ws.take<double>((size_t)o.max_inner + 2);
   Ctl* octl = ws.take<Ctl>(1);
   if (!ctl || !partials || !rhat || !e[0] || !e[1] || !e[2] || !hist || !octl)
     return set_error(MS_EWORKSPACE, "jacobi_solve: workspace carve failed");
-  // FP32 grids share the FP64 grid's element strides, so their halos (zero:
-  // the correction has homogeneous boundary values) line up cell for cell.
+  if (g.ny > 65535 || g.nz > 65535)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: refined path needs ny, nz <= 65535");
+  const void* ptrs[4] = {rhat, e[0], e[1], e[2]};
+  const SweepGeom geo = sweep_geom(h, MS_F32, vec_alignment(h, MS_F32, ptrs, 4));
+  // The correction has homogeneous boundary values: zero every FP32 grid
+  // once (halos included); the sweeps never write a halo.
   for (float* p : {rhat, e[0], e[1], e[2]}) {
-    hipLaunchKernelGGL(fill_f32_kernel, dim3(1024), dim3(256), 0, s, p, (int64_t)span);
+    hipLaunchKernelGGL(fill_f32_kernel, dim3(1024), dim3(256), 0, s, p, (int64_t)span32);
     MS_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, octl, 0.0, (int64_t)0, 0, 0, 0);
   MS_LAUNCH_CHECK();
-  if (int rc = launch_residual(g, MS_F64, x, f, true, partials, 0, geo, s)) return rc;
-  if (int rc = launch_finalize(partials, 0, geo.nblocks, &octl->res0, nullptr, nullptr, 0, s))
+  if (int rc = launch_residual(g, MS_F64, x, f, true, partials, 0, s)) return rc;
+  if (int rc = launch_finalize(partials, 0, residual_blocks(g), &octl->res0, nullptr, nullptr,
+                               0, s))
     return rc;
   double res0 = 0.0;
   MS_HIP_TRY(hipMemcpyAsync(&res0, &octl->res0, sizeof(double), hipMemcpyDeviceToHost, s));
   MS_HIP_TRY(hipStreamSynchronize(s));
 
   const double ncells = (double)g.nx * g.ny * g.nz;
-  if (g.ny > 65535 || g.nz > 65535)
-    return set_error(MS_EUNSUPPORTED, "jacobi_solve: refined path needs ny, nz <= 65535");
   const dim3 eb(256), eg((g.nx + 255) / 256, g.ny, g.nz);
   int64_t total = 0;
   int outer = 0;
   int status = MS_OK;
   double nr = 0.0, rel = 0.0;
   for (;;) {
-    if (int rc = launch_residual(g, MS_F64, x, f, false, partials, 0, geo, s)) return rc;
-    if (int rc = launch_finalize(partials, 0, geo.nblocks, &octl->last, nullptr, nullptr, 0, s))
+    if (int rc = launch_residual(g, MS_F64, x, f, false, partials, 0, s)) return rc;
+    if (int rc = launch_finalize(partials, 0, residual_blocks(g), &octl->last, nullptr, nullptr,
+                                 0, s))
       return rc;
     MS_HIP_TRY(hipMemcpyAsync(&nr, &octl->last, sizeof(double), hipMemcpyDeviceToHost, s));
     MS_HIP_TRY(hipStreamSynchronize(s));
@@ -445,10 +472,10 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
     const double sc = pow2_scale(nr, ncells);
     if (f)
       hipLaunchKernelGGL(refine_rhs_kernel<true>, eg, eb, 0, s, x, f, rhat, e[0], 1.0 / sc,
-                         g.nx, g.ny, g.nz, g.sy, g.sz, g.sy, g.sz);
+                         g.nx, g.ny, g.nz, g.sy, g.sz, h.sy, h.sz);
     else
       hipLaunchKernelGGL(refine_rhs_kernel<false>, eg, eb, 0, s, x, f, rhat, e[0], 1.0 / sc,
-                         g.nx, g.ny, g.nz, g.sy, g.sz, g.sy, g.sz);
+                         g.nx, g.ny, g.nz, g.sy, g.sz, h.sy, h.sz);
     MS_LAUNCH_CHECK();
     int64_t cap = o.max_inner;
     if (o.max_sweeps - total < cap) cap = o.max_sweeps - total;
@@ -457,7 +484,7 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
     MS_LAUNCH_CHECK();
     Ctl hc{};
     hc.max_sweeps = cap;
-    ChunkRunner run{g, MS_F32, {e[0], e[1], e[2]}, rhat, partials, hist, ctl, geo,
+    ChunkRunner run{h, MS_F32, {e[0], e[1], e[2]}, rhat, partials, hist, ctl, geo,
                     auto_chunk(g, o.check_every), o.use_graph != 0, s};
     if (int rc = run.run(&hc)) return rc;
     if (hc.done == NONFINITE) {
@@ -465,7 +492,7 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
       break;
     }
     hipLaunchKernelGGL(refine_update_kernel, eg, eb, 0, s, x, e[0], e[1], e[2], ctl, sc, g.nx,
-                       g.sy, g.sz, g.sy, g.sz);
+                       g.sy, g.sz, h.sy, h.sz);
     MS_LAUNCH_CHECK();
     total += hc.K;
     ++outer;
@@ -500,6 +527,6 @@ extern "C" int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
     return set_error(MS_EINVAL, "jacobi_solve: workspace overlaps a field");
   Workspace ws{static_cast<char*>(work), work_bytes};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o->precision == MS_SOLVE_F64) return solve_f64(*g, *o, u, f, ws, L, hist_host, res, s);
-  return solve_refined(*g, *o, u, f, ws, L, hist_host, res, s);
+  if (o->precision == MS_SOLVE_F64) return solve_f64(*g, *o, u, f, ws, hist_host, res, s);
+  return solve_refined(*g, *o, u, f, ws, hist_host, res, s);
 }

@@ -1,0 +1,73 @@
+"""Small, fixed workloads for rocprofv3 runs (kernel traces and HBM counters).
+
+    python -m paper_2310_01882_amd.profile_run sweep  [--dtype f64|f32] [--sweeps N]
+    python -m paper_2310_01882_amd.profile_run advect [--passes N]
+    python -m paper_2310_01882_amd.profile_run copy   [--mib M]
+
+`sweep` runs N sweeps of the 512^3 Poisson workload (8 Gaussian sources,
+seed 1, zero start) on aligned fields, with the launch geometry the
+benchmark uses. `advect` runs N passes of the 512 x 512 x 256 advection
+term. `copy` is the calibration kernel of known size: one device-to-device
+tensor copy of M MiB (reads M MiB, writes M MiB), used to scale the
+FETCH_SIZE / WRITE_SIZE counters.
+"""
+
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["sweep", "advect", "copy"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--sweeps", type=int, default=10)
+    ap.add_argument("--passes", type=int, default=5)
+    ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=512)
+    args = ap.parse_args()
+
+    import torch
+
+    import paper_2310_01882_amd as ms
+    import synth
+
+    if args.what == "copy":
+        n = args.mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"copy of {args.mib} MiB x 3 done", flush=True)
+        return
+    if args.what == "sweep":
+        n = args.n
+        dt = torch.float64 if args.dtype == "f64" else torch.float32
+        f = ms.field_from(synth.gaussian_sources(n, n, n, 8, 1), dt)
+        u = ms.alloc_field(n, n, n, dt)
+        tmp = ms.alloc_field(n, n, n, dt)
+        res = torch.zeros(args.sweeps + 1, dtype=torch.float64, device="cuda")
+        ms.jacobi_sweeps(u, tmp, args.sweeps, f=f, res=res)
+        torch.cuda.synchronize()
+        print(f"{args.sweeps} sweeps of {n}^3 ({args.dtype}) done; "
+              f"final residual {res[-1].item():.6e}", flush=True)
+        return
+    nx, ny, nz = 512, 512, 256
+    u, v, w = (ms.field_from(a) for a in synth.velocity_fields(nx, ny, nz, 2))
+    t1, t2 = (torch.from_numpy(a).cuda() for a in synth.tzc_arrays(nz, 3))
+    outs = [ms.alloc_field(nx, ny, nz) for _ in range(3)]
+    for _ in range(args.passes):
+        ms.advect_source(u, v, w, t1, t2, 0.25, 0.25, *outs)
+    torch.cuda.synchronize()
+    print(f"{args.passes} advection passes done", flush=True)
+
+
+if __name__ == "__main__":
+    main()
