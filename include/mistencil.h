@@ -137,15 +137,16 @@ int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
  *
  * precision MS_SOLVE_F64: plain FP64 sweeps, max_sweeps caps K.
  * precision MS_SOLVE_F32_REFINED: FP64 iterative refinement around FP32
- *   sweeps. Outer: r = f - L(x) in FP64; stop if ||r||/res0 <= rel_tol;
+ *   sweeps. Outer: r = f - L(x) in FP64; stop if rel = ||r||/res0 <= rel_tol;
  *   s = 2^floor(log2(||r|| / sqrt(N))); rhat = fl32(r / s); inner FP32 Jacobi
  *   on L(e) = rhat from e = 0 (zero halo) until its FP64 residual drops to
- *   inner_eta times its start, or stalls (no decrease over stall_window
- *   sweeps), or max_inner sweeps; then x += s * e in FP64. max_outer caps
- *   the outer steps, max_sweeps the total inner sweeps.
+ *   max(inner_eta, rel_tol / (2 rel)) times its start, or stalls (no
+ *   decrease over stall_window sweeps), or max_inner sweeps; then
+ *   x += s * e in FP64. max_outer caps the outer steps, max_sweeps the total
+ *   inner sweeps.
  * check_every: sweeps per device-side chunk between host checks (0 = auto).
- * temporal_block: sweeps fused per pass (0/1 = none; 2 = two-sweep blocking,
- *   FP64 only; the per-cell arithmetic is unchanged).
+ * temporal_block: sweeps fused per pass (0 or 1; larger values return
+ *   MS_EUNSUPPORTED).
  * use_graph: 1 = replay chunks as hipGraphs (default), 0 = plain launches.
  *
  * u: device, in: initial guess + Dirichlet halo; out: the answer u_K.

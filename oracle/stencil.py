@@ -175,8 +175,10 @@ def refined_solve(x0, f, tol: float, eta: float, max_outer: int, max_inner: int,
     Otherwise s = pow2_scale(||r||, N), rhat = fl32(r / s), and the inner FP32
     Jacobi solves L(e) = rhat from e = 0 with a zero halo. Inner sweep j
     first measures the FP64 residual rho_j = ||rhat - L(e_j)|| of its input;
-    the inner stops at the first j with rho_j <= eta * rho_0, or j =
+    the inner stops at the first j with rho_j <= eta_o * rho_0, or j =
     max_inner, or (stagnation) j >= stall and rho_j >= rho_{j - stall}.
+    The inner target eta_o = max(eta, tol / (2 rel_o)) asks for no more than
+    the reduction that brings the outer residual to half the tolerance.
     Then x += s * e on the interior, in FP64.
 
     ``inner_counts`` replays given inner sweep counts instead of testing
@@ -204,6 +206,7 @@ def refined_solve(x0, f, tol: float, eta: float, max_outer: int, max_inner: int,
         if outer == max_outer:
             break
         s = pow2_scale(nr, ncells)
+        eta_o = max(eta, 0.5 * tol / rel)
         rhat = np.zeros(x.shape, np.float32)
         rhat[INTERIOR] = (r / s).astype(np.float32)
         e = np.zeros(x.shape, np.float32)
@@ -214,7 +217,7 @@ def refined_solve(x0, f, tol: float, eta: float, max_outer: int, max_inner: int,
                 if j == inner_counts[outer]:
                     break
             else:
-                if rho[j] <= eta * rho[0] or j == max_inner:
+                if rho[j] <= eta_o * rho[0] or j == max_inner:
                     break
                 if j >= stall and rho[j] >= rho[j - stall]:
                     break

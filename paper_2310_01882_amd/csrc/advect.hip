@@ -8,10 +8,18 @@
 // where P on each side is phi at the neighbour on that side times the sum of
 // the two samples of the advecting velocity that straddle that face.
 //
-// One thread owns an (i, j) column of a tile and marches up a z-chunk. The
-// values of u, v, w on the column at levels k-1, k, k+1 rotate through
-// registers; in-plane neighbours are read from global memory and served by
-// the L1/L2 caches (neighbouring lanes touch the same lines).
+// Staged kernel (default): a block owns a 64 x 8 (x, y) tile and marches a
+// z-chunk. Planes of u, v, w (tile plus a one-cell ring, corners included)
+// pass through a ring of four LDS buffers: at level k the block reads level
+// k (all in-plane neighbours) and level k+1 (the four off-column values the
+// upper face needs), writes level k+2 that it prefetched into registers one
+// step earlier, and issues the global loads of level k+3. Four buffers
+// leave one barrier per level. The level-(k-1) values (five per cell) are
+// carried in registers from the previous level. Every input element is read
+// from HBM once per z-chunk plus the ring; outputs are nontemporal stores.
+//
+// Direct kernel (cross-check): one thread per column, all neighbours read
+// from global memory through the caches.
 #include "ms_internal.hpp"
 
 #pragma clang fp contract(off)
@@ -31,7 +39,164 @@ struct AdvK {
   double tcx, tcy;
   int nx, ny, nz, zc;
   int64_t sy, sz;
+  int tiles_x, tiles_y, nblocks;
 };
+
+// s_phi from its six face products, in the order of the definition.
+__device__ __forceinline__ double combine(double tcx, double tcy, double c1, double c2,
+                                          double pxm, double pxp, double pym, double pyp,
+                                          double pzm, double pzp) {
+  return (tcx * (pxm - pxp) + tcy * (pym - pyp)) + (c1 * pzm - c2 * pzp);
+}
+
+// ------------------------------------------------------------ staged kernel
+
+constexpr int kAdvTX = 64;
+constexpr int kAdvRows = 2;                  // rows per thread
+constexpr int kAdvTY = kWavesY * kAdvRows;   // 8
+constexpr int kAdvLX = kAdvTX + 2;           // 66
+constexpr int kAdvLY = kAdvTY + 2;           // 10
+constexpr int kAdvRing = 2 * kAdvLX + 2 * kAdvTY;  // 148 ring cells per field
+
+__global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
+  __shared__ double L[4][3][kAdvLY][kAdvLX];
+
+  const int tile = xcd_tile(blockIdx.x, a.nblocks);
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int tzi = rest / a.tiles_y;
+  const int i0 = txi * kAdvTX, j0 = tyi * kAdvTY;
+  const int z0 = tzi * a.zc;
+  const int z1 = min(z0 + a.zc, a.nz);
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  const int nx = a.nx, ny = a.ny;
+  const int64_t sy = a.sy, sz = a.sz;
+  const double* __restrict__ fld[3] = {a.u, a.v, a.w};
+  double* __restrict__ out[3] = {a.su, a.sv, a.sw};
+
+  // Centre cells of this thread: column i, rows j0 + wy*R + r.
+  const int i = i0 + lane;
+  int64_t coff[kAdvRows];
+  bool cld[kAdvRows], cact[kAdvRows];
+#pragma unroll
+  for (int r = 0; r < kAdvRows; ++r) {
+    const int j = j0 + wy * kAdvRows + r;
+    coff[r] = (int64_t)(j + 1) * sy + (i + 1);
+    cld[r] = i <= nx && j <= ny;
+    cact[r] = i < nx && j < ny;
+  }
+  // Ring cell of this thread (threads 0..147): rows 0 and LY-1 in full, then
+  // columns 0 and LX-1 of the rows in between.
+  int rrow = 0, rcol = 0;
+  bool rown = false;
+  {
+    const int t = threadIdx.x;
+    if (t < kAdvLX) {
+      rrow = 0; rcol = t; rown = true;
+    } else if (t < 2 * kAdvLX) {
+      rrow = kAdvLY - 1; rcol = t - kAdvLX; rown = true;
+    } else if (t < 2 * kAdvLX + kAdvTY) {
+      rrow = t - 2 * kAdvLX + 1; rcol = 0; rown = true;
+    } else if (t < kAdvRing) {
+      rrow = t - 2 * kAdvLX - kAdvTY + 1; rcol = kAdvLX - 1; rown = true;
+    }
+  }
+  const int ri = i0 - 1 + rcol, rj = j0 - 1 + rrow;
+  const bool rld = rown && ri <= nx && rj <= ny;
+  const int64_t roff = (int64_t)(rj + 1) * sy + (ri + 1);
+
+  auto plane = [&](int k) { return (int64_t)(k + 1) * sz; };
+  // registers of one staged level: centre rows and the ring cell, per field
+  auto load_level = [&](double (&c)[3][kAdvRows], double (&rg)[3], int k) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int r = 0; r < kAdvRows; ++r) c[q][r] = cld[r] ? fld[q][plane(k) + coff[r]] : 0.0;
+      rg[q] = rld ? fld[q][plane(k) + roff] : 0.0;
+    }
+  };
+  auto store_level = [&](const double (&c)[3][kAdvRows], const double (&rg)[3], int b) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+#pragma unroll
+      for (int r = 0; r < kAdvRows; ++r) L[b][q][wy * kAdvRows + r + 1][lane + 1] = c[q][r];
+      if (rown) L[b][q][rrow][rcol] = rg[q];
+    }
+  };
+
+  // Level z0-1 values each cell needs: u, v, w at the cell, w at (i+1, j)
+  // and at (i, j+1).
+  double um1[kAdvRows], vm1[kAdvRows], wm1[kAdvRows], wm1x[kAdvRows], wm1y[kAdvRows];
+#pragma unroll
+  for (int r = 0; r < kAdvRows; ++r) {
+    const int64_t p = plane(z0 - 1) + coff[r];
+    um1[r] = cact[r] ? a.u[p] : 0.0;
+    vm1[r] = cact[r] ? a.v[p] : 0.0;
+    wm1[r] = cact[r] ? a.w[p] : 0.0;
+    wm1x[r] = cact[r] ? a.w[p + 1] : 0.0;
+    wm1y[r] = cact[r] ? a.w[p + sy] : 0.0;
+  }
+  {
+    double c[3][kAdvRows], rg[3];
+    load_level(c, rg, z0);
+    store_level(c, rg, 0);
+    load_level(c, rg, z0 + 1);
+    store_level(c, rg, 1);
+  }
+  double pc[3][kAdvRows], prg[3];  // prefetched level k+2
+  if (z0 + 1 < z1) load_level(pc, prg, z0 + 2);
+
+  const double tcx = a.tcx, tcy = a.tcy;
+  for (int k = z0; k < z1; ++k) {
+    const int b = (k - z0) & 3, nb = (b + 1) & 3, wb = (b + 2) & 3;
+    if (k + 1 < z1) {
+      store_level(pc, prg, wb);
+      if (k + 2 < z1) load_level(pc, prg, k + 3);
+    }
+    __syncthreads();
+    const double c1 = a.t1[k], c2 = a.t2[k];
+#pragma unroll
+    for (int r = 0; r < kAdvRows; ++r) {
+      const int y = wy * kAdvRows + r + 1, x = lane + 1;
+      auto Lu = [&](int dy, int dx) { return L[b][0][y + dy][x + dx]; };
+      auto Lv = [&](int dy, int dx) { return L[b][1][y + dy][x + dx]; };
+      auto Lw = [&](int dy, int dx) { return L[b][2][y + dy][x + dx]; };
+      const double u0 = Lu(0, 0), v0 = Lv(0, 0), w0 = Lw(0, 0);
+      const double up = L[nb][0][y][x], upxm = L[nb][0][y][x - 1];
+      const double vp = L[nb][1][y][x], vpym = L[nb][1][y - 1][x];
+      const double wp = L[nb][2][y][x];
+      if (cact[r]) {
+        const int64_t p = plane(k) + coff[r];
+        const double su = combine(
+            tcx, tcy, c1, c2,
+            Lu(0, -1) * (Lu(0, -1) + u0), Lu(0, 1) * (u0 + Lu(0, 1)),
+            Lu(-1, 0) * (Lv(-1, 0) + Lv(-1, 1)), Lu(1, 0) * (v0 + Lv(0, 1)),
+            um1[r] * (wm1[r] + wm1x[r]), up * (w0 + Lw(0, 1)));
+        const double sv = combine(
+            tcx, tcy, c1, c2,
+            Lv(0, -1) * (Lu(0, -1) + Lu(1, -1)), Lv(0, 1) * (u0 + Lu(1, 0)),
+            Lv(-1, 0) * (Lv(-1, 0) + v0), Lv(1, 0) * (v0 + Lv(1, 0)),
+            vm1[r] * (wm1[r] + wm1y[r]), vp * (w0 + Lw(1, 0)));
+        const double sw = combine(
+            tcx, tcy, c1, c2,
+            Lw(0, -1) * (Lu(0, -1) + upxm), Lw(0, 1) * (u0 + up),
+            Lw(-1, 0) * (Lv(-1, 0) + vpym), Lw(1, 0) * (v0 + vp),
+            wm1[r] * (wm1[r] + w0), wp * (w0 + wp));
+        __builtin_nontemporal_store(su, out[0] + p);
+        __builtin_nontemporal_store(sv, out[1] + p);
+        __builtin_nontemporal_store(sw, out[2] + p);
+      }
+      um1[r] = u0;
+      vm1[r] = v0;
+      wm1[r] = w0;
+      wm1x[r] = Lw(0, 1);
+      wm1y[r] = Lw(1, 0);
+    }
+  }
+}
+
+// ------------------------------------------------------------ direct kernel
 
 __global__ __launch_bounds__(256) void advect_kernel(AdvK a) {
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -48,34 +213,23 @@ __global__ __launch_bounds__(256) void advect_kernel(AdvK a) {
   for (int k = z0; k < z1; ++k, p += Z) {
     const double c1 = a.t1[k], c2 = a.t2[k];
     const double u0 = u[p], v0 = v[p], w0 = w[p];
-    {
-      const double pxm = u[p - X] * (u[p - X] + u0);
-      const double pxp = u[p + X] * (u0 + u[p + X]);
-      const double pym = u[p - Y] * (v[p - Y] + v[p - Y + X]);
-      const double pyp = u[p + Y] * (v0 + v[p + X]);
-      const double pzm = u[p - Z] * (w[p - Z] + w[p - Z + X]);
-      const double pzp = u[p + Z] * (w0 + w[p + X]);
-      a.su[p] = (tcx * (pxm - pxp) + tcy * (pym - pyp)) + (c1 * pzm - c2 * pzp);
-    }
-    {
-      const double pxm = v[p - X] * (u[p - X] + u[p - X + Y]);
-      const double pxp = v[p + X] * (u0 + u[p + Y]);
-      const double pym = v[p - Y] * (v[p - Y] + v0);
-      const double pyp = v[p + Y] * (v0 + v[p + Y]);
-      const double pzm = v[p - Z] * (w[p - Z] + w[p - Z + Y]);
-      const double pzp = v[p + Z] * (w0 + w[p + Y]);
-      a.sv[p] = (tcx * (pxm - pxp) + tcy * (pym - pyp)) + (c1 * pzm - c2 * pzp);
-    }
-    {
-      const double pxm = w[p - X] * (u[p - X] + u[p - X + Z]);
-      const double pxp = w[p + X] * (u0 + u[p + Z]);
-      const double pym = w[p - Y] * (v[p - Y] + v[p - Y + Z]);
-      const double pyp = w[p + Y] * (v0 + v[p + Z]);
-      const double pzm = w[p - Z] * (w[p - Z] + w0);
-      const double pzp = w[p + Z] * (w0 + w[p + Z]);
-      a.sw[p] = (tcx * (pxm - pxp) + tcy * (pym - pyp)) + (c1 * pzm - c2 * pzp);
-    }
+    a.su[p] = combine(tcx, tcy, c1, c2, u[p - X] * (u[p - X] + u0), u[p + X] * (u0 + u[p + X]),
+                      u[p - Y] * (v[p - Y] + v[p - Y + X]), u[p + Y] * (v0 + v[p + X]),
+                      u[p - Z] * (w[p - Z] + w[p - Z + X]), u[p + Z] * (w0 + w[p + X]));
+    a.sv[p] = combine(tcx, tcy, c1, c2, v[p - X] * (u[p - X] + u[p - X + Y]),
+                      v[p + X] * (u0 + u[p + Y]), v[p - Y] * (v[p - Y] + v0),
+                      v[p + Y] * (v0 + v[p + Y]), v[p - Z] * (w[p - Z] + w[p - Z + Y]),
+                      v[p + Z] * (w0 + w[p + Y]));
+    a.sw[p] = combine(tcx, tcy, c1, c2, w[p - X] * (u[p - X] + u[p - X + Z]),
+                      w[p + X] * (u0 + u[p + Z]), w[p - Y] * (v[p - Y] + v[p - Y + Z]),
+                      w[p + Y] * (v0 + v[p + Z]), w[p - Z] * (w[p - Z] + w0),
+                      w[p + Z] * (w0 + w[p + Z]));
   }
+}
+
+int env_int(const char* name) {
+  const char* v = getenv(name);
+  return v ? atoi(v) : 0;
 }
 
 }  // namespace
@@ -94,25 +248,46 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   const size_t bytes = (size_t)field_span(*g) * 8;
   const void* ins[3] = {u, v, w};
   void* outs[3] = {su, sv, sw};
-  for (int a = 0; a < 3; ++a) {
+  for (int q = 0; q < 3; ++q) {
     for (int b = 0; b < 3; ++b)
-      if (overlaps(outs[a], bytes, ins[b], bytes))
+      if (overlaps(outs[q], bytes, ins[b], bytes))
         return set_error(MS_EINVAL, "advect_source: an output aliases an input field");
-    for (int b = a + 1; b < 3; ++b)
-      if (overlaps(outs[a], bytes, outs[b], bytes))
+    for (int b = q + 1; b < 3; ++b)
+      if (overlaps(outs[q], bytes, outs[b], bytes))
         return set_error(MS_EINVAL, "advect_source: outputs overlap");
   }
-  if (g->ny > 4 * 65535) return set_error(MS_EUNSUPPORTED, "advect_source: ny too large");
   AdvK a{u, v, w, tzc1, tzc2, su, sv, sw, tcx, tcy, g->nx, g->ny, g->nz, 0, g->sy, g->sz};
-  const int tiles = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
-  int chunks = (4096 + tiles - 1) / tiles;
-  if (chunks > g->nz) chunks = g->nz;
-  a.zc = (g->nz + chunks - 1) / chunks;
-  chunks = (g->nz + a.zc - 1) / a.zc;
-  if (chunks > 65535) return set_error(MS_EUNSUPPORTED, "advect_source: nz too large");
-  const dim3 grid((g->nx + 63) / 64, (g->ny + 3) / 4, chunks);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(advect_kernel, grid, dim3(256), 0, s, a);
+  // MS_ADVECT_VARIANT=0 selects the direct kernel (a cross-check).
+  if (getenv("MS_ADVECT_VARIANT") && env_int("MS_ADVECT_VARIANT") == 0) {
+    if (g->ny > 4 * 65535) return set_error(MS_EUNSUPPORTED, "advect_source: ny too large");
+    const int tiles = ((g->nx + 63) / 64) * ((g->ny + 3) / 4);
+    int chunks = (4096 + tiles - 1) / tiles;
+    if (chunks > g->nz) chunks = g->nz;
+    a.zc = (g->nz + chunks - 1) / chunks;
+    chunks = (g->nz + a.zc - 1) / a.zc;
+    if (chunks > 65535) return set_error(MS_EUNSUPPORTED, "advect_source: nz too large");
+    const dim3 grid((g->nx + 63) / 64, (g->ny + 3) / 4, chunks);
+    hipLaunchKernelGGL(advect_kernel, grid, dim3(256), 0, s, a);
+    MS_LAUNCH_CHECK();
+    return MS_OK;
+  }
+  // Staged kernel: about two resident blocks per CU, each marching long z.
+  a.tiles_x = (g->nx + kAdvTX - 1) / kAdvTX;
+  a.tiles_y = (g->ny + kAdvTY - 1) / kAdvTY;
+  const int64_t tiles2d = (int64_t)a.tiles_x * a.tiles_y;
+  int zc = env_int("MS_ADVECT_ZC");
+  if (zc <= 0) {
+    int64_t chunks = (512 + tiles2d - 1) / tiles2d;
+    zc = (int)((g->nz + chunks - 1) / chunks);
+    if (zc < 4) zc = 4;
+  }
+  if (zc > g->nz) zc = g->nz;
+  const int64_t nb = tiles2d * ((g->nz + zc - 1) / zc);
+  if (nb > 0x7fffffffLL) return set_error(MS_EUNSUPPORTED, "advect_source: grid too large");
+  a.zc = zc;
+  a.nblocks = (int)nb;
+  hipLaunchKernelGGL(advect_staged_kernel, dim3(a.nblocks), dim3(kThreads), 0, s, a);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

@@ -11,6 +11,7 @@
 // being written).
 #include "ms_internal.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -230,8 +231,9 @@ int check_opts(const ms_solve_opts* o) {
     return set_error(MS_EINVAL, "jacobi_solve: rel_tol must be finite and >= 0");
   if (o->max_sweeps < 0) return set_error(MS_EINVAL, "jacobi_solve: max_sweeps < 0");
   if (o->check_every < 0) return set_error(MS_EINVAL, "jacobi_solve: check_every < 0");
-  if (o->temporal_block < 0 || o->temporal_block > 2)
-    return set_error(MS_EUNSUPPORTED, "jacobi_solve: temporal_block %d", o->temporal_block);
+  if (o->temporal_block < 0 || o->temporal_block > 1)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: temporal_block %d not available",
+                     o->temporal_block);
   if (o->precision == MS_SOLVE_F32_REFINED) {
     if (!(o->inner_eta > 0.0 && o->inner_eta < 1.0))
       return set_error(MS_EINVAL, "jacobi_solve: inner_eta must be in (0, 1)");
@@ -334,7 +336,7 @@ extern "C" void ms_solve_opts_default(ms_solve_opts* o) {
   o->max_sweeps = 10000000;
   o->precision = MS_SOLVE_F64;
   o->check_every = 0;
-  o->inner_eta = 1e-4;
+  o->inner_eta = 1e-5;
   o->max_outer = 20;
   o->max_inner = 5000000;
   o->stall_window = 256;
@@ -479,7 +481,9 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
     MS_LAUNCH_CHECK();
     int64_t cap = o.max_inner;
     if (o.max_sweeps - total < cap) cap = o.max_sweeps - total;
-    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, o.inner_eta, cap, 1,
+    // No more reduction than brings the outer residual to half the tolerance.
+    const double eta = std::max(o.inner_eta, 0.5 * o.rel_tol / rel);
+    hipLaunchKernelGGL(ctl_init_kernel, dim3(1), dim3(1), 0, s, ctl, eta, cap, 1,
                        o.stall_window, 0);
     MS_LAUNCH_CHECK();
     Ctl hc{};
