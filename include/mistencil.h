@@ -129,6 +129,17 @@ int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
                   const void* f, int64_t n, double* res_dev, void* work,
                   size_t work_bytes, void* stream);
 
+/* As jacobi_sweeps, with temporal_block sweeps fused into each pass over
+ * memory (1 or 2). With 2, each pass reads u_k and f once and writes
+ * u_{k+2}; the intermediate iterate stays on chip; an odd n ends with one
+ * single sweep. Per-cell arithmetic, results and res_dev are identical to
+ * jacobi_sweeps. u_n lands in u if the number of passes (n for 1,
+ * n/2 + n%2 for 2) is even, else in u_tmp. Same workspace. Async. */
+int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                     const void* f, int64_t n, int temporal_block,
+                     double* res_dev, void* work, size_t work_bytes,
+                     void* stream);
+
 /* ---- convergence-controlled solve ----------------------------------------
  * Relative-residual Jacobi solve of L(u) = f with Dirichlet halo.
  * res0 = ||r(u^0)||, u^0 = u with its interior zeroed (same halo, same f);
@@ -145,8 +156,8 @@ int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
  *   x += s * e in FP64. max_outer caps the outer steps, max_sweeps the total
  *   inner sweeps.
  * check_every: sweeps per device-side chunk between host checks (0 = auto).
- * temporal_block: sweeps fused per pass (0 or 1; larger values return
- *   MS_EUNSUPPORTED).
+ * temporal_block: sweeps fused per pass over memory: 0 or 1 = one,
+ *   2 = two (as jacobi_sweeps_tb; same iterates, same K).
  * use_graph: 1 = replay chunks as hipGraphs (default), 0 = plain launches.
  *
  * u: device, in: initial guess + Dirichlet halo; out: the answer u_K.
@@ -188,6 +199,37 @@ size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* o);
 int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
                  const double* f, void* work, size_t work_bytes,
                  double* hist_host, ms_solve_result* res, void* stream);
+
+/* ---- batched solves ---------------------------------------------------------
+ * Many independent instances of jacobi_solve, each with its own grid,
+ * solved in ONE persistent kernel launch (captured in a hipGraph). The
+ * device's resident blocks are split into teams, one per instance, sized by
+ * the instance's estimated work (cells x Jacobi sweeps to rel_tol from the
+ * spectral radius); a team runs its instance's whole solve with team
+ * barriers and never waits for another team. precision: MS_SOLVE_F64 or
+ * MS_SOLVE_F32_REFINED with the refinement rules of jacobi_solve (same
+ * per-cell arithmetic, same stopping rules; norms are summed per team, so an
+ * iteration count may differ from jacobi_solve's by one only when a norm
+ * sits within rounding of its threshold). Options used: rel_tol,
+ * max_sweeps, precision, inner_eta, max_outer, max_inner, stall_window
+ * (<= 1024). Instances must not overlap; n <= resident blocks of the device.
+ * res: host array of n results. Blocks until done. Returns MS_OK,
+ * MS_NOT_CONVERGED or MS_ENONFINITE (worst over instances), or an error;
+ * MS_EHIP if a team barrier exceeds its time limit (20 s). */
+typedef struct {
+  ms_grid grid;
+  double* x;       /* device: initial guess + Dirichlet halo; the answer on return */
+  const double* f; /* device right-hand side, may be NULL */
+} ms_instance;
+
+size_t jacobi_batched_workspace_bytes(int n, const ms_instance* inst,
+                                      const ms_solve_opts* o);
+int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
+                         void* work, size_t work_bytes, ms_solve_result* res,
+                         void* stream);
+/* The team sizes (n ints) and the grid size the batched solve would use. */
+int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
+                        int* team_sizes, int* grid_blocks);
 
 /* ---- advection source term ------------------------------------------------
  * The fused three-field Piacsek-Williams advection source term of Section

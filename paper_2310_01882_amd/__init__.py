@@ -72,6 +72,10 @@ class SolveResult(ctypes.Structure):
                 ("res_final", ctypes.c_double), ("rel_final", ctypes.c_double)]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("x", ctypes.c_void_p), ("f", ctypes.c_void_p)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
@@ -87,18 +91,25 @@ SIGNATURES = {
     "residual_norm": (_I, [ctypes.POINTER(Grid), _I, _P, _P, ctypes.POINTER(_D), _I, _P, _SZ, _P]),
     "jacobi_sweeps_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
     "jacobi_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "jacobi_sweeps_tb": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _P, _P, _SZ, _P]),
     "ms_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "jacobi_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts)]),
     "jacobi_solve": (_I, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts), _P, _P, _P, _SZ,
                           ctypes.POINTER(_D), ctypes.POINTER(SolveResult), _P]),
     "advect_source": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _D, _D, _P, _P, _P, _P]),
+    "jacobi_batched_workspace_bytes": (_SZ, [_I, ctypes.POINTER(Instance),
+                                             ctypes.POINTER(SolveOpts)]),
+    "jacobi_solve_batched": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts), _P,
+                                  _SZ, ctypes.POINTER(SolveResult), _P]),
+    "jacobi_batched_plan": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
 }
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it first (python -m paper_2310_01882_amd.build). "
+            f"{LIB_PATH} is missing: build it first (python paper_2310_01882_amd/build.py). "
             "There is no fallback implementation.")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
@@ -244,10 +255,11 @@ def jacobi_sweeps_workspace(u) -> torch.Tensor:
     return _workspace(lib.jacobi_sweeps_workspace_bytes(ctypes.byref(g)), u.device)
 
 
-def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):
-    """Exactly ``n`` Jacobi sweeps with ping-pong buffers; u_n ends in ``u``
-    if n is even, else in ``u_tmp`` (returned). ``res`` (float64 device
-    tensor of n + 1 entries, optional) receives ||r(u_k)||, k = 0..n."""
+def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None, temporal_block=1):
+    """Exactly ``n`` Jacobi sweeps with ping-pong buffers; returns the buffer
+    holding u_n (``u`` if the number of passes is even, else ``u_tmp``).
+    ``res`` (float64 device tensor of n + 1 entries, optional) receives
+    ||r(u_k)||, k = 0..n. ``temporal_block`` = 2 fuses two sweeps per pass."""
     _field_check(u, "u")
     _field_check(u_tmp, "u_tmp", u.dtype)
     _same_layout(u, u_tmp, "u/u_tmp")
@@ -259,9 +271,17 @@ def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):
     g = grid_of(u)
     if work is None:
         work = jacobi_sweeps_workspace(u)
-    _check(lib.jacobi_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f),
-                             int(n), _ptr(res), _ptr(work), work.numel(), _stream(stream)))
-    return u if n % 2 == 0 else u_tmp
+    tb = int(temporal_block)
+    if tb == 1:
+        _check(lib.jacobi_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f),
+                                 int(n), _ptr(res), _ptr(work), work.numel(), _stream(stream)))
+        passes = n
+    else:
+        _check(lib.jacobi_sweeps_tb(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp),
+                                    _ptr(f), int(n), tb, _ptr(res), _ptr(work), work.numel(),
+                                    _stream(stream)))
+        passes = n // 2 + n % 2
+    return u if passes % 2 == 0 else u_tmp
 
 
 @dataclass
@@ -335,3 +355,47 @@ def advect_source(u, v, w, tzc1, tzc2, tcx, tcy, su, sv, sw, stream=None):
     _check(lib.advect_source(ctypes.byref(g), _ptr(u), _ptr(v), _ptr(w), _ptr(tzc1), _ptr(tzc2),
                              float(tcx), float(tcy), _ptr(su), _ptr(sv), _ptr(sw), _stream(stream)))
     return su, sv, sw
+
+
+def _instances(xs, fs):
+    if len(xs) != len(fs):
+        raise ValueError("xs and fs must have the same length")
+    arr = (Instance * len(xs))()
+    for n, (x, f) in enumerate(zip(xs, fs)):
+        _field_check(x, f"xs[{n}]", torch.float64)
+        if f is not None:
+            _field_check(f, f"fs[{n}]", torch.float64)
+            _same_layout(x, f, f"xs[{n}]/fs[{n}]")
+        arr[n].grid = grid_of(x)
+        arr[n].x = x.data_ptr()
+        arr[n].f = f.data_ptr() if f is not None else None
+    return arr
+
+
+def batched_plan(xs, fs, **opts):
+    """(team sizes, grid blocks) the batched solve would use."""
+    arr = _instances(xs, fs)
+    o = solve_opts(**opts)
+    teams = (ctypes.c_int * len(xs))()
+    g = ctypes.c_int(0)
+    _check(lib.jacobi_batched_plan(len(xs), arr, ctypes.byref(o), teams, ctypes.byref(g)))
+    return list(teams), g.value
+
+
+def jacobi_solve_batched(xs, fs, work=None, stream=None, **opts):
+    """Solve every instance (xs[i]: float64 field, initial guess + halo; fs[i]:
+    right-hand side or None) in one persistent launch. Returns a SolveInfo per
+    instance; raises MsError on errors other than non-convergence."""
+    arr = _instances(xs, fs)
+    o = solve_opts(**opts)
+    if work is None:
+        nbytes = lib.jacobi_batched_workspace_bytes(len(xs), arr, ctypes.byref(o))
+        if nbytes == 0:
+            raise MsError(MS_EINVAL, last_error())
+        work = _workspace(nbytes, xs[0].device)
+    res = (SolveResult * len(xs))()
+    rc = lib.jacobi_solve_batched(len(xs), arr, ctypes.byref(o), _ptr(work), work.numel(), res,
+                                  _stream(stream))
+    _check(rc, allow=(MS_OK, MS_NOT_CONVERGED))
+    return [SolveInfo(r.status, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, [])
+            for r in res]

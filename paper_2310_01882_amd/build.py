@@ -1,6 +1,6 @@
 """Builds libmistencil.so (HIP, gfx950) in-tree.
 
-    python -m paper_2310_01882_amd.build
+    python paper_2310_01882_amd/build.py
 
 Every source under csrc/ is compiled to its own object in parallel, then
 linked into one shared library next to this file. Flags:

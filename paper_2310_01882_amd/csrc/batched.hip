@@ -1,0 +1,621 @@
+// Batched solves: many independent Poisson instances of uneven size in one
+// persistent launch.
+//
+// The grid holds G blocks, no more than can be resident at once. Blocks are
+// split into teams, one per instance, sized by the instance's estimated
+// work (cells x Jacobi sweeps to the tolerance, from the spectral radius)
+// and placed XCD by XCD so that a team shares an L2 where it can. A team
+// runs its instance's whole solve -- FP64 Jacobi, or FP32-storage Jacobi
+// inside FP64 iterative refinement -- with team barriers (a counter and a
+// generation word in device memory) between dependent steps; it never waits
+// for another team. Every block of a team sums the team's per-block partial
+// norms in the same fixed order, so all of them take the same decisions
+// without a broadcast. Waits are bounded: a barrier that does not complete
+// within a time limit raises the batch's error flag and every block leaves.
+//
+// The per-cell arithmetic is the single-instance path's (same operation
+// order), so each instance's iterates are those of jacobi_solve.
+#include "ms_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+namespace ms {
+namespace {
+
+constexpr int kBatchTX = 64, kBatchTY = kWavesY;  // 64 x 4 columns per tile
+constexpr int kStallMax = 1024;                    // longest stagnation window
+
+// Per-instance description and state (device memory).
+struct Inst {
+  int nx, ny, nz, pad0;
+  int64_t sy, sz;
+  double* x;          // FP64 iterate (caller's field)
+  const double* f;    // FP64 right-hand side or null
+  double* xb;         // second FP64 buffer (plain FP64 mode)
+  float* rhat;        // FP32 correction right-hand side
+  float* e0;          // FP32 correction iterates
+  float* e1;
+  double* part;       // team partials: [2][team]
+  unsigned* bar;      // [0] arrivals, [1] generation
+  int team0, team;    // first block of the team in team order, team size
+  int tiles_x, tiles_y;
+  // results
+  double res0, res_final, rel_final;
+  int64_t sweeps;
+  int outer, status;
+};
+
+struct BatchK {
+  Inst* inst;
+  const int* block_team;  // per block: instance index
+  const int* block_rank;  // per block: rank inside its team
+  int* error;             // batch-wide error flag
+  int ninst;
+  int mode;  // MS_SOLVE_F64 or MS_SOLVE_F32_REFINED
+  double tol, eta;
+  int64_t max_sweeps;
+  int max_outer, max_inner, stall;
+  int64_t spin_ticks;  // barrier time limit in s_memrealtime ticks
+};
+
+__device__ __forceinline__ int64_t off3(const Inst& q, int i, int j, int k) {
+  return (int64_t)(k + 1) * q.sz + (int64_t)(j + 1) * q.sy + (i + 1);
+}
+
+// Team barrier. Returns false if the batch failed (time limit or another
+// team's error); every thread of the block gets the same answer.
+__device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __threadfence();  // release this block's writes to the team
+    unsigned* cnt = q.bar;
+    unsigned* gen = q.bar + 1;
+    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned arrived = atomicAdd(cnt, 1u);
+    if (arrived == (unsigned)q.team - 1) {
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          ok = 0;
+          break;
+        }
+        if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > a.spin_ticks) {
+          atomicExch(a.error, 1);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __threadfence();  // acquire the team's writes
+    *s_flag = ok;
+  }
+  __syncthreads();
+  return *s_flag != 0;
+}
+
+// Sum of the team's partials in slot `slot` (fixed order, every block alike).
+__device__ double team_sum(const Inst& q, int slot, double* red) {
+  double t = 0.0;
+  const double* p = q.part + (int64_t)slot * q.team;
+  for (int r = threadIdx.x; r < q.team; r += blockDim.x)
+    t += __hip_atomic_load(p + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return block_sum(t, red);
+}
+
+// Broadcast of a block-wide value held by thread 0.
+__device__ double bcast(double v, double* cell) {
+  if (threadIdx.x == 0) *cell = v;
+  __syncthreads();
+  const double r = *cell;
+  __syncthreads();
+  return r;
+}
+
+// One sweep of the tiles owned by this block: dst = (S(src) - f) * fl(1/6)
+// on the interior; returns this thread's sum of r(src)^2 (FP64).
+template <typename T>
+__device__ double sweep_tiles(const Inst& q, int rank, const T* __restrict__ src,
+                              T* __restrict__ dst, const T* __restrict__ f) {
+  double acc = 0.0;
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  const int ntiles = q.tiles_x * q.tiles_y;
+  const T c6 = T(1) / T(6);
+  for (int tile = rank; tile < ntiles; tile += q.team) {
+    const int i = (tile % q.tiles_x) * kBatchTX + lane;
+    const int j = (tile / q.tiles_x) * kBatchTY + wy;
+    if (i >= q.nx || j >= q.ny) continue;
+    int64_t p = off3(q, i, j, 0);
+    T zm = src[p - q.sz], zc = src[p];
+    for (int k = 0; k < q.nz; ++k, p += q.sz) {
+      const T zp = src[p + q.sz];
+      const T xp = src[p + 1], xm = src[p - 1], yp = src[p + q.sy], ym = src[p - q.sy];
+      const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
+      const T fv = f ? f[p] : T(0);
+      dst[p] = f ? (s - fv) * c6 : s * c6;
+      const double sd = ((((double(xp) + double(xm)) + double(yp)) + double(ym)) + double(zp)) +
+                        double(zm);
+      const double lap = sd - double(zc) * 6.0;
+      const double r = f ? double(fv) - lap : -lap;
+      acc += r * r;
+      zm = zc;
+      zc = zp;
+    }
+  }
+  return acc;
+}
+
+// FP64 residual of x (zero_int: with its interior replaced by 0); with
+// rhat != null also writes rhat = fl32(r * inv_s) and zeroes e0's interior.
+__device__ double residual_tiles(const Inst& q, int rank, bool zero_int, float* rhat,
+                                 double inv_s) {
+  double acc = 0.0;
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  const int ntiles = q.tiles_x * q.tiles_y;
+  const double* __restrict__ x = q.x;
+  for (int tile = rank; tile < ntiles; tile += q.team) {
+    const int i = (tile % q.tiles_x) * kBatchTX + lane;
+    const int j = (tile / q.tiles_x) * kBatchTY + wy;
+    if (i >= q.nx || j >= q.ny) continue;
+    const bool xlo = i == 0, xhi = i == q.nx - 1, ylo = j == 0, yhi = j == q.ny - 1;
+    int64_t p = off3(q, i, j, 0);
+    for (int k = 0; k < q.nz; ++k, p += q.sz) {
+      double xp = x[p + 1], xm = x[p - 1], yp = x[p + q.sy], ym = x[p - q.sy];
+      double zp = x[p + q.sz], zm = x[p - q.sz], c = x[p];
+      if (zero_int) {  // keep halo values only
+        if (!xhi) xp = 0.0;
+        if (!xlo) xm = 0.0;
+        if (!yhi) yp = 0.0;
+        if (!ylo) ym = 0.0;
+        if (k != q.nz - 1) zp = 0.0;
+        if (k != 0) zm = 0.0;
+        c = 0.0;
+      }
+      const double s = ((((xp + xm) + yp) + ym) + zp) + zm;
+      const double lap = s - c * 6.0;
+      const double r = q.f ? q.f[p] - lap : -lap;
+      acc += r * r;
+      if (rhat) {
+        rhat[p] = (float)(r * inv_s);
+        q.e0[p] = 0.0f;
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ void update_tiles(const Inst& q, int rank, const float* __restrict__ e, double s) {
+  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+  const int ntiles = q.tiles_x * q.tiles_y;
+  for (int tile = rank; tile < ntiles; tile += q.team) {
+    const int i = (tile % q.tiles_x) * kBatchTX + lane;
+    const int j = (tile / q.tiles_x) * kBatchTY + wy;
+    if (i >= q.nx || j >= q.ny) continue;
+    int64_t p = off3(q, i, j, 0);
+    for (int k = 0; k < q.nz; ++k, p += q.sz) q.x[p] = q.x[p] + s * (double)e[p];
+  }
+}
+
+// Zero a whole field's storage (halo included), team-distributed.
+template <typename T>
+__device__ void zero_span(const Inst& q, int rank, T* p) {
+  const int64_t n = off3(q, q.nx, q.ny, q.nz) + 1;
+  for (int64_t t = (int64_t)rank * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)q.team * blockDim.x)
+    p[t] = T(0);
+}
+
+__device__ __forceinline__ double pow2_scale_dev(double norm, double ncells) {
+  const double m = norm / sqrt(ncells);
+  if (m == 0.0 || !isfinite(m)) return 1.0;
+  int e = 0;
+  frexp(m, &e);
+  return ldexp(1.0, e - 1);
+}
+
+// One inner (or plain) Jacobi solve on the team: sweeps from buffer 0 until
+// the stopping rule fires. Returns the accepted iterate K (its buffer is
+// K % 2) or -1 on failure. hist: LDS ring of the last kStallMax+1 norms.
+template <typename T>
+__device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
+                               double tol_rel, double ref_fixed, bool ref_from_first,
+                               int64_t cap, double* red, double* cell, double* hist,
+                               int* s_flag, int* status) {
+  double ref = ref_fixed;
+  for (int64_t j = 0;; ++j) {
+    const T* src = (j & 1) ? b1 : b0;
+    T* dst = (j & 1) ? b0 : b1;
+    const double mine = block_sum(sweep_tiles<T>(q, rank, src, dst, f), red);
+    if (threadIdx.x == 0) q.part[(int64_t)(j & 1) * q.team + rank] = mine;
+    if (!team_barrier(a, q, s_flag)) return -1;
+    const double norm = bcast(sqrt(team_sum(q, (int)(j & 1), red)), cell);
+    if (ref_from_first && j == 0) ref = norm;
+    if (threadIdx.x == 0) hist[j % (kStallMax + 1)] = norm;
+    __syncthreads();
+    if (!isfinite(norm)) {
+      *status = MS_ENONFINITE;
+      return j;
+    }
+    if (ref == 0.0 || norm / ref <= tol_rel) return j;
+    if (j >= cap) {
+      *status = MS_NOT_CONVERGED;
+      return j;
+    }
+    if (a.stall > 0 && j >= a.stall && norm >= hist[(j - a.stall) % (kStallMax + 1)]) return j;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
+  __shared__ double red[kWavesY];
+  __shared__ double cell;
+  __shared__ double hist[kStallMax + 1];
+  __shared__ int s_flag;
+  const int qi = a.block_team[blockIdx.x];
+  const int rank = a.block_rank[blockIdx.x];
+  Inst& q = a.inst[qi];
+  const double ncells = (double)q.nx * q.ny * q.nz;
+  int status = MS_OK;
+
+  // reference norm ||r(u^0)|| (interior zeroed)
+  {
+    const double mine = block_sum(residual_tiles(q, rank, true, nullptr, 0.0), red);
+    if (threadIdx.x == 0) q.part[rank] = mine;
+    if (a.mode == MS_SOLVE_F32_REFINED) {
+      zero_span<float>(q, rank, q.rhat);
+      zero_span<float>(q, rank, q.e0);
+      zero_span<float>(q, rank, q.e1);
+    }
+    if (!team_barrier(a, q, &s_flag)) return;
+  }
+  const double res0 = bcast(sqrt(team_sum(q, 0, red)), &cell);
+  if (!team_barrier(a, q, &s_flag)) return;  // partial slot 0 is reused below
+
+  if (a.mode == MS_SOLVE_F64) {
+    int64_t K = team_jacobi<double>(a, q, rank, q.x, q.xb, q.f, a.tol, res0, false,
+                                    a.max_sweeps, red, &cell, hist, &s_flag, &status);
+    if (K < 0) return;
+    // the answer is buffer K % 2; bring it into x
+    if (K & 1) {
+      const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+      const int ntiles = q.tiles_x * q.tiles_y;
+      for (int tile = rank; tile < ntiles; tile += q.team) {
+        const int i = (tile % q.tiles_x) * kBatchTX + lane;
+        const int j = (tile / q.tiles_x) * kBatchTY + wy;
+        if (i >= q.nx || j >= q.ny) continue;
+        int64_t p = off3(q, i, j, 0);
+        for (int k = 0; k < q.nz; ++k, p += q.sz) q.x[p] = q.xb[p];
+      }
+    }
+    if (rank == 0 && threadIdx.x == 0) {
+      const double last = hist[K % (kStallMax + 1)];
+      q.res0 = res0;
+      q.res_final = last;
+      q.rel_final = res0 > 0.0 ? last / res0 : 0.0;
+      q.sweeps = K;
+      q.outer = 0;
+      q.status = status;
+    }
+    return;
+  }
+
+  int64_t total = 0;
+  int outer = 0;
+  double nr = 0.0, rel = 0.0;
+  for (;;) {
+    const double mine = block_sum(residual_tiles(q, rank, false, nullptr, 0.0), red);
+    if (threadIdx.x == 0) q.part[rank] = mine;
+    if (!team_barrier(a, q, &s_flag)) return;
+    nr = bcast(sqrt(team_sum(q, 0, red)), &cell);
+    rel = res0 > 0.0 ? nr / res0 : 0.0;
+    if (!team_barrier(a, q, &s_flag)) return;  // slot 0 is rewritten below
+    if (!isfinite(nr)) {
+      status = MS_ENONFINITE;
+      break;
+    }
+    if (res0 == 0.0 || rel <= a.tol) break;
+    if (outer == a.max_outer || total >= a.max_sweeps) {
+      status = MS_NOT_CONVERGED;
+      break;
+    }
+    const double sc = pow2_scale_dev(nr, ncells);
+    residual_tiles(q, rank, false, q.rhat, 1.0 / sc);
+    if (!team_barrier(a, q, &s_flag)) return;
+    const double eta = fmax(a.eta, 0.5 * a.tol / rel);
+    int64_t cap = a.max_inner;
+    if (a.max_sweeps - total < cap) cap = a.max_sweeps - total;
+    int inner_status = MS_OK;
+    const int64_t K = team_jacobi<float>(a, q, rank, q.e0, q.e1, q.rhat, eta, 0.0, true, cap,
+                                         red, &cell, hist, &s_flag, &inner_status);
+    if (K < 0) return;
+    if (inner_status == MS_ENONFINITE) {
+      status = MS_ENONFINITE;
+      break;
+    }
+    update_tiles(q, rank, (K & 1) ? q.e1 : q.e0, sc);
+    if (!team_barrier(a, q, &s_flag)) return;
+    total += K;
+    ++outer;
+  }
+  if (rank == 0 && threadIdx.x == 0) {
+    q.res0 = res0;
+    q.res_final = nr;
+    q.rel_final = rel;
+    q.sweeps = total;
+    q.outer = outer;
+    q.status = status;
+  }
+}
+
+// ------------------------------------------------------------------ host
+
+struct Plan {
+  int G = 0;
+  std::vector<int> team, first, block_team, block_rank;
+  size_t bytes = 0;
+};
+
+double est_work(const ms_grid& g, double tol) {
+  const double pi = 3.14159265358979323846;
+  const double rho =
+      (std::cos(pi / (g.nx + 1)) + std::cos(pi / (g.ny + 1)) + std::cos(pi / (g.nz + 1))) / 3.0;
+  const double k = std::log(std::max(tol, 1e-300)) / std::log(std::min(rho, 1.0 - 1e-16));
+  return (double)g.nx * g.ny * g.nz * std::max(k, 1.0);
+}
+
+int tiles_of(const ms_grid& g) {
+  return ((g.nx + kBatchTX - 1) / kBatchTX) * ((g.ny + kBatchTY - 1) / kBatchTY);
+}
+
+// Splits G blocks into teams proportional to estimated work (at least one
+// block, at most one per tile column), then lays the teams out XCD by XCD.
+void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) w[i] = est_work(inst[i].grid, tol);
+  const double W = std::accumulate(w.begin(), w.end(), 0.0);
+  P.team.assign(n, 1);
+  int used = n;
+  std::vector<double> want(n);
+  for (int i = 0; i < n; ++i) want[i] = G * w[i] / W;
+  // largest deficit first, one block at a time
+  while (used < G) {
+    int best = -1;
+    double bd = 0.0;
+    for (int i = 0; i < n; ++i) {
+      if (P.team[i] >= tiles_of(inst[i].grid)) continue;
+      const double d = want[i] - P.team[i];
+      if (best < 0 || d > bd) {
+        best = i;
+        bd = d;
+      }
+    }
+    if (best < 0 || bd <= 0.0) break;
+    ++P.team[best];
+    ++used;
+  }
+  P.G = used;
+  // block ids in XCD-major order: x, x+8, x+16, ... for x = 0..7
+  std::vector<int> order;
+  order.reserve(P.G);
+  for (int x = 0; x < 8; ++x)
+    for (int b = x; b < P.G; b += 8) order.push_back(b);
+  P.block_team.assign(P.G, 0);
+  P.block_rank.assign(P.G, 0);
+  P.first.assign(n, 0);
+  // biggest teams first so they stay within as few XCDs as possible
+  std::vector<int> idx(n);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return P.team[x] > P.team[y]; });
+  int pos = 0;
+  for (int i : idx) {
+    P.first[i] = pos;
+    for (int r = 0; r < P.team[i]; ++r, ++pos) {
+      P.block_team[order[pos]] = i;
+      P.block_rank[order[pos]] = r;
+    }
+  }
+}
+
+int resident_blocks() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel, kThreads, 0) !=
+      hipSuccess)
+    return 0;
+  return cus * per;
+}
+
+size_t inst_bytes(const ms_grid& g, int mode, int team) {
+  const size_t span = (size_t)field_span(g);
+  size_t t = align_up(2 * (size_t)team * sizeof(double), 256) + 256;  // partials + barrier
+  if (mode == MS_SOLVE_F64) t += align_up(span * 8, 256);
+  else t += 3 * align_up(span * 4, 256);
+  return t;
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+namespace {
+
+int check_batch(int n, const ms_instance* inst, const ms_solve_opts* o) {
+  if (n < 1 || !inst) return set_error(MS_EINVAL, "jacobi_solve_batched: no instances");
+  if (!o) return set_error(MS_EINVAL, "jacobi_solve_batched: opts is NULL");
+  if (o->precision != MS_SOLVE_F64 && o->precision != MS_SOLVE_F32_REFINED)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: precision %d", o->precision);
+  if (!(o->rel_tol >= 0.0) || !std::isfinite(o->rel_tol))
+    return set_error(MS_EINVAL, "jacobi_solve_batched: rel_tol must be finite and >= 0");
+  if (o->stall_window < 0 || o->stall_window > kStallMax)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: stall_window above %d", kStallMax);
+  if (o->precision == MS_SOLVE_F32_REFINED &&
+      (!(o->inner_eta > 0.0 && o->inner_eta < 1.0) || o->max_inner < 1 || o->max_outer < 0))
+    return set_error(MS_EINVAL, "jacobi_solve_batched: bad refinement options");
+  for (int i = 0; i < n; ++i) {
+    if (int rc = check_grid(&inst[i].grid, "jacobi_solve_batched")) return rc;
+    if (!inst[i].x) return set_error(MS_EINVAL, "jacobi_solve_batched: instance %d has no x", i);
+    const size_t b = (size_t)field_span(inst[i].grid) * 8;
+    if (inst[i].f && overlaps(inst[i].f, b, inst[i].x, b))
+      return set_error(MS_EINVAL, "jacobi_solve_batched: instance %d: f overlaps x", i);
+    for (int j = 0; j < i; ++j) {
+      const size_t bj = (size_t)field_span(inst[j].grid) * 8;
+      if (overlaps(inst[i].x, b, inst[j].x, bj))
+        return set_error(MS_EINVAL, "jacobi_solve_batched: instances %d and %d overlap", j, i);
+    }
+  }
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t jacobi_batched_workspace_bytes(int n, const ms_instance* inst,
+                                                 const ms_solve_opts* o) {
+  if (check_batch(n, inst, o)) return 0;
+  const int G = resident_blocks();
+  if (G <= 0) return 0;
+  Plan P;
+  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
+  size_t t = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
+  for (int i = 0; i < n; ++i) t += inst_bytes(inst[i].grid, o->precision, P.team[i]);
+  return t;
+}
+
+extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
+                                    void* work, size_t work_bytes, ms_solve_result* res,
+                                    void* stream) {
+  clear_error();
+  if (int rc = check_batch(n, inst, o)) return rc;
+  if (!res) return set_error(MS_EINVAL, "jacobi_solve_batched: res is NULL");
+  const int G = resident_blocks();
+  if (G <= 0) return set_error(MS_EHIP, "jacobi_solve_batched: occupancy query failed");
+  if (G < n)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: %d instances need %d resident "
+                     "blocks, the device holds %d", n, n, G);
+  Plan P;
+  plan_teams(n, inst, o->rel_tol, G, P);
+  size_t need = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
+  for (int i = 0; i < n; ++i) need += inst_bytes(inst[i].grid, o->precision, P.team[i]);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "jacobi_solve_batched: workspace needs %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws{static_cast<char*>(work), work_bytes};
+  Inst* dinst = ws.take<Inst>(n);
+  int* dmap = ws.take<int>(2 * (size_t)P.G);
+  int* derr = ws.take<int>(64);
+  std::vector<Inst> h(n);
+  for (int i = 0; i < n; ++i) {
+    const ms_grid& g = inst[i].grid;
+    Inst& q = h[i];
+    q = Inst{};
+    q.nx = g.nx; q.ny = g.ny; q.nz = g.nz;
+    q.sy = g.sy; q.sz = g.sz;
+    q.x = inst[i].x;
+    q.f = inst[i].f;
+    q.team0 = P.first[i];
+    q.team = P.team[i];
+    q.tiles_x = (g.nx + kBatchTX - 1) / kBatchTX;
+    q.tiles_y = (g.ny + kBatchTY - 1) / kBatchTY;
+    q.part = ws.take<double>(2 * (size_t)q.team);
+    q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
+    const size_t span = (size_t)field_span(g);
+    if (o->precision == MS_SOLVE_F64) {
+      q.xb = ws.take<double>(span);
+    } else {
+      q.rhat = ws.take<float>(span);
+      q.e0 = ws.take<float>(span);
+      q.e1 = ws.take<float>(span);
+    }
+    if (!q.part || !q.bar || (o->precision == MS_SOLVE_F64 ? !q.xb : !q.e1))
+      return set_error(MS_EWORKSPACE, "jacobi_solve_batched: workspace carve failed");
+  }
+  std::vector<int> map(2 * (size_t)P.G);
+  std::copy(P.block_team.begin(), P.block_team.end(), map.begin());
+  std::copy(P.block_rank.begin(), P.block_rank.end(), map.begin() + P.G);
+  MS_HIP_TRY(hipMemcpyAsync(dinst, h.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s));
+  MS_HIP_TRY(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, s));
+  MS_HIP_TRY(hipMemsetAsync(derr, 0, 256, s));
+  for (int i = 0; i < n; ++i) MS_HIP_TRY(hipMemsetAsync(h[i].bar, 0, 256, s));
+  // FP64 mode: the second buffer carries the same Dirichlet halo
+  if (o->precision == MS_SOLVE_F64)
+    for (int i = 0; i < n; ++i)
+      MS_HIP_TRY(hipMemcpyAsync(h[i].xb, h[i].x, (size_t)field_span(inst[i].grid) * 8,
+                                hipMemcpyDeviceToDevice, s));
+  BatchK a{};
+  a.inst = dinst;
+  a.block_team = dmap;
+  a.block_rank = dmap + P.G;
+  a.error = derr;
+  a.ninst = n;
+  a.mode = o->precision;
+  a.tol = o->rel_tol;
+  a.eta = o->inner_eta;
+  a.max_sweeps = o->max_sweeps;
+  a.max_outer = o->max_outer;
+  a.max_inner = o->max_inner;
+  a.stall = o->stall_window;
+  a.spin_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz real-time clock
+  // One persistent launch, replayed from a captured graph.
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  MS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(batched_kernel, dim3(P.G), dim3(kThreads), 0, cap, a);
+    e = hipStreamEndCapture(cap, &graph);
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cap);
+  if (e != hipSuccess)
+    return set_error(MS_EHIP, "jacobi_solve_batched: graph capture failed: %s",
+                     hipGetErrorString(e));
+  e = hipGraphLaunch(exec, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess)
+    return set_error(MS_EHIP, "jacobi_solve_batched: %s", hipGetErrorString(e));
+  int herr = 0;
+  MS_HIP_TRY(hipMemcpy(&herr, derr, sizeof(int), hipMemcpyDeviceToHost));
+  MS_HIP_TRY(hipMemcpy(h.data(), dinst, sizeof(Inst) * n, hipMemcpyDeviceToHost));
+  if (herr) return set_error(MS_EHIP, "jacobi_solve_batched: a team barrier timed out");
+  int worst = MS_OK;
+  for (int i = 0; i < n; ++i) {
+    res[i].sweeps = h[i].sweeps;
+    res[i].outer_iters = h[i].outer;
+    res[i].status = h[i].status;
+    res[i].res0 = h[i].res0;
+    res[i].res_final = h[i].res_final;
+    res[i].rel_final = h[i].rel_final;
+    if (h[i].status == MS_ENONFINITE) worst = MS_ENONFINITE;
+    else if (h[i].status == MS_NOT_CONVERGED && worst == MS_OK) worst = MS_NOT_CONVERGED;
+  }
+  if (worst == MS_ENONFINITE) return set_error(worst, "jacobi_solve_batched: non-finite norm");
+  if (worst == MS_NOT_CONVERGED)
+    return set_error(worst, "jacobi_solve_batched: an instance did not converge");
+  return MS_OK;
+}
+
+extern "C" int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
+                                   int* team_sizes, int* grid_blocks) {
+  clear_error();
+  if (int rc = check_batch(n, inst, o)) return rc;
+  const int G = resident_blocks();
+  if (G <= 0) return set_error(MS_EHIP, "jacobi_batched_plan: occupancy query failed");
+  Plan P;
+  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
+  if (team_sizes) std::copy(P.team.begin(), P.team.end(), team_sizes);
+  if (grid_blocks) *grid_blocks = P.G;
+  return MS_OK;
+}

@@ -33,7 +33,7 @@ template <typename T>
 struct SweepK {
   T* buf[3];
   const T* f;
-  double* partials;  // [2][kMaxBlocks]
+  double* partials;  // [kPartialSlots][kMaxBlocks]
   double* hist;
   Ctl* ctl;
   int64_t k_off;
@@ -74,7 +74,7 @@ __device__ __forceinline__ bool sweep_prologue(const SweepK<T>& a, int64_t k, do
                                                int* s_done) {
   if (WRITE && blockIdx.x == 0 && k >= 1 && (a.hist || a.ctl)) {
     if (!a.ctl || a.ctl->done == RUNNING) {
-      const double t = sum_partials(a.partials + ((k - 1) & 1) * (int64_t)kMaxBlocks,
+      const double t = sum_partials(a.partials + ((k - 1) & 3) * (int64_t)kMaxBlocks,
                                     a.nblocks, red);
       if (threadIdx.x == 0) judge(a.ctl, a.hist, k - 1, sqrt(t));
     }
@@ -310,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void sweep_rt_kernel(SweepK<T> a) {
   }
 
   const double tot = block_sum(acc, red);
-  if (threadIdx.x == 0) a.partials[(int64_t)(k & 1) * kMaxBlocks + blockIdx.x] = tot;
+  if (threadIdx.x == 0) a.partials[(int64_t)(k & 3) * kMaxBlocks + blockIdx.x] = tot;
 }
 
 // --------------------------------------------------- LDS-tiled kernel
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void sweep_kernel(SweepK<T> a) {
   const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
   const int i = i0 + lane;
 
-  const int slot = WRITE ? (int)(k & 1) : a.slot;
+  const int slot = WRITE ? (int)(k & 3) : a.slot;
   const T* __restrict__ src = WRITE ? a.buf[k % a.nbuf] : a.buf[0];
   T* __restrict__ dst = WRITE ? a.buf[(k + 1) % a.nbuf] : nullptr;
   const T* __restrict__ f = a.f;
@@ -463,6 +463,230 @@ __global__ void finalize_kernel(const double* partials, int nb, double* out, Ctl
   }
 }
 
+// ------------------------------------------- two-sweep temporal blocking
+
+// A block owns a 64 x 8 output tile and marches a z-chunk, applying two
+// sweeps per pass. Stage A computes u_{k+1} on the tile plus a one-cell ring
+// (66 x 10) from u_k staged in LDS with a two-cell ring (68 x 12); stage B
+// computes u_{k+2} on the tile from u_{k+1} staged in LDS. Stage A runs one
+// level ahead of stage B. Both stages use the single-sweep arithmetic, so
+// the results are bit-identical to two plain sweeps; ring cells that are
+// Dirichlet halo keep their value, as a plain sweep never writes the halo.
+// Four LDS buffers per stage leave one barrier per level. Stage A adds the
+// residual of u_k on the tile, stage B the residual of u_{k+1}.
+constexpr int kTbX = 64, kTbY = 8;
+constexpr int kTbAX = kTbX + 4, kTbAY = kTbY + 4;  // u_k region (68 x 12)
+constexpr int kTbBX = kTbX + 2, kTbBY = kTbY + 2;  // u_{k+1} region (66 x 10)
+constexpr int kTbACells = kTbAX * kTbAY;           // 816 -> 4 per thread
+constexpr int kTbBCells = kTbBX * kTbBY;           // 660 -> 3 per thread
+constexpr int kTbOut = kTbX * kTbY;                // 512 -> 2 per thread
+
+template <typename T, bool HAS_F>
+__global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
+  __shared__ T A[4][kTbAY][kTbAX];
+  __shared__ T B[4][kTbBY][kTbBX];
+  __shared__ double red[kWavesY];
+  __shared__ int s_done;
+
+  const int64_t L = (a.ctl ? a.ctl->base : 0) + a.k_off;
+  const int64_t k0 = 2 * L;  // iterate read by this launch
+  // Block 0 finalises the two iterates of the previous launch, in order.
+  if (blockIdx.x == 0 && L >= 1 && (a.hist || a.ctl)) {
+#pragma unroll
+    for (int d = 2; d >= 1; --d) {
+      if (!a.ctl || a.ctl->done == RUNNING) {
+        const double t = sum_partials(a.partials + ((k0 - d) & 3) * (int64_t)kMaxBlocks,
+                                      a.nblocks, red);
+        if (threadIdx.x == 0) judge(a.ctl, a.hist, k0 - d, sqrt(t));
+        __syncthreads();
+      }
+    }
+  }
+  if (a.ctl) {
+    if (threadIdx.x == 0) s_done = a.ctl->done;
+    __syncthreads();
+    if (s_done != RUNNING) return;
+  }
+
+  const int tile = xcd_tile(blockIdx.x, a.nblocks);
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int tzi = rest / a.tiles_y;
+  const int i0 = txi * kTbX, j0 = tyi * kTbY;
+  const int z0 = tzi * a.zc;
+  const int z1 = min(z0 + a.zc, a.nz);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int64_t sy = a.sy, sz = a.sz;
+  const T* __restrict__ src = a.buf[L % a.nbuf];
+  T* __restrict__ dst = a.buf[(L + 1) % a.nbuf];
+  const T* __restrict__ f = a.f;
+  const int t = threadIdx.x;
+  auto off = [&](int i, int j, int k) {
+    return (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
+  };
+  auto exists = [&](int i, int j, int k) {
+    return i >= -1 && i <= nx && j >= -1 && j <= ny && k >= -1 && k <= nz;
+  };
+  auto abuf = [&](int k) { return (k - z0 + 8) & 3; };
+
+  // u_k region cells owned by this thread (LDS staging): c = t + 256 q.
+  constexpr int QA = (kTbACells + kThreads - 1) / kThreads;
+  auto a_cell = [&](int q, int& ra, int& ca) {
+    const int c = t + q * kThreads;
+    ra = c / kTbAX;
+    ca = c % kTbAX;
+    return c < kTbACells;
+  };
+  auto load_a = [&](T (&r)[QA], int k) {
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      int ra, ca;
+      const bool own = a_cell(q, ra, ca);
+      const int i = i0 - 2 + ca, j = j0 - 2 + ra;
+      r[q] = (own && exists(i, j, k)) ? src[off(i, j, k)] : T(0);
+    }
+  };
+  auto store_a = [&](const T (&r)[QA], int k) {
+    const int b = abuf(k);
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+      int ra, ca;
+      if (a_cell(q, ra, ca)) A[b][ra][ca] = r[q];
+    }
+  };
+
+  // Prologue: levels z0-2 .. z0 into LDS, z0+1 into registers.
+  {
+    T r[QA];
+    for (int k = z0 - 2; k <= z0; ++k) {
+      if (k < -1) continue;
+      load_a(r, k);
+      store_a(r, k);
+    }
+  }
+  T pre[QA];
+  const int klast = min(z1 + 1, nz);  // last u_k level stage A needs
+  load_a(pre, z0 + 1);                // z0 + 1 <= nz always
+  __syncthreads();
+
+  double acc_a = 0.0, acc_b = 0.0;
+  const T c6 = C6<T>::v();
+  constexpr int QB = (kTbBCells + kThreads - 1) / kThreads;
+  constexpr int QO = kTbOut / kThreads;
+  // Loop-invariant cell bookkeeping. Stage A: cells of the 66 x 10 region.
+  int arb[QB], acb[QB];
+  int64_t aoff[QB];
+  bool aown[QB], ain[QB], atile[QB];
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int c = t + q * kThreads;
+    aown[q] = c < kTbBCells;
+    arb[q] = c / kTbBX;
+    acb[q] = c % kTbBX;
+    const int i = i0 - 1 + acb[q], j = j0 - 1 + arb[q];
+    ain[q] = aown[q] && i >= 0 && i < nx && j >= 0 && j < ny;
+    atile[q] = arb[q] >= 1 && arb[q] <= kTbY && acb[q] >= 1 && acb[q] <= kTbX;
+    aoff[q] = (int64_t)(j + 1) * sy + (i + 1);
+  }
+  // Stage B: cells of the 64 x 8 tile.
+  int brt[QO], bct[QO];
+  int64_t boff[QO];
+  bool bin[QO];
+#pragma unroll
+  for (int q = 0; q < QO; ++q) {
+    const int c = t + q * kThreads;
+    brt[q] = c / kTbX;
+    bct[q] = c % kTbX;
+    const int i = i0 + bct[q], j = j0 + brt[q];
+    bin[q] = i < nx && j < ny;
+    boff[q] = (int64_t)(j + 1) * sy + (i + 1);
+  }
+  auto zin = [&](int z) { return z >= 0 && z < nz; };
+  // f for stage A at level z and for stage B at level z-1, prefetched one
+  // step ahead.
+  auto ld_fa = [&](T (&d)[QB], int z) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q)
+      d[q] = (HAS_F && ain[q] && zin(z)) ? f[(int64_t)(z + 1) * sz + aoff[q]] : T(0);
+  };
+  auto ld_fb = [&](T (&d)[QO], int z) {
+#pragma unroll
+    for (int q = 0; q < QO; ++q)
+      d[q] = (HAS_F && bin[q] && z >= z0 && z < z1) ? f[(int64_t)(z + 1) * sz + boff[q]] : T(0);
+  };
+  T fa[QB], fb[QO];
+  ld_fa(fa, z0 - 1);
+#pragma unroll
+  for (int q = 0; q < QO; ++q) fb[q] = T(0);
+
+  for (int z = z0 - 1; z <= z1; ++z) {
+    // 1. publish level z+2 of u_k (read from step z+1 on), prefetch z+3
+    if (z + 2 <= klast) {
+      store_a(pre, z + 2);
+      if (z + 3 <= klast) load_a(pre, z + 3);
+    }
+    T fa_n[QB], fb_n[QO];
+    ld_fa(fa_n, z + 1);
+    ld_fb(fb_n, z);
+    // 2. stage A at level z: u_{k+1} on the 66 x 10 region
+    {
+      const int bm = abuf(z - 1), bc = abuf(z), bp = abuf(z + 1);
+      const bool zz = zin(z);
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        if (!aown[q]) continue;
+        const int ra = arb[q] + 1, ca = acb[q] + 1;
+        const T uc = A[bc][ra][ca];
+        T v = uc;  // halo cells keep their Dirichlet value
+        if (ain[q] && zz) {
+          const T xp = A[bc][ra][ca + 1], xm = A[bc][ra][ca - 1];
+          const T yp = A[bc][ra + 1][ca], ym = A[bc][ra - 1][ca];
+          const T zp = A[bp][ra][ca], zm = A[bm][ra][ca];
+          const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
+          v = HAS_F ? (s - fa[q]) * c6 : s * c6;
+          if (atile[q] && z >= z0 && z < z1) {
+            const double res = cell_residual(xp, xm, yp, ym, zp, zm, uc, fa[q], HAS_F);
+            acc_a += res * res;
+          }
+        }
+        B[bc][arb[q]][acb[q]] = v;
+      }
+    }
+    __syncthreads();
+    // 3. stage B at level z-1: u_{k+2} on the tile
+    const int zb = z - 1;
+    if (zb >= z0 && zb < z1) {
+      const int bm = abuf(zb - 1), bc = abuf(zb), bp = abuf(zb + 1);
+#pragma unroll
+      for (int q = 0; q < QO; ++q) {
+        if (!bin[q]) continue;
+        const int rb = brt[q] + 1, cb = bct[q] + 1;
+        const T uc = B[bc][rb][cb];
+        const T xp = B[bc][rb][cb + 1], xm = B[bc][rb][cb - 1];
+        const T yp = B[bc][rb + 1][cb], ym = B[bc][rb - 1][cb];
+        const T zp = B[bp][rb][cb], zm = B[bm][rb][cb];
+        const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
+        const T v = HAS_F ? (s - fb[q]) * c6 : s * c6;
+        __builtin_nontemporal_store(v, dst + (int64_t)(zb + 1) * sz + boff[q]);
+        const double res = cell_residual(xp, xm, yp, ym, zp, zm, uc, fb[q], HAS_F);
+        acc_b += res * res;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) fa[q] = fa_n[q];
+#pragma unroll
+    for (int q = 0; q < QO; ++q) fb[q] = fb_n[q];
+  }
+
+  const double ta = block_sum(acc_a, red);
+  const double tb = block_sum(acc_b, red);
+  if (threadIdx.x == 0) {
+    a.partials[(int64_t)(k0 & 3) * kMaxBlocks + blockIdx.x] = ta;
+    a.partials[(int64_t)((k0 + 1) & 3) * kMaxBlocks + blockIdx.x] = tb;
+  }
+}
+
 template <typename T, bool HAS_F, bool WRITE, bool ZERO_INT>
 int launch_lds(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
   const dim3 grid(geo.nblocks), block(kThreads);
@@ -567,6 +791,60 @@ int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
 }
 
 int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
+
+SweepGeom tb2_geom(const ms_grid& g) {
+  SweepGeom s{};
+  s.variant = kVariantLds;
+  s.vec = 1;
+  s.wx = 1;
+  s.rows = 2;
+  s.tiles_x = (g.nx + kTbX - 1) / kTbX;
+  s.tiles_y = (g.ny + kTbY - 1) / kTbY;
+  const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
+  // about two resident blocks per CU, long z marches (>= 8 levels);
+  // MS_TB_BLOCKS overrides the target for tuning
+  const char* ev = getenv("MS_TB_BLOCKS");
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 512;
+  int64_t chunks = (want + tiles2d - 1) / tiles2d;
+  int zc = (int)((g.nz + chunks - 1) / chunks);
+  if (zc < 8) zc = 8;
+  if (zc > g.nz) zc = g.nz;
+  while (tiles2d * ((g.nz + zc - 1) / zc) > kMaxBlocks && zc < g.nz) zc *= 2;
+  if (zc > g.nz) zc = g.nz;
+  s.zc = zc;
+  s.chunks_z = (g.nz + zc - 1) / zc;
+  const int64_t nb = tiles2d * s.chunks_z;
+  s.nblocks = nb > kMaxBlocks ? kMaxBlocks + 1 : (int)nb;
+  return s;
+}
+
+int tb2_blocks(const ms_grid& g) { return tb2_geom(g).nblocks; }
+
+int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
+                     const void* f, double* partials, double* hist, Ctl* ctl, int64_t k_off,
+                     hipStream_t s) {
+  const SweepGeom geo = tb2_geom(g);
+  if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
+    return set_error(MS_EUNSUPPORTED, "two-sweep geometry with %d blocks", geo.nblocks);
+  const dim3 grid(geo.nblocks), block(kThreads);
+  if (dtype == MS_F64) {
+    auto a = make_args<double>(g, geo);
+    for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<double*>(bufs[q]);
+    a.f = static_cast<const double*>(f);
+    a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
+    if (f) hipLaunchKernelGGL((sweep_tb2_kernel<double, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_tb2_kernel<double, false>), grid, block, 0, s, a);
+  } else {
+    auto a = make_args<float>(g, geo);
+    for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<float*>(bufs[q]);
+    a.f = static_cast<const float*>(f);
+    a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
+    if (f) hipLaunchKernelGGL((sweep_tb2_kernel<float, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((sweep_tb2_kernel<float, false>), grid, block, 0, s, a);
+  }
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
 
 int launch_finalize(const double* partials, int slot, int nblocks, double* out_norm, Ctl* ctl,
                     double* hist, int64_t k, hipStream_t s) {

@@ -183,9 +183,21 @@ struct Workspace {
 };
 
 // Sweeps (FP64 or FP32 storage) -------------------------------------------
+// One sweep per launch: launch index base + k_off = iterate index k; reads
+// bufs[k % nbuf], writes bufs[(k + 1) % nbuf].
 int launch_sweep(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
                  const void* f, double* partials, double* hist, Ctl* ctl,
                  int64_t k_off, const SweepGeom& geo, hipStream_t s);
+
+// Two fused sweeps per launch (temporal blocking): launch index L = base +
+// k_off covers iterates 2L (read from bufs[L % nbuf]) and 2L + 1 (never
+// stored) and writes u_{2L+2} to bufs[(L + 1) % nbuf]; it adds the norms of
+// both iterates and judges 2L - 2 and 2L - 1.
+int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
+                     const void* f, double* partials, double* hist, Ctl* ctl,
+                     int64_t k_off, hipStream_t s);
+// Blocks of the two-sweep kernel (for finalising its last partials).
+int tb2_blocks(const ms_grid& g);
 
 // Standalone residual: per-block partials of sum r^2 into partials[slot];
 // zero_interior evaluates u with its interior replaced by 0. It launches
@@ -194,8 +206,11 @@ int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
                     bool zero_interior, double* partials, int slot, hipStream_t s);
 int residual_blocks(const ms_grid& g);
 
-// Partials table: two slots of kMaxBlocks doubles.
-constexpr size_t kPartialsBytes = 2 * (size_t)kMaxBlocks * sizeof(double);
+// Partials table: four slots of kMaxBlocks doubles; iterate k's partials go
+// to slot k & 3 (a two-sweep launch fills two slots, and block 0 of the next
+// launch still reads the previous two).
+constexpr int kPartialSlots = 4;
+constexpr size_t kPartialsBytes = kPartialSlots * (size_t)kMaxBlocks * sizeof(double);
 
 // One-block finalisation: norm = sqrt(sum partials[slot]); writes *out_norm
 // (if not null) and judges iterate k against ctl (if not null).

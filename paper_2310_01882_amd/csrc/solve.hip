@@ -59,11 +59,10 @@ __global__ __launch_bounds__(256) void refine_rhs_kernel(const double* __restric
   e0[q] = 0.0f;
 }
 
-// x += s * e on the interior, e taken from the inner buffer holding the
-// accepted iterate (index K read from the inner control block).
+// x += s * e on the interior (e: the inner buffer holding the accepted
+// iterate).
 __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__ x,
-                                                            float* e0, float* e1, float* e2,
-                                                            const Ctl* __restrict__ c,
+                                                            const float* __restrict__ e,
                                                             double s, int nx, int64_t sy,
                                                             int64_t sz, int64_t sy32,
                                                             int64_t sz32) {
@@ -71,8 +70,6 @@ __global__ __launch_bounds__(256) void refine_update_kernel(double* __restrict__
   const int j = blockIdx.y;
   const int k = blockIdx.z;
   if (i >= nx) return;
-  const int64_t kk = c->K;
-  const float* e = (kk % 3 == 0) ? e0 : (kk % 3 == 1) ? e1 : e2;
   const int64_t p = (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
   const int64_t q = (int64_t)(k + 1) * sz32 + (int64_t)(j + 1) * sy32 + (i + 1);
   x[p] = x[p] + s * (double)e[q];
@@ -110,10 +107,12 @@ struct ChunkRunner {
   int m;
   bool use_graph;
   hipStream_t s;
+  int tb;  // sweeps per launch: 1, or 2 (temporal blocking)
 
   int enqueue_chunk() {
     for (int i = 0; i < m; ++i) {
-      int rc = launch_sweep(g, dtype, bufs, 3, f, partials, hist, ctl, i, geo, s);
+      int rc = tb == 2 ? launch_sweep_tb2(g, dtype, bufs, 3, f, partials, hist, ctl, i, s)
+                       : launch_sweep(g, dtype, bufs, 3, f, partials, hist, ctl, i, geo, s);
       if (rc) return rc;
     }
     hipLaunchKernelGGL(ctl_advance_kernel, dim3(1), dim3(1), 0, s, ctl, (int64_t)m);
@@ -150,7 +149,7 @@ struct ChunkRunner {
     // sweeps did not run.
     int64_t launched = 0;
     for (;;) {
-      if (launched > host_ctl->max_sweeps + 2 * (int64_t)m + 2) {
+      if (launched * tb > host_ctl->max_sweeps + 2 * (int64_t)m * tb + 2) {
         rc = set_error(MS_EHIP, "sweep chunks ran without the control block completing");
         break;
       }
@@ -177,6 +176,30 @@ struct ChunkRunner {
     return rc;
   }
 };
+
+// Buffer holding iterate K once a chunked solve is done. One sweep per
+// launch: bufs[K % 3]. Two per launch: launch L keeps u_{2L} in bufs[L % 3];
+// an odd K was never stored, so one plain sweep recomputes it from u_{K-1}
+// into a buffer no later launch needs.
+int locate_iterate(const ms_grid& g, int dtype, void* const bufs[3], const void* f,
+                   double* partials, const SweepGeom& geo, int tb, int64_t K, hipStream_t s,
+                   void** out) {
+  if (tb != 2) {
+    *out = bufs[K % 3];
+    return MS_OK;
+  }
+  const int64_t L = K / 2;
+  if (K % 2 == 0) {
+    *out = bufs[L % 3];
+    return MS_OK;
+  }
+  void* b2[3] = {bufs[L % 3], bufs[(L + 1) % 3], bufs[L % 3]};
+  if (int rc = launch_sweep(g, dtype, b2, 2, f, partials, nullptr, nullptr, 0, geo, s)) return rc;
+  *out = b2[1];
+  return MS_OK;
+}
+
+int tb_of(const ms_solve_opts& o) { return o.temporal_block == 2 ? 2 : 1; }
 
 int auto_chunk(const ms_grid& g, int requested) {
   if (requested > 0) return requested;
@@ -231,7 +254,7 @@ int check_opts(const ms_solve_opts* o) {
     return set_error(MS_EINVAL, "jacobi_solve: rel_tol must be finite and >= 0");
   if (o->max_sweeps < 0) return set_error(MS_EINVAL, "jacobi_solve: max_sweeps < 0");
   if (o->check_every < 0) return set_error(MS_EINVAL, "jacobi_solve: check_every < 0");
-  if (o->temporal_block < 0 || o->temporal_block > 1)
+  if (o->temporal_block < 0 || o->temporal_block > 2)
     return set_error(MS_EUNSUPPORTED, "jacobi_solve: temporal_block %d not available",
                      o->temporal_block);
   if (o->precision == MS_SOLVE_F32_REFINED) {
@@ -288,13 +311,15 @@ extern "C" size_t jacobi_sweeps_workspace_bytes(const ms_grid* g) {
   return align_up(kPartialsBytes, 256);
 }
 
-extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
-                             int64_t n, double* res_dev, void* work, size_t work_bytes,
-                             void* stream) {
+extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                                const void* f, int64_t n, int temporal_block, double* res_dev,
+                                void* work, size_t work_bytes, void* stream) {
   clear_error();
   if (int rc = check_grid(g, "jacobi_sweeps")) return rc;
   if (dtype != MS_F64 && dtype != MS_F32)
     return set_error(MS_EUNSUPPORTED, "jacobi_sweeps: dtype %d", dtype);
+  if (temporal_block != 1 && temporal_block != 2)
+    return set_error(MS_EUNSUPPORTED, "jacobi_sweeps: temporal_block %d", temporal_block);
   if (!u || !u_tmp) return set_error(MS_EINVAL, "jacobi_sweeps: u and u_tmp required");
   if (n < 0) return set_error(MS_EINVAL, "jacobi_sweeps: n < 0");
   const size_t bytes = (size_t)field_span(*g) * elem_size(dtype);
@@ -310,22 +335,51 @@ extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, 
   const SweepGeom geo = sweep_geom(*g, dtype, vec_alignment(*g, dtype, ptrs, 3));
   double* partials = static_cast<double*>(work);
   void* bufs[3] = {u, u_tmp, u};
-  for (int64_t k = 0; k < n; ++k)
-    if (int rc = launch_sweep(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, k, geo, s))
-      return rc;
-  if (res_dev) {
-    if (n >= 1)
-      if (int rc = launch_finalize(partials, (int)((n - 1) & 1), geo.nblocks, nullptr, nullptr,
+  void* last = u;
+  if (temporal_block == 1) {
+    for (int64_t k = 0; k < n; ++k)
+      if (int rc = launch_sweep(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, k, geo, s))
+        return rc;
+    if (res_dev && n >= 1)
+      if (int rc = launch_finalize(partials, (int)((n - 1) & 3), geo.nblocks, nullptr, nullptr,
                                    res_dev, n - 1, s))
         return rc;
-    const int slot = (int)(n & 1);
-    if (int rc = launch_residual(*g, dtype, (n & 1) ? u_tmp : u, f, false, partials, slot, s))
-      return rc;
+    last = (n & 1) ? u_tmp : u;
+  } else {
+    const int64_t nl = n / 2;
+    for (int64_t l = 0; l < nl; ++l)
+      if (int rc = launch_sweep_tb2(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, l, s))
+        return rc;
+    if (res_dev && nl >= 1)
+      for (int64_t k = 2 * nl - 2; k < 2 * nl; ++k)
+        if (int rc = launch_finalize(partials, (int)(k & 3), tb2_blocks(*g), nullptr, nullptr,
+                                     res_dev, k, s))
+          return rc;
+    last = bufs[nl % 2];
+    if (n & 1) {
+      void* b2[3] = {last, bufs[(nl + 1) % 2], last};
+      if (int rc = launch_sweep(*g, dtype, b2, 2, f, partials, nullptr, nullptr, 0, geo, s))
+        return rc;
+      if (res_dev)
+        if (int rc = launch_finalize(partials, 0, geo.nblocks, nullptr, nullptr, res_dev, n - 1, s))
+          return rc;
+      last = b2[1];
+    }
+  }
+  if (res_dev) {
+    const int slot = (int)(n & 3) == 0 ? 1 : (int)(n & 3);  // not slot 0 (odd tail above)
+    if (int rc = launch_residual(*g, dtype, last, f, false, partials, slot, s)) return rc;
     if (int rc = launch_finalize(partials, slot, residual_blocks(*g), nullptr, nullptr, res_dev,
                                  n, s))
       return rc;
   }
   return MS_OK;
+}
+
+extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
+                             int64_t n, double* res_dev, void* work, size_t work_bytes,
+                             void* stream) {
+  return jacobi_sweeps_tb(g, dtype, u, u_tmp, f, n, 1, res_dev, work, work_bytes, stream);
 }
 
 // ------------------------------------------------------------- jacobi_solve
@@ -363,7 +417,7 @@ int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double*
               Workspace& ws, double* hist_host, ms_solve_result* res, hipStream_t s) {
   const size_t span = (size_t)field_span(g);
   Ctl* ctl = ws.take<Ctl>(1);
-  double* partials = ws.take<double>(2 * (size_t)kMaxBlocks);
+  double* partials = ws.take<double>((size_t)kPartialSlots * kMaxBlocks);
   double* b1 = take_field<double>(ws, g, elem_phase(u, 8));
   double* b2 = take_field<double>(ws, g, elem_phase(u, 8));
   double* hist = ws.take<double>((size_t)o.max_sweeps + 2);
@@ -385,12 +439,14 @@ int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double*
 
   Ctl hc{};
   hc.max_sweeps = o.max_sweeps;
+  const int tb = tb_of(o);
   ChunkRunner run{g, MS_F64, {u, b1, b2}, f, partials, hist, ctl, geo,
-                  auto_chunk(g, o.check_every), o.use_graph != 0, s};
+                  auto_chunk(g, o.check_every), o.use_graph != 0, s, tb};
   if (int rc = run.run(&hc)) return rc;
   const int64_t K = hc.K;
-  if (K % 3 != 0)
-    MS_HIP_TRY(hipMemcpyAsync(u, K % 3 == 1 ? b1 : b2, span * 8, hipMemcpyDeviceToDevice, s));
+  void* ans = nullptr;
+  if (int rc = locate_iterate(g, MS_F64, run.bufs, f, partials, geo, tb, K, s, &ans)) return rc;
+  if (ans != u) MS_HIP_TRY(hipMemcpyAsync(u, ans, span * 8, hipMemcpyDeviceToDevice, s));
   double res_final = 0.0;
   MS_HIP_TRY(hipMemcpyAsync(&res_final, hist + K, sizeof(double), hipMemcpyDeviceToHost, s));
   if (hist_host)
@@ -418,7 +474,7 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
   const ms_grid h = f32_grid(g);
   const size_t span32 = (size_t)field_span(h);
   Ctl* ctl = ws.take<Ctl>(1);
-  double* partials = ws.take<double>(2 * (size_t)kMaxBlocks);
+  double* partials = ws.take<double>((size_t)kPartialSlots * kMaxBlocks);
   // base one element before a 128-byte boundary: phase 31 of 64 floats
   float* rhat = take_field<float>(ws, h, 31);
   float* e[3] = {take_field<float>(ws, h, 31), take_field<float>(ws, h, 31),
@@ -488,15 +544,19 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
     MS_LAUNCH_CHECK();
     Ctl hc{};
     hc.max_sweeps = cap;
+    const int tb = tb_of(o);
     ChunkRunner run{h, MS_F32, {e[0], e[1], e[2]}, rhat, partials, hist, ctl, geo,
-                    auto_chunk(g, o.check_every), o.use_graph != 0, s};
+                    auto_chunk(g, o.check_every), o.use_graph != 0, s, tb};
     if (int rc = run.run(&hc)) return rc;
     if (hc.done == NONFINITE) {
       status = set_error(MS_ENONFINITE, "jacobi_solve: inner residual not finite");
       break;
     }
-    hipLaunchKernelGGL(refine_update_kernel, eg, eb, 0, s, x, e[0], e[1], e[2], ctl, sc, g.nx,
-                       g.sy, g.sz, h.sy, h.sz);
+    void* ek = nullptr;
+    if (int rc = locate_iterate(h, MS_F32, run.bufs, rhat, partials, geo, tb, hc.K, s, &ek))
+      return rc;
+    hipLaunchKernelGGL(refine_update_kernel, eg, eb, 0, s, x, static_cast<const float*>(ek), sc,
+                       g.nx, g.sy, g.sz, h.sy, h.sz);
     MS_LAUNCH_CHECK();
     total += hc.K;
     ++outer;

@@ -186,3 +186,45 @@ def test_every_tile_geometry_is_bit_exact(geom, dtype, monkeypatch):
                 want = oracle.sweep_f32(want, f)
         assert np.array_equal(host(out), want), (geom, dims)
         np.testing.assert_allclose(host(res)[:3], hist, rtol=NORM_RTOL)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("dims", [(64, 8, 9), (130, 37, 11), (5, 3, 2), (1, 1, 1), (65, 17, 40),
+                                  (200, 9, 3)])
+def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype):
+    """Two sweeps fused per pass: the same fields and norms as the oracle's
+    plain sweeps, for even and odd sweep counts."""
+    note(f"case: tb2 {dims} {dtype.__name__}")
+    u, f = _problem(*dims, seed=3 * dims[0] + dims[2])
+    u, f = u.astype(dtype), f.astype(dtype)
+    for n in (1, 2, 3, 4, 7):
+        du, dt, df = ms.field_from(u), ms.field_from(u), ms.field_from(f)
+        res = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        out = ms.jacobi_sweeps(du, dt, n, f=df, res=res, temporal_block=2)
+        want, hist = u, []
+        for _ in range(n):
+            if dtype == np.float64:
+                hist.append(oracle.residual_norm(want, f))
+                want = oracle.jacobi_sweep(want, f)
+            else:
+                hist.append(oracle.residual_norm_f32_storage(want, f))
+                want = oracle.sweep_f32(want, f)
+        hist.append(oracle.residual_norm(want, f) if dtype == np.float64
+                    else oracle.residual_norm_f32_storage(want, f))
+        assert np.array_equal(host(out), want), (dims, n)
+        np.testing.assert_allclose(host(res), hist, rtol=NORM_RTOL)
+
+
+def test_temporal_blocking_at_benchmark_size():
+    note("case: tb2 512^3 x 4 sweeps vs plain")
+    n = 512
+    f = ms.field_from(synth.gaussian_sources(n, n, n, 8, 1))
+    outs = []
+    for tb in (1, 2):
+        u, t = ms.alloc_field(n, n, n), ms.alloc_field(n, n, n)
+        res = torch.zeros(5, dtype=torch.float64, device="cuda")
+        o = ms.jacobi_sweeps(u, t, 4, f=f, res=res, temporal_block=tb)
+        outs.append((o.clone(), res.clone()))
+        del u, t
+    assert torch.equal(outs[0][0], outs[1][0])
+    np.testing.assert_allclose(host(outs[0][1]), host(outs[1][1]), rtol=NORM_RTOL)

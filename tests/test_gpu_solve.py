@@ -155,3 +155,27 @@ def test_refined_fields_replay_bit_exact_per_outer_step():
     own = oracle.refined_solve(u, f, 1e-12, 1e-3, 2, 10 ** 7, 256)
     for a, b in zip(counts, own["inner"]):
         assert abs(a - b) <= 1
+
+
+@pytest.mark.parametrize("dims,tol", [((16, 16, 16), 1e-6), ((33, 20, 12), 1e-7), ((9, 5, 3), 1e-9)])
+def test_temporal_blocking_solve_matches_plain(dims, tol):
+    u, f = _poisson(*dims, seed=sum(dims) + 1)
+    res = []
+    for tb in (1, 2):
+        du = dev(u)
+        info = ms.jacobi_solve(du, dev(f), rel_tol=tol, temporal_block=tb, check_every=13)
+        res.append((info.sweeps, host(du)))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    K, uk, hist, res0, ok = oracle.jacobi_solve(u, f, tol, 200000)
+    assert _count_ok(res[1][0], K, hist, res0, tol)
+
+
+def test_temporal_blocking_refined_solve_matches_plain():
+    u, f = _poisson(22, 18, 14, 6, halo=False, nsrc=4)
+    out = []
+    for tb in (1, 2):
+        du, info = _refined(u, f, rel_tol=1e-8, temporal_block=tb)
+        out.append((info.sweeps, info.outer_iters, host(du)))
+    assert out[0][:2] == out[1][:2]
+    assert np.array_equal(out[0][2], out[1][2])
