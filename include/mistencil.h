@@ -200,6 +200,32 @@ int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
                  const double* f, void* work, size_t work_bytes,
                  double* hist_host, ms_solve_result* res, void* stream);
 
+/* ---- autotuning of the sweep tile shape ------------------------------------
+ * The sweeps of jacobi_sweeps / jacobi_solve run z-marching wave tiles whose
+ * shape -- x cells per lane (vec), waves across x (wx), rows per lane
+ * (rows) and the number of blocks the z split aims at -- changes the
+ * bandwidth they reach. ms_autotune_sweeps times every candidate shape on
+ * the caller's buffers (u and u_tmp are overwritten: pass scratch fields
+ * laid out like the real ones), keeps the fastest in a process-wide table
+ * keyed by (dtype, nx, ny, nz, vector alignment of the buffers) and returns
+ * it; later sweeps on a matching grid use it. Every shape gives the same
+ * bits. ms_tuning_get / ms_tuning_set export and import the table (for a
+ * cache file); ms_tuning_clear empties it. */
+typedef struct {
+  int32_t dtype, nx, ny, nz, vec_ok;
+  int32_t vec, wx, rows;
+  int64_t target_blocks;
+  double us_per_sweep; /* measured time of the chosen shape */
+} ms_tuning;
+
+int ms_autotune_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
+                       int sweeps_per_trial, void* work, size_t work_bytes,
+                       ms_tuning* best, void* stream);
+/* Copies up to cap entries into out; returns the number of entries. */
+int ms_tuning_get(ms_tuning* out, int cap);
+int ms_tuning_set(const ms_tuning* in, int n);
+void ms_tuning_clear(void);
+
 /* ---- batched solves ---------------------------------------------------------
  * Many independent instances of jacobi_solve, each with its own grid,
  * solved in ONE persistent kernel launch (captured in a hipGraph). The
@@ -252,6 +278,65 @@ int advect_source(const ms_grid* g, const double* u, const double* v,
                   const double* w, const double* tzc1, const double* tzc2,
                   double tcx, double tcy, double* su, double* sv, double* sw,
                   void* stream);
+
+/* ---- learned warm start: 3x3x3 convolutions on BF16 MFMA ----------------
+ * Not in the paper: a small 3D CNN (2 -> 32 -> 32 -> 32 -> 1 channels,
+ * ReLU after the first three layers) maps [f/s, g/s] (right-hand side and
+ * boundary lift g, scaled by s = max(max|f|, max|g|)) to u / (s * lambda),
+ * an initial guess for jacobi_solve. These entry points are its training
+ * and inference kernels.
+ *
+ * Activations: BF16, channels-last over an X x Y x Z volume with a
+ * one-voxel zero halo (the "same" zero padding of the convolution): element
+ * (x, y, z, c) at ((((z+1)*(Y+2) + (y+1))*(X+2) + (x+1))*C + c); C = cin
+ * (8 or 32) for inputs, 32 for outputs (channels beyond the real count are
+ * zero). The caller allocates them zero-filled; kernels write the interior.
+ * Weights: BF16 [27][32][cin] (forward) and [27][cin][32] (input gradient),
+ * tap t = (dx+1) + 3(dy+1) + 9(dz+1); FP32 master copies [27][32][cin] and
+ * biases [32]. Products in BF16, sums in FP32. All pointers are device
+ * pointers; all calls are async on `stream`. */
+
+/* out[v][co] = act(bias[co] + sum_{t,ci} w[t][co][ci] in[v + d_t][ci]);
+ * act = ReLU if relu, else identity. out (BF16, C = 32) and/or out32 (FP32
+ * channel 0 in the field layout (X+2)(Y+2)(Z+2), sy = X+2) may be NULL. */
+int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, const void* w,
+                    const float* bias, void* out, float* out32, int relu,
+                    void* stream);
+/* din[v][ci] = [mask[v][ci] > 0] * sum_{t,co} wd[t][ci][co] dout[v - d_t][co]
+ * (mask = the layer input, i.e. the previous layer's ReLU output; NULL for
+ * no mask). */
+int conv3d_bf16_dgrad(int X, int Y, int Z, int cin, const void* dout, const void* wd,
+                      const void* mask, void* din, void* stream);
+/* dw[t][co][ci] = sum_v dpre[v][co] in[v + d_t][ci], db[co] = sum_v dpre[v][co]
+ * (FP32, deterministic two-pass reduction through `work`). */
+size_t conv3d_bf16_wgrad_workspace_bytes(int cin);
+int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, const void* dpre,
+                      float* dw, float* db, void* work, size_t work_bytes, void* stream);
+/* loss_part[b] = partial sums of (pred - target)^2 over interior voxels
+ * (nparts blocks); dpre channel 0 = BF16(2 (pred - target) / N). pred and
+ * target: FP32 in the field layout. dpre channels 1..31 are left as they are
+ * (zero). */
+int cnn_mse_grad(int X, int Y, int Z, const float* pred, const float* target, void* dpre,
+                 double* loss_part, int nparts, void* stream);
+/* One Adam step (beta 0.9, 0.999, eps 1e-8, step t >= 1) on FP32 master
+ * weights w and biases b, then BF16 copies in both layouts. */
+int cnn_adam(int cin, float* w, float* b, float* mw, float* vw, float* mb, float* vb,
+             const float* gw, const float* gb, void* wf, void* wd, float lr, int t,
+             void* stream);
+/* BF16 copies of FP32 master weights in both layouts. */
+int cnn_pack_weights(int cin, const float* w, void* wf, void* wd, void* stream);
+/* Features [f/s, g/s, 0 x 6] (BF16, C = 8) of the Poisson problem (u: halo =
+ * Dirichlet values, f may be NULL) and *scale = s (device); part: nparts
+ * doubles of scratch. */
+int cnn_features(const ms_grid* g, const double* u, const double* f, void* feat,
+                 double* scale, double* part, int nparts, void* stream);
+/* x interior = (*scale) * lambda * uhat (FP64); the halo is not touched. */
+int cnn_guess(const ms_grid* g, const float* uhat, const double* scale, double lambda,
+              double* x, void* stream);
+/* out (FP32, field layout of the volume) = u / ((*scale) * lambda) on the
+ * interior: training targets from solved fields. */
+int cnn_target(const ms_grid* g, const double* u, const double* scale, double lambda,
+               float* out, void* stream);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,183 @@
+"""Oracle for the learned warm start -- TEST INFRASTRUCTURE ONLY.
+
+A small 3D CNN maps the right-hand side and the boundary data of a Poisson
+problem to an initial guess. The paper has no learned component; this
+follows the project's reading (feature definition, scaling, network shape)
+recorded with each function. Everything is FP64 numpy; the BF16 rounding the
+GPU applies to inputs, weights and stored activations is emulated where the
+GPU rounds (round to nearest even).
+
+Layout: an activation is an array [C, Z, Y, X] over the interior (no halo);
+"same" convolution pads with zeros. Weights are [Cout, Cin, 3, 3, 3] with
+index [.., dz + 1, dy + 1, dx + 1] for the tap at offset (dx, dy, dz); the
+layer computes out[co, p] = b[co] + sum_{ci, d} w[co, ci, d] * x[ci, p + d].
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+TAPS = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def round_bf16(a):
+    """Round to the nearest bfloat16 (ties to even), returned as float64.
+    Values are first rounded to float32 (the GPU's accumulator type)."""
+    x = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    b = x.view(np.uint32).astype(np.uint64)
+    lsb = (b >> 16) & 1
+    r = ((b + 0x7FFF + lsb) >> 16) << 16
+    nan = np.isnan(x)
+    out = (r & 0xFFFFFFFF).astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def _shift(xpad, d, shape):
+    """View of the zero-padded activation at offset d = (dx, dy, dz)."""
+    dx, dy, dz = d
+    _, z, y, x = shape
+    return xpad[:, 1 + dz:1 + dz + z, 1 + dy:1 + dy + y, 1 + dx:1 + dx + x]
+
+
+def conv3d(x, w, b=None):
+    """'Same' 3x3x3 convolution (cross-correlation) with zero padding."""
+    cin, z, y, xx = x.shape
+    cout = w.shape[0]
+    xpad = np.zeros((cin, z + 2, y + 2, xx + 2))
+    xpad[:, 1:-1, 1:-1, 1:-1] = x
+    out = np.zeros((cout, z, y, xx))
+    for dx, dy, dz in TAPS:
+        wt = w[:, :, dz + 1, dy + 1, dx + 1]  # [cout, cin]
+        out += np.tensordot(wt, _shift(xpad, (dx, dy, dz), x.shape), axes=(1, 0))
+    if b is not None:
+        out += b.reshape(cout, 1, 1, 1)
+    return out
+
+
+def conv3d_dgrad(g, w):
+    """Gradient w.r.t. the input of conv3d for output gradient g."""
+    cout, z, y, xx = g.shape
+    cin = w.shape[1]
+    gpad = np.zeros((cout, z + 2, y + 2, xx + 2))
+    gpad[:, 1:-1, 1:-1, 1:-1] = g
+    out = np.zeros((cin, z, y, xx))
+    for dx, dy, dz in TAPS:
+        wt = w[:, :, dz + 1, dy + 1, dx + 1]  # [cout, cin]
+        # x[ci, p + d] feeds out[co, p]: dx[ci, q] += w[co, ci, d] g[co, q - d]
+        out += np.tensordot(wt, _shift(gpad, (-dx, -dy, -dz), g.shape), axes=(0, 0))
+    return out
+
+
+def conv3d_wgrad(x, g):
+    """Gradients w.r.t. weights and bias of conv3d for input x, output grad g."""
+    cin, z, y, xx = x.shape
+    cout = g.shape[0]
+    xpad = np.zeros((cin, z + 2, y + 2, xx + 2))
+    xpad[:, 1:-1, 1:-1, 1:-1] = x
+    dw = np.zeros((cout, cin, 3, 3, 3))
+    gm = g.reshape(cout, -1)
+    for dx, dy, dz in TAPS:
+        xs = _shift(xpad, (dx, dy, dz), x.shape).reshape(cin, -1)
+        dw[:, :, dz + 1, dy + 1, dx + 1] = gm @ xs.T
+    db = g.sum(axis=(1, 2, 3))
+    return dw, db
+
+
+class Net:
+    """Layers 2 -> C -> C -> C -> 1, ReLU after the first three, no
+    activation after the last. ``bf16`` emulates the GPU's storage rounding:
+    inputs and weights rounded to BF16 before each layer, hidden activations
+    stored as BF16 after bias + ReLU, the output kept in FP32."""
+
+    def __init__(self, params, bf16=True):
+        self.params = params  # list of (w, b)
+        self.bf16 = bf16
+
+    def _r(self, a):
+        return round_bf16(a) if self.bf16 else np.asarray(a, dtype=np.float64)
+
+    def forward(self, x):
+        acts = [self._r(x)]
+        pre = []
+        n = len(self.params)
+        for li, (w, b) in enumerate(self.params):
+            z = conv3d(acts[-1], self._r(w), b)
+            pre.append(z)
+            if li < n - 1:
+                acts.append(self._r(np.maximum(z, 0.0)))
+            else:
+                out = z.astype(np.float32).astype(np.float64) if self.bf16 else z
+                acts.append(out)
+        self.acts, self.pre = acts, pre
+        return acts[-1]
+
+    def backward(self, gout):
+        """Gradients of sum(gout * output) w.r.t. every (w, b), after
+        forward(). Hidden gradients pass through the ReLU mask (pre > 0)."""
+        grads = [None] * len(self.params)
+        g = np.asarray(gout, dtype=np.float64)
+        for li in range(len(self.params) - 1, -1, -1):
+            w, _ = self.params[li]
+            if li < len(self.params) - 1:
+                g = g * (self.pre[li] > 0)
+            dw, db = conv3d_wgrad(self.acts[li], g)
+            grads[li] = (dw, db)
+            if li > 0:
+                g = conv3d_dgrad(g, self._r(w))
+                if self.bf16:
+                    g = round_bf16(g)
+        return grads
+
+
+def mse_and_grad(pred, target):
+    """Mean squared error over all voxels and its gradient w.r.t. pred."""
+    d = pred - target
+    n = d.size
+    return float(np.sum(d * d) / n), 2.0 * d / n
+
+
+def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) of parameter p with gradient g; moments
+    m, v updated in place; t is the 1-based step count. Returns new p."""
+    m *= b1
+    m += (1 - b1) * g
+    v *= b2
+    v += (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps)
+
+
+def boundary_lift(u):
+    """g = for every interior cell, the sum of the Dirichlet halo values among
+    its six neighbours (the boundary's contribution to the 7-point sum), with
+    the interior of u ignored. Input/Output: halo-padded array (Z+2, Y+2, X+2)
+    in, interior array (Z, Y, X) out."""
+    z = np.array(u, dtype=np.float64, copy=True)
+    z[1:-1, 1:-1, 1:-1] = 0.0
+    nz, ny, nx = (s - 2 for s in z.shape)
+    g = np.zeros((nz, ny, nx))
+    for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        g += z[1 + dz:nz + 1 + dz, 1 + dy:ny + 1 + dy, 1 + dx:nx + 1 + dx]
+    return g
+
+
+def features(u, f):
+    """Network input [f/s, g/s] and the scale s = max(max|f|, max|g|) (1 if 0).
+    f and u are halo-padded; features cover the interior."""
+    fi = np.asarray(f, dtype=np.float64)[1:-1, 1:-1, 1:-1] if f is not None else None
+    g = boundary_lift(u)
+    if fi is None:
+        fi = np.zeros_like(g)
+    s = max(float(np.max(np.abs(fi))), float(np.max(np.abs(g))))
+    if s == 0.0:
+        s = 1.0
+    return np.stack([fi / s, g / s]), s
+
+
+def output_scale(nx, ny, nz):
+    """lambda = max(n)^2 / 8: the solution of a unit-scale source grows like
+    the square of the domain size; the network predicts u / (s * lambda)."""
+    n = max(nx, ny, nz)
+    return n * n / 8.0

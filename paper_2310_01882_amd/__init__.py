@@ -72,6 +72,13 @@ class SolveResult(ctypes.Structure):
                 ("res_final", ctypes.c_double), ("rel_final", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("vec_ok", ctypes.c_int32), ("vec", ctypes.c_int32),
+                ("wx", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("target_blocks", ctypes.c_int64), ("us_per_sweep", ctypes.c_double)]
+
+
 class Instance(ctypes.Structure):
     _fields_ = [("grid", Grid), ("x", ctypes.c_void_p), ("f", ctypes.c_void_p)]
 
@@ -103,6 +110,21 @@ SIGNATURES = {
                                   _SZ, ctypes.POINTER(SolveResult), _P]),
     "jacobi_batched_plan": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "ms_autotune_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I, _P, _SZ,
+                                ctypes.POINTER(Tuning), _P]),
+    "ms_tuning_get": (_I, [ctypes.POINTER(Tuning), _I]),
+    "ms_tuning_set": (_I, [ctypes.POINTER(Tuning), _I]),
+    "ms_tuning_clear": (None, []),
+    "conv3d_bf16_fwd": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P]),
+    "conv3d_bf16_dgrad": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "conv3d_bf16_wgrad_workspace_bytes": (_SZ, [_I]),
+    "conv3d_bf16_wgrad": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
+    "cnn_mse_grad": (_I, [_I, _I, _I, _P, _P, _P, _P, _I, _P]),
+    "cnn_adam": (_I, [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _I, _P]),
+    "cnn_pack_weights": (_I, [_I, _P, _P, _P, _P]),
+    "cnn_features": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _I, _P]),
+    "cnn_guess": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
+    "cnn_target": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
 }
 
 
@@ -399,3 +421,57 @@ def jacobi_solve_batched(xs, fs, work=None, stream=None, **opts):
     _check(rc, allow=(MS_OK, MS_NOT_CONVERGED))
     return [SolveInfo(r.status, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, [])
             for r in res]
+
+
+# ------------------------------------------------------------------ tuning
+
+_TUNING_FIELDS = [name for name, _ in Tuning._fields_]
+
+
+def autotune_sweeps(u, u_tmp, f=None, sweeps_per_trial=10, stream=None) -> dict:
+    """Time every sweep tile shape on (scratch) fields laid out like the real
+    ones, keep the fastest for this grid, dtype and alignment, return it."""
+    _field_check(u, "u")
+    _field_check(u_tmp, "u_tmp", u.dtype)
+    _same_layout(u, u_tmp, "u/u_tmp")
+    if f is not None:
+        _field_check(f, "f", u.dtype)
+        _same_layout(u, f, "u/f")
+    g = grid_of(u)
+    work = jacobi_sweeps_workspace(u)
+    best = Tuning()
+    _check(lib.ms_autotune_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f),
+                                  int(sweeps_per_trial), _ptr(work), work.numel(),
+                                  ctypes.byref(best), _stream(stream)))
+    return {k: getattr(best, k) for k in _TUNING_FIELDS}
+
+
+def tuning_table() -> list:
+    n = lib.ms_tuning_get(None, 0)
+    arr = (Tuning * max(n, 1))()
+    lib.ms_tuning_get(arr, n)
+    return [{k: getattr(arr[i], k) for k in _TUNING_FIELDS} for i in range(n)]
+
+
+def tuning_load(entries) -> None:
+    arr = (Tuning * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        for k in _TUNING_FIELDS:
+            setattr(arr[i], k, e[k])
+    _check(lib.ms_tuning_set(arr, len(entries)))
+
+
+def tuning_save_json(path) -> None:
+    import json
+    with open(path, "w") as fh:
+        json.dump(tuning_table(), fh, indent=1)
+
+
+def tuning_load_json(path) -> None:
+    import json
+    with open(path) as fh:
+        tuning_load(json.load(fh))
+
+
+def tuning_clear() -> None:
+    lib.ms_tuning_clear()

@@ -1,0 +1,571 @@
+// Learned warm start: 3x3x3 convolutions on BF16 MFMA with FP32
+// accumulation (forward, input gradient, weight gradient), the MSE loss,
+// Adam, and the feature / guess kernels.
+//
+// Activations are channels-last with a one-voxel zero halo ("same" zero
+// padding): element (x, y, z, c) of an X x Y x Z volume with C channels is
+// at ((((z+1)*(Y+2) + (y+1))*(X+2) + (x+1))*C + c). C is 8 (input features)
+// or 32 (hidden layers); output channels are always padded to 32.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_32x32x16_bf16: a wave
+// owns 32 consecutive voxels along x (M) times 32 channels (N) and walks K
+// = 27 taps x input channels in steps of 16; the lane layout (checked on
+// the device) is A[m = l%32][k = 8(l/32)+e], B[k = 8(l/32)+e][n = l%32],
+// D[m = 8(r/4) + 4(l/32) + r%4][n = l%32].
+//  * forward:  A = input at voxel + tap offset, B = W[tap][co][ci] (LDS);
+//    epilogue adds the bias, applies ReLU (hidden layers) and stores BF16,
+//    or stores channel 0 in FP32 (last layer).
+//  * dgrad:    A = output gradient at voxel - tap offset, B = W[tap][ci][co];
+//    epilogue multiplies by the ReLU mask of the layer input (post > 0).
+//  * wgrad:    dW[tap][co][ci] = sum over voxels of dPre[v][co] in[v+d][ci];
+//    M = co, N = ci, K = 16 voxels per step, operands transposed through
+//    LDS; each wave owns up to 7 taps; per-block partials are summed by a
+//    second kernel in a fixed order (deterministic).
+#include "ms_internal.hpp"
+
+#include <hip/hip_bf16.h>
+
+namespace ms {
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+constexpr int kTaps = 27;
+constexpr int kCo = 32;  // padded output channels
+
+__device__ __forceinline__ void tap_offset(int t, int& dx, int& dy, int& dz) {
+  dx = t % 3 - 1;
+  dy = (t / 3) % 3 - 1;
+  dz = t / 9 - 1;
+}
+
+struct Vol {
+  int X, Y, Z;
+  __device__ __forceinline__ int64_t vox(int x, int y, int z) const {
+    return (((int64_t)(z + 1) * (Y + 2) + (y + 1)) * (X + 2) + (x + 1));
+  }
+};
+
+__device__ __forceinline__ bf16x8 zero8() {
+  bf16x8 z;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) z[e] = (bf16)0.0f;
+  return z;
+}
+
+// ------------------------------------------------------------- forward
+
+struct FwdK {
+  Vol v;
+  const bf16* in;      // C = CIN
+  const bf16* w;       // [27][32][CIN]
+  const float* bias;   // [32]
+  bf16* out;           // C = 32 (hidden layers)
+  float* out32;        // channel 0 in FP32 (last layer), field layout
+  int relu;
+  int nseg;
+};
+
+template <int CIN>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(FwdK a) {
+  __shared__ bf16x8 wl[kTaps * kCo * CIN / 8];
+  for (int t = threadIdx.x; t < kTaps * kCo * CIN / 8; t += blockDim.x)
+    wl[t] = reinterpret_cast<const bf16x8*>(a.w)[t];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + 31) / 32;
+  constexpr int KS = (kTaps * CIN + 15) / 16;
+  const float bj = a.bias[m];
+  for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
+    const int x0 = (seg % sx) * 32, y = (seg / sx) % a.v.Y, z = seg / (sx * a.v.Y);
+    const bool mok = x0 + m < a.v.X;
+    f32x16 acc = {};
+#pragma unroll 2
+    for (int s = 0; s < KS; ++s) {
+      const int k0 = s * 16 + 8 * h;
+      const int t = k0 / CIN, c0 = k0 % CIN;
+      bf16x8 av = zero8(), bv = zero8();
+      if (t < kTaps) {
+        int dx, dy, dz;
+        tap_offset(t, dx, dy, dz);
+        if (mok)
+          av = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x0 + m + dx, y + dy, z + dz) * CIN +
+                                                c0);
+        bv = wl[((t * kCo + m) * CIN + c0) / 8];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      const int x = x0 + i;
+      if (x >= a.v.X) continue;
+      float val = acc[r] + bj;
+      if (a.relu) val = fmaxf(val, 0.0f);
+      const int64_t p = a.v.vox(x, y, z);
+      if (a.out) a.out[p * kCo + m] = (bf16)val;
+      if (a.out32 && m == 0) a.out32[p] = val;
+    }
+  }
+}
+
+// --------------------------------------------------------------- dgrad
+
+struct DgK {
+  Vol v;
+  const bf16* dout;  // C = 32 (gradient w.r.t. the layer's pre-activation)
+  const bf16* wd;    // [27][CIN][32]
+  const bf16* mask;  // layer input (post-ReLU of the previous layer), C = CIN
+  bf16* din;         // C = CIN: gradient w.r.t. the previous pre-activation
+  int nseg;
+};
+
+template <int CIN>
+__global__ __launch_bounds__(256) void conv_dgrad_kernel(DgK a) {
+  __shared__ bf16x8 wl[kTaps * CIN * kCo / 8];
+  for (int t = threadIdx.x; t < kTaps * CIN * kCo / 8; t += blockDim.x)
+    wl[t] = reinterpret_cast<const bf16x8*>(a.wd)[t];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + 31) / 32;
+  constexpr int KS = kTaps * kCo / 16;
+  for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
+    const int x0 = (seg % sx) * 32, y = (seg / sx) % a.v.Y, z = seg / (sx * a.v.Y);
+    const bool mok = x0 + m < a.v.X;
+    f32x16 acc = {};
+#pragma unroll 2
+    for (int s = 0; s < KS; ++s) {
+      const int k0 = s * 16 + 8 * h;
+      const int t = k0 / kCo, c0 = k0 % kCo;
+      int dx, dy, dz;
+      tap_offset(t, dx, dy, dz);
+      bf16x8 av = zero8(), bv = zero8();
+      // input voxel q feeds output q - d through tap d
+      if (mok)
+        av = *reinterpret_cast<const bf16x8*>(a.dout + a.v.vox(x0 + m - dx, y - dy, z - dz) * kCo +
+                                              c0);
+      if (m < CIN) bv = wl[((t * CIN + m) * kCo + c0) / 8];
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+    }
+    if (m >= CIN) continue;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 8 * (r / 4) + 4 * h + (r % 4);
+      const int x = x0 + i;
+      if (x >= a.v.X) continue;
+      const int64_t p = a.v.vox(x, y, z);
+      float g = acc[r];
+      if (a.mask && !((float)a.mask[p * CIN + m] > 0.0f)) g = 0.0f;
+      a.din[p * CIN + m] = (bf16)g;
+    }
+  }
+}
+
+// --------------------------------------------------------------- wgrad
+
+struct WgK {
+  Vol v;
+  const bf16* in;    // C = CIN
+  const bf16* dpre;  // C = 32
+  float* part;       // per block: [27][32][CIN] then [32] bias
+  int nseg16;        // segments of 16 voxels along x
+};
+
+template <int CIN>
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(WgK a) {
+  __shared__ bf16 dp[16][kCo];
+  __shared__ bf16 inr[9][18][CIN];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + 15) / 16;
+  f32x16 acc[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc[q] = f32x16{};
+  float dbacc = 0.0f;
+  for (int seg = blockIdx.x; seg < a.nseg16; seg += gridDim.x) {
+    const int x0 = (seg % sx) * 16, y = (seg / sx) % a.v.Y, z = seg / (sx * a.v.Y);
+    __syncthreads();  // previous segment's reads are done
+    // dPre: 16 voxels x 32 channels (voxels past X read as 0)
+    for (int e = threadIdx.x; e < 16 * kCo / 8; e += blockDim.x) {
+      const int vx = e / (kCo / 8), c8 = (e % (kCo / 8)) * 8;
+      bf16x8 val = zero8();
+      if (x0 + vx < a.v.X)
+        val = *reinterpret_cast<const bf16x8*>(a.dpre + a.v.vox(x0 + vx, y, z) * kCo + c8);
+      *reinterpret_cast<bf16x8*>(&dp[vx][c8]) = val;
+    }
+    // input rows for the 9 (dy, dz) offsets, x from x0-1 to x0+16
+    for (int e = threadIdx.x; e < 9 * 18 * CIN / 8; e += blockDim.x) {
+      const int c8 = (e % (CIN / 8)) * 8;
+      const int vx = (e / (CIN / 8)) % 18;
+      const int row = e / (CIN / 8) / 18;
+      const int dy = row % 3 - 1, dz = row / 3 - 1;
+      const int x = x0 - 1 + vx;
+      bf16x8 val = zero8();
+      if (x <= a.v.X)  // the halo voxel x = X exists (zero)
+        val = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x, y + dy, z + dz) * CIN + c8);
+      *reinterpret_cast<bf16x8*>(&inr[row][vx][c8]) = val;
+    }
+    __syncthreads();
+    bf16x8 av;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) av[e] = dp[8 * h + e][m];  // A[co = m][voxel]
+#pragma unroll
+    for (int q = 0; q < 7; ++q) {
+      const int t = w + 4 * q;
+      if (t >= kTaps) break;
+      int dx, dy, dz;
+      tap_offset(t, dx, dy, dz);
+      const int row = (dz + 1) * 3 + (dy + 1);
+      bf16x8 bv = zero8();
+      if (m < CIN) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) bv[e] = inr[row][8 * h + e + 1 + dx][m];  // B[voxel][ci = m]
+      }
+      acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[q], 0, 0, 0);
+    }
+    if (w == 0 && h == 0) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) dbacc += (float)dp[e][m];
+    }
+  }
+  // block partials: D[i = co][j = ci]
+  float* out = a.part + (int64_t)blockIdx.x * (kTaps * kCo * CIN + kCo);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    const int t = w + 4 * q;
+    if (t >= kTaps) break;
+    if (m < CIN) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int co = 8 * (r / 4) + 4 * h + (r % 4);
+        out[(t * kCo + co) * CIN + m] = acc[q][r];
+      }
+    }
+  }
+  if (w == 0 && h == 0) out[kTaps * kCo * CIN + m] = dbacc;
+}
+
+// Sums block partials in block order: dw[27*32*CIN], db[32].
+__global__ void wgrad_reduce_kernel(const float* part, int nblocks, int n, float* dw, float* db) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n + kCo) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * (n + kCo) + i];
+  if (i < n) dw[i] = s;
+  else db[i - n] = s;
+}
+
+// ------------------------------------------------- loss, Adam, features
+
+// loss partials and dPre of the last layer: d = 2 (pred - target) / N in
+// channel 0 (BF16), channels 1..31 zero. Interior voxels only.
+__global__ __launch_bounds__(256) void mse_kernel(Vol v, const float* pred, const float* target,
+                                                  double inv_n, bf16* dpre, double* part) {
+  __shared__ double red[kWavesY];
+  double acc = 0.0;
+  const int64_t n = (int64_t)v.X * v.Y * v.Z;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int x = (int)(t % v.X), y = (int)((t / v.X) % v.Y), z = (int)(t / ((int64_t)v.X * v.Y));
+    const int64_t p = v.vox(x, y, z);
+    const double d = (double)pred[p] - (double)target[p];
+    acc += d * d;
+    dpre[p * kCo] = (bf16)(float)(2.0 * d * inv_n);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Adam on FP32 master weights; writes both BF16 layouts.
+struct AdamK {
+  float* w;       // [27][32][cin] master
+  float* b;       // [32]
+  float* mw;
+  float* vw;
+  float* mb;
+  float* vb;
+  const float* gw;
+  const float* gb;
+  bf16* wf;       // [27][32][cin]
+  bf16* wd;       // [27][cin][32]
+  int cin;
+  float lr, b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t
+};
+
+__global__ void adam_kernel(AdamK a) {
+  const int n = kTaps * kCo * a.cin;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const float g = a.gw[i];
+    const float mm = a.b1 * a.mw[i] + (1.0f - a.b1) * g;
+    const float vv = a.b2 * a.vw[i] + (1.0f - a.b2) * g * g;
+    a.mw[i] = mm;
+    a.vw[i] = vv;
+    const float wv = a.w[i] - a.lr * (mm / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+    a.w[i] = wv;
+    const int t = i / (kCo * a.cin), co = (i / a.cin) % kCo, ci = i % a.cin;
+    a.wf[i] = (bf16)wv;
+    a.wd[(t * a.cin + ci) * kCo + co] = (bf16)wv;
+  } else if (i < n + kCo) {
+    const int j = i - n;
+    const float g = a.gb[j];
+    const float mm = a.b1 * a.mb[j] + (1.0f - a.b1) * g;
+    const float vv = a.b2 * a.vb[j] + (1.0f - a.b2) * g * g;
+    a.mb[j] = mm;
+    a.vb[j] = vv;
+    a.b[j] = a.b[j] - a.lr * (mm / a.c1) / (sqrtf(vv / a.c2) + a.eps);
+  }
+}
+
+// BF16 copies of FP32 master weights in both layouts (initialisation).
+__global__ void pack_weights_kernel(const float* w, int cin, bf16* wf, bf16* wd) {
+  const int n = kTaps * kCo * cin;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int t = i / (kCo * cin), co = (i / cin) % kCo, ci = i % cin;
+  wf[i] = (bf16)w[i];
+  wd[(t * cin + ci) * kCo + co] = (bf16)w[i];
+}
+
+// max(|f|, |g|) partials over the interior; g = sum of Dirichlet neighbours.
+__device__ __forceinline__ double lift(const double* u, const ms_grid& g, int i, int j, int k) {
+  const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+  double s = 0.0;
+  if (i == g.nx - 1) s += u[p + 1];
+  if (i == 0) s += u[p - 1];
+  if (j == g.ny - 1) s += u[p + g.sy];
+  if (j == 0) s += u[p - g.sy];
+  if (k == g.nz - 1) s += u[p + g.sz];
+  if (k == 0) s += u[p - g.sz];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void feat_max_kernel(ms_grid g, const double* u,
+                                                       const double* f, double* part) {
+  __shared__ double red[kWavesY];
+  double mx = 0.0;
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    mx = fmax(mx, fabs(lift(u, g, i, j, k)));
+    if (f) mx = fmax(mx, fabs(f[p]));
+  }
+  // block max (order-independent)
+  for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_down(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    part[blockIdx.x] = r;
+  }
+}
+
+__global__ void feat_scale_kernel(const double* part, int nb, double* scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double r = 0.0;
+  for (int b = 0; b < nb; ++b) r = fmax(r, part[b]);
+  *scale = r > 0.0 ? r : 1.0;
+}
+
+// features [f/s, g/s, 0 x 6] in BF16, 8 channels, interior voxels.
+__global__ void feat_write_kernel(ms_grid g, const double* u, const double* f,
+                                  const double* scale, Vol v, bf16* feat) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const double s = *scale;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    bf16x8 val = zero8();
+    val[0] = (bf16)(float)((f ? f[p] : 0.0) / s);
+    val[1] = (bf16)(float)(lift(u, g, i, j, k) / s);
+    *reinterpret_cast<bf16x8*>(feat + v.vox(i, j, k) * 8) = val;
+  }
+}
+
+// guess: x interior = s * lambda * uhat (FP64), halo untouched.
+__global__ void guess_kernel(ms_grid g, const float* uhat, Vol v, const double* scale,
+                             double lambda, double* x) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const double s = *scale * lambda;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    x[p] = s * (double)uhat[v.vox(i, j, k)];
+  }
+}
+
+// target: uhat = u / (s * lambda) in FP32 on the interior (training data).
+__global__ void target_kernel(ms_grid g, const double* u, Vol v, const double* scale,
+                              double lambda, float* out) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const double s = *scale * lambda;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    out[v.vox(i, j, k)] = (float)(u[p] / s);
+  }
+}
+
+int conv_grid_blocks() { return 1024; }
+
+bool cin_ok(int cin) { return cin == 8 || cin == 32; }
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+// ------------------------------------------------------------- C ABI
+
+extern "C" int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, const void* w,
+                               const float* bias, void* out, float* out32, int relu,
+                               void* stream) {
+  clear_error();
+  if (X < 1 || Y < 1 || Z < 1 || !cin_ok(cin) || !in || !w || !bias || (!out && !out32))
+    return set_error(MS_EINVAL, "conv3d_bf16_fwd: bad arguments");
+  FwdK a{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
+         static_cast<bf16*>(out), out32, relu, ((X + 31) / 32) * Y * Z};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (cin == 8)
+    hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int conv3d_bf16_dgrad(int X, int Y, int Z, int cin, const void* dout, const void* wd,
+                                 const void* mask, void* din, void* stream) {
+  clear_error();
+  if (X < 1 || Y < 1 || Z < 1 || !cin_ok(cin) || !dout || !wd || !din)
+    return set_error(MS_EINVAL, "conv3d_bf16_dgrad: bad arguments");
+  DgK a{{X, Y, Z}, static_cast<const bf16*>(dout), static_cast<const bf16*>(wd),
+        static_cast<const bf16*>(mask), static_cast<bf16*>(din), ((X + 31) / 32) * Y * Z};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (cin == 8)
+    hipLaunchKernelGGL(conv_dgrad_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(conv_dgrad_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" size_t conv3d_bf16_wgrad_workspace_bytes(int cin) {
+  if (!cin_ok(cin)) return 0;
+  return (size_t)conv_grid_blocks() * (kTaps * kCo * cin + kCo) * sizeof(float);
+}
+
+extern "C" int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, const void* dpre,
+                                 float* dw, float* db, void* work, size_t work_bytes,
+                                 void* stream) {
+  clear_error();
+  if (X < 1 || Y < 1 || Z < 1 || !cin_ok(cin) || !in || !dpre || !dw || !db)
+    return set_error(MS_EINVAL, "conv3d_bf16_wgrad: bad arguments");
+  const size_t need = conv3d_bf16_wgrad_workspace_bytes(cin);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "conv3d_bf16_wgrad: workspace needs %zu bytes", need);
+  WgK a{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(dpre),
+        static_cast<float*>(work), ((X + 15) / 16) * Y * Z};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nb = conv_grid_blocks();
+  if (cin == 8)
+    hipLaunchKernelGGL(conv_wgrad_kernel<8>, dim3(nb), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(conv_wgrad_kernel<32>, dim3(nb), dim3(256), 0, s, a);
+  MS_LAUNCH_CHECK();
+  const int n = kTaps * kCo * cin;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + kCo + 255) / 256), dim3(256), 0, s,
+                     static_cast<const float*>(work), nb, n, dw, db);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_mse_grad(int X, int Y, int Z, const float* pred, const float* target,
+                            void* dpre, double* loss_part, int nparts, void* stream) {
+  clear_error();
+  if (X < 1 || Y < 1 || Z < 1 || !pred || !target || !dpre || !loss_part || nparts < 1)
+    return set_error(MS_EINVAL, "cnn_mse_grad: bad arguments");
+  const double inv_n = 1.0 / ((double)X * Y * Z);
+  hipLaunchKernelGGL(mse_kernel, dim3(nparts), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     Vol{X, Y, Z}, pred, target, inv_n, static_cast<bf16*>(dpre), loss_part);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_adam(int cin, float* w, float* b, float* mw, float* vw, float* mb, float* vb,
+                        const float* gw, const float* gb, void* wf, void* wd, float lr, int t,
+                        void* stream) {
+  clear_error();
+  if (!cin_ok(cin) || t < 1) return set_error(MS_EINVAL, "cnn_adam: bad arguments");
+  AdamK a{w, b, mw, vw, mb, vb, gw, gb, static_cast<bf16*>(wf), static_cast<bf16*>(wd), cin,
+          lr, 0.9f, 0.999f, 1e-8f, 1.0f - powf(0.9f, (float)t), 1.0f - powf(0.999f, (float)t)};
+  const int n = kTaps * kCo * cin + kCo;
+  hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), a);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_pack_weights(int cin, const float* w, void* wf, void* wd, void* stream) {
+  clear_error();
+  if (!cin_ok(cin) || !w || !wf || !wd) return set_error(MS_EINVAL, "cnn_pack_weights");
+  const int n = kTaps * kCo * cin;
+  hipLaunchKernelGGL(pack_weights_kernel, dim3((n + 255) / 256), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), w, cin, static_cast<bf16*>(wf),
+                     static_cast<bf16*>(wd));
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_features(const ms_grid* g, const double* u, const double* f, void* feat,
+                            double* scale, double* part, int nparts, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "cnn_features")) return rc;
+  if (!u || !feat || !scale || !part || nparts < 1)
+    return set_error(MS_EINVAL, "cnn_features: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(feat_max_kernel, dim3(nparts), dim3(256), 0, s, *g, u, f, part);
+  MS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(feat_scale_kernel, dim3(1), dim3(64), 0, s, part, nparts, scale);
+  MS_LAUNCH_CHECK();
+  hipLaunchKernelGGL(feat_write_kernel, dim3(1024), dim3(256), 0, s, *g, u, f, scale,
+                     Vol{g->nx, g->ny, g->nz}, static_cast<bf16*>(feat));
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_guess(const ms_grid* g, const float* uhat, const double* scale, double lambda,
+                         double* x, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "cnn_guess")) return rc;
+  if (!uhat || !scale || !x) return set_error(MS_EINVAL, "cnn_guess: bad arguments");
+  hipLaunchKernelGGL(guess_kernel, dim3(1024), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     *g, uhat, Vol{g->nx, g->ny, g->nz}, scale, lambda, x);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+extern "C" int cnn_target(const ms_grid* g, const double* u, const double* scale, double lambda,
+                          float* out, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "cnn_target")) return rc;
+  if (!u || !scale || !out) return set_error(MS_EINVAL, "cnn_target: bad arguments");
+  hipLaunchKernelGGL(target_kernel, dim3(1024), dim3(256), 0, static_cast<hipStream_t>(stream),
+                     *g, u, Vol{g->nx, g->ny, g->nz}, scale, lambda, out);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}

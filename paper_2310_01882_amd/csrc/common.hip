@@ -4,6 +4,9 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 namespace ms {
 
@@ -105,29 +108,17 @@ SweepGeom sweep_geom_lds(const ms_grid& g) {
   return s;
 }
 
-SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok) {
+SweepGeom geom_register(const ms_grid& g, int dtype, int vec_ok, int vec, int wx, int rows,
+                        int zc_hint, int64_t target_blocks) {
   SweepGeom s{};
-  const int ev = env_int("MS_SWEEP_VARIANT");
-  s.variant = (getenv("MS_SWEEP_VARIANT") && ev == 0) ? kVariantLds : kVariantRegister;
-  int rows = env_int("MS_SWEEP_ROWS");
-  if (s.variant == kVariantLds) {
-    s.vec = 1;
-    s.wx = 1;
-    s.rows = (rows == 8) ? 8 : 4;
-    s.tiles_x = (g.nx + kTileX - 1) / kTileX;
-    s.tiles_y = (g.ny + kWavesY * s.rows - 1) / (kWavesY * s.rows);
-    split_z(s, g, env_int("MS_SWEEP_ZC"), kTargetBlocks);
-    return s;
-  }
+  s.variant = kVariantRegister;
   const int vmax = dtype == MS_F64 ? 2 : 4;
-  int vec = env_int("MS_SWEEP_VEC");
-  if (vec != 1 && vec != 2 && vec != 4) vec = dtype == MS_F64 ? 2 : 4;
+  if (vec != 1 && vec != 2 && vec != 4) vec = vmax;
   if (vec > vmax) vec = vmax;
   while (vec > vec_ok) vec >>= 1;
   // Narrow grids: do not let a lane hold cells that do not exist.
   while (vec > 1 && 64 * vec > g.nx + 64) vec >>= 1;
   s.vec = vec;
-  int wx = env_int("MS_SWEEP_WX");
   if (wx != 1 && wx != 2 && wx != 4) {
     const int waves_x = (g.nx + 64 * vec - 1) / (64 * vec);
     wx = waves_x >= 2 ? 2 : 1;
@@ -137,8 +128,72 @@ SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok) {
   s.tiles_x = (g.nx + 64 * vec * wx - 1) / (64 * vec * wx);
   const int tile_y = (kWavesY / wx) * s.rows;
   s.tiles_y = (g.ny + tile_y - 1) / tile_y;
-  split_z(s, g, env_int("MS_SWEEP_ZC"), kTargetBlocks);
+  split_z(s, g, zc_hint, target_blocks > 0 ? target_blocks : kTargetBlocks);
   return s;
+}
+
+// ------------------------------------------------------------ tuning table
+
+namespace {
+struct TuneKey {
+  int dtype, nx, ny, nz, vec_ok;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dtype, nx, ny, nz, vec_ok) < std::tie(o.dtype, o.nx, o.ny, o.nz, o.vec_ok);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, ms_tuning> g_tune;
+}  // namespace
+
+bool tuned_lookup(const ms_grid& g, int dtype, int vec_ok, ms_tuning* out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(TuneKey{dtype, g.nx, g.ny, g.nz, vec_ok});
+  if (it == g_tune.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+void tuned_store(const ms_tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[TuneKey{t.dtype, t.nx, t.ny, t.nz, t.vec_ok}] = t;
+}
+
+int tuned_export(ms_tuning* out, int cap) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int n = 0;
+  for (const auto& kv : g_tune) {
+    if (out && n < cap) out[n] = kv.second;
+    ++n;
+  }
+  return n;
+}
+
+void tuned_clear() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok) {
+  const int ev = env_int("MS_SWEEP_VARIANT");
+  const bool forced = getenv("MS_SWEEP_VARIANT") || getenv("MS_SWEEP_VEC") ||
+                      getenv("MS_SWEEP_ROWS") || getenv("MS_SWEEP_WX") || getenv("MS_SWEEP_ZC");
+  if (getenv("MS_SWEEP_VARIANT") && ev == 0) {
+    SweepGeom s{};
+    s.variant = kVariantLds;
+    s.vec = 1;
+    s.wx = 1;
+    const int rows = env_int("MS_SWEEP_ROWS");
+    s.rows = (rows == 8) ? 8 : 4;
+    s.tiles_x = (g.nx + kTileX - 1) / kTileX;
+    s.tiles_y = (g.ny + kWavesY * s.rows - 1) / (kWavesY * s.rows);
+    split_z(s, g, env_int("MS_SWEEP_ZC"), kTargetBlocks);
+    return s;
+  }
+  ms_tuning t{};
+  if (!forced && tuned_lookup(g, dtype, vec_ok, &t))
+    return geom_register(g, dtype, vec_ok, t.vec, t.wx, t.rows, 0, t.target_blocks);
+  return geom_register(g, dtype, vec_ok, env_int("MS_SWEEP_VEC"), env_int("MS_SWEEP_WX"),
+                       env_int("MS_SWEEP_ROWS"), env_int("MS_SWEEP_ZC"), kTargetBlocks);
 }
 
 }  // namespace ms

@@ -801,10 +801,10 @@ SweepGeom tb2_geom(const ms_grid& g) {
   s.tiles_x = (g.nx + kTbX - 1) / kTbX;
   s.tiles_y = (g.ny + kTbY - 1) / kTbY;
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
-  // about two resident blocks per CU, long z marches (>= 8 levels);
-  // MS_TB_BLOCKS overrides the target for tuning
+  // about eight blocks per CU (measured best at 512^3 FP64), marches of at
+  // least 8 levels; MS_TB_BLOCKS overrides the target for tuning
   const char* ev = getenv("MS_TB_BLOCKS");
-  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 512;
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 2048;
   int64_t chunks = (want + tiles2d - 1) / tiles2d;
   int zc = (int)((g.nz + chunks - 1) / chunks);
   if (zc < 8) zc = 8;

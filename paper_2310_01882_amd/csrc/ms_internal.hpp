@@ -111,6 +111,16 @@ int vec_alignment(const ms_grid& g, int dtype, const void* const* ptrs, int n);
 SweepGeom sweep_geom(const ms_grid& g, int dtype, int vec_ok);
 // LDS-tiled geometry with 4 rows per thread (standalone residual passes).
 SweepGeom sweep_geom_lds(const ms_grid& g);
+// Register-tiled geometry with explicit parameters (0 picks a default).
+SweepGeom geom_register(const ms_grid& g, int dtype, int vec_ok, int vec, int wx, int rows,
+                        int zc_hint, int64_t target_blocks);
+
+// Process-wide table of tuned sweep geometries (filled by the autotuner,
+// consulted by sweep_geom unless an MS_SWEEP_* override is set).
+bool tuned_lookup(const ms_grid& g, int dtype, int vec_ok, ms_tuning* out);
+void tuned_store(const ms_tuning& t);
+int tuned_export(ms_tuning* out, int cap);
+void tuned_clear();
 
 // Maps hardware block ids so that consecutive tiles share an XCD: blocks are
 // dispatched round-robin over the 8 XCDs, each with its own L2.

@@ -594,3 +594,82 @@ extern "C" int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
   if (o->precision == MS_SOLVE_F64) return solve_f64(*g, *o, u, f, ws, hist_host, res, s);
   return solve_refined(*g, *o, u, f, ws, hist_host, res, s);
 }
+
+// ---------------------------------------------------------------- autotuner
+
+extern "C" int ms_autotune_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                                  const void* f, int sweeps_per_trial, void* work,
+                                  size_t work_bytes, ms_tuning* best, void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "ms_autotune_sweeps")) return rc;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "ms_autotune_sweeps: dtype %d", dtype);
+  if (!u || !u_tmp || !best || sweeps_per_trial < 1)
+    return set_error(MS_EINVAL, "ms_autotune_sweeps: bad arguments");
+  if (!work || work_bytes < jacobi_sweeps_workspace_bytes(g))
+    return set_error(MS_EWORKSPACE, "ms_autotune_sweeps: workspace too small");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const void* ptrs[3] = {u, u_tmp, f};
+  const int vec_ok = vec_alignment(*g, dtype, ptrs, 3);
+  double* partials = static_cast<double*>(work);
+  void* bufs[3] = {u, u_tmp, u};
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  MS_HIP_TRY(hipEventCreate(&e0));
+  MS_HIP_TRY(hipEventCreate(&e1));
+  ms_tuning out{};
+  out.us_per_sweep = 1e300;
+  const int vmax = dtype == MS_F64 ? 2 : 4;
+  int rc = MS_OK;
+  for (int vec = vmax; vec >= 1 && rc == MS_OK; vec >>= 1) {
+    if (vec > vec_ok) continue;
+    for (int wx : {1, 2, 4})
+      for (int rows : {2, 4, 8})
+        for (int64_t tb : {256, 512, 1024, 2048}) {
+          const SweepGeom geo = geom_register(*g, dtype, vec_ok, vec, wx, rows, 0, tb);
+          if (geo.vec != vec || geo.nblocks > kMaxBlocks) continue;
+          // one untimed sweep, then the timed trial
+          for (int k = 0; k <= sweeps_per_trial && rc == MS_OK; ++k) {
+            if (k == 1) (void)hipEventRecord(e0, s);
+            rc = launch_sweep(*g, dtype, bufs, 2, f, partials, nullptr, nullptr, k, geo, s);
+          }
+          if (rc) break;
+          (void)hipEventRecord(e1, s);
+          if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = set_error(MS_EHIP, "ms_autotune_sweeps: timing failed");
+            break;
+          }
+          float ms_el = 0.0f;
+          (void)hipEventElapsedTime(&ms_el, e0, e1);
+          const double us = 1e3 * ms_el / sweeps_per_trial;
+          if (us < out.us_per_sweep) {
+            out.dtype = dtype; out.nx = g->nx; out.ny = g->ny; out.nz = g->nz;
+            out.vec_ok = vec_ok; out.vec = geo.vec; out.wx = geo.wx; out.rows = geo.rows;
+            out.target_blocks = tb; out.us_per_sweep = us;
+          }
+        }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  tuned_store(out);
+  *best = out;
+  return MS_OK;
+}
+
+extern "C" int ms_tuning_get(ms_tuning* out, int cap) { return tuned_export(out, cap); }
+
+extern "C" int ms_tuning_set(const ms_tuning* in, int n) {
+  clear_error();
+  if (n < 0 || (n > 0 && !in)) return set_error(MS_EINVAL, "ms_tuning_set: bad arguments");
+  for (int i = 0; i < n; ++i) {
+    const ms_tuning& t = in[i];
+    if ((t.dtype != MS_F64 && t.dtype != MS_F32) || t.nx < 1 || t.ny < 1 || t.nz < 1 ||
+        (t.vec != 1 && t.vec != 2 && t.vec != 4) || (t.wx != 1 && t.wx != 2 && t.wx != 4) ||
+        (t.rows != 2 && t.rows != 4 && t.rows != 8) || t.target_blocks < 1)
+      return set_error(MS_EINVAL, "ms_tuning_set: entry %d is not a valid shape", i);
+    tuned_store(t);
+  }
+  return MS_OK;
+}
+
+extern "C" void ms_tuning_clear(void) { tuned_clear(); }

@@ -136,3 +136,17 @@ def test_advect_rejects_aliasing_outputs():
     rc = ms.lib.advect_source(ctypes.byref(g), p[0], p[1], p[2], p[3], p[4], 0.25, 0.25, p[0],
                               p[5], p[6], None)
     assert rc == ms.MS_EINVAL
+
+
+def test_tuning_table_round_trip_without_a_device():
+    import paper_2310_01882_amd as ms
+    ms.tuning_clear()
+    e = dict(dtype=0, nx=64, ny=32, nz=16, vec_ok=2, vec=2, wx=1, rows=4, target_blocks=512,
+             us_per_sweep=12.5)
+    ms.tuning_load([e])
+    assert ms.tuning_table() == [e]
+    bad = dict(e, rows=3)
+    with pytest.raises(ms.MsError):
+        ms.tuning_load([bad])
+    ms.tuning_clear()
+    assert ms.tuning_table() == []

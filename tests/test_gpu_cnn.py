@@ -1,0 +1,186 @@
+"""GPU warm-start kernels against the CNN oracle (BF16 inputs and weights,
+FP32 accumulation on the device vs FP64 on the host)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpuhelp import dev, note
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_01882_amd as ms  # noqa: E402
+from paper_2310_01882_amd import warmstart as wsm  # noqa: E402
+
+X, Y, Z = 40, 6, 5  # x not a multiple of the 32-voxel wave tile
+
+
+def _bf16_act(a, cpad):
+    """[C, Z, Y, X] float array -> zero-haloed channels-last BF16 device tensor."""
+    c, z, y, x = a.shape
+    t = torch.zeros((z + 2, y + 2, x + 2, cpad), dtype=torch.float32)
+    t[1:-1, 1:-1, 1:-1, :c] = torch.from_numpy(np.transpose(a, (1, 2, 3, 0)).copy())
+    return t.to(torch.bfloat16).cuda().reshape(-1)
+
+
+def _act_np(t, c, cpad, shape=(X, Y, Z)):
+    x, y, z = shape
+    a = t.float().view(z + 2, y + 2, x + 2, cpad)[1:-1, 1:-1, 1:-1, :c].cpu().numpy()
+    return np.transpose(a, (3, 0, 1, 2)).astype(np.float64)
+
+
+def _weights(cin, cinp, cout, seed, scale=0.2):
+    w = np.zeros((27, 32, cinp), np.float32)
+    w[:, :cout, :cin] = scale * synth.rng(seed).standard_normal((27, cout, cin))
+    wf = torch.empty(27 * 32 * cinp, dtype=torch.bfloat16, device="cuda")
+    wd = torch.empty_like(wf)
+    wt = torch.from_numpy(w).cuda()
+    assert ms.lib.cnn_pack_weights(cinp, ms._ptr(wt), ms._ptr(wf), ms._ptr(wd), None) == 0
+    return w, wf, wd
+
+
+def _close(got, want, tol=1e-2):
+    g, w = got.ravel(), want.ravel()
+    cos = float(g @ w / (np.linalg.norm(g) * np.linalg.norm(w) + 1e-300))
+    rel = float(np.linalg.norm(g - w) / (np.linalg.norm(w) + 1e-300))
+    assert cos >= 0.999 and rel <= tol, (cos, rel)
+
+
+@pytest.mark.parametrize("cin,cinp,relu", [(2, 8, True), (32, 32, True), (32, 32, False)])
+def test_forward_conv_matches_oracle(cin, cinp, relu):
+    x = cnn.round_bf16(synth.rng(1).standard_normal((cin, Z, Y, X)))
+    w, wf, wd = _weights(cin, cinp, 32, 2)
+    b = (0.1 * synth.rng(3).standard_normal(32)).astype(np.float32)
+    bt = torch.from_numpy(b).cuda()
+    xin = _bf16_act(x, cinp)
+    out = torch.zeros((Z + 2) * (Y + 2) * (X + 2) * 32, dtype=torch.bfloat16, device="cuda")
+    out32 = torch.zeros((Z + 2, Y + 2, X + 2), dtype=torch.float32, device="cuda")
+    rc = ms.lib.conv3d_bf16_fwd(X, Y, Z, cinp, ms._ptr(xin), ms._ptr(wf), ms._ptr(bt),
+                                ms._ptr(out), ms._ptr(out32), int(relu), None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    wo = cnn.round_bf16(wsm.to_oracle_weights(w, cin, 32))
+    ref = cnn.conv3d(x, wo, b.astype(np.float64))
+    if relu:
+        ref = np.maximum(ref, 0.0)
+    got = _act_np(out, 32, 32)
+    # one BF16 rounding of an FP32 vs an FP64 sum: within 2^-8 relative
+    assert np.all(np.abs(got - cnn.round_bf16(ref)) <= 2.0 ** -7 * np.abs(ref) + 1e-6)
+    got32 = out32[1:-1, 1:-1, 1:-1].cpu().numpy().astype(np.float64)
+    mag = cnn.conv3d(np.abs(x), np.abs(wo), np.abs(b.astype(np.float64)))[0]
+    assert np.all(np.abs(got32 - ref[0]) <= 1e-5 * mag + 1e-7)
+    # the halo of the output stays zero
+    o = out.float().view(Z + 2, Y + 2, X + 2, 32)
+    assert torch.all(o[0] == 0) and torch.all(o[:, :, -1] == 0)
+
+
+@pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
+def test_dgrad_and_wgrad_match_oracle(cin, cinp):
+    r = synth.rng(4)
+    x = cnn.round_bf16(np.maximum(r.standard_normal((cin, Z, Y, X)), 0.0))  # a ReLU output
+    g = cnn.round_bf16(r.standard_normal((32, Z, Y, X)))
+    w, wf, wd = _weights(cin, cinp, 32, 5)
+    wo = cnn.round_bf16(wsm.to_oracle_weights(w, cin, 32))
+    xin, gin = _bf16_act(x, cinp), _bf16_act(g, 32)
+    din = torch.zeros_like(xin)
+    assert ms.lib.conv3d_bf16_dgrad(X, Y, Z, cinp, ms._ptr(gin), ms._ptr(wd), ms._ptr(xin),
+                                    ms._ptr(din), None) == 0
+    dw = torch.zeros(27 * 32 * cinp, dtype=torch.float32, device="cuda")
+    db = torch.zeros(32, dtype=torch.float32, device="cuda")
+    work = torch.empty(ms.lib.conv3d_bf16_wgrad_workspace_bytes(cinp), dtype=torch.uint8,
+                       device="cuda")
+    assert ms.lib.conv3d_bf16_wgrad(X, Y, Z, cinp, ms._ptr(xin), ms._ptr(gin), ms._ptr(dw),
+                                    ms._ptr(db), ms._ptr(work), work.numel(), None) == 0
+    torch.cuda.synchronize()
+    ref_dx = cnn.conv3d_dgrad(g, wo) * (x > 0)
+    _close(_act_np(din, cin, cinp), ref_dx)
+    ref_dw, ref_db = cnn.conv3d_wgrad(x, g)
+    got_dw = wsm.to_oracle_weights(dw.cpu().numpy().reshape(27, 32, cinp), cin, 32)
+    np.testing.assert_allclose(got_dw, ref_dw, rtol=1e-4, atol=1e-4)
+    np.testing.assert_allclose(db.cpu().numpy(), ref_db, rtol=1e-4, atol=1e-4)
+
+
+def test_adam_matches_oracle():
+    w, wf, wd = _weights(32, 32, 32, 6)
+    wt = torch.from_numpy(w).cuda()
+    b = torch.zeros(32, dtype=torch.float32, device="cuda")
+    mw, vw = torch.zeros_like(wt), torch.zeros_like(wt)
+    mb, vb = torch.zeros_like(b), torch.zeros_like(b)
+    g1 = synth.rng(7).standard_normal(w.shape).astype(np.float32)
+    g2 = synth.rng(8).standard_normal(w.shape).astype(np.float32)
+    gb = torch.ones(32, dtype=torch.float32, device="cuda")
+    pw, m, v = w.astype(np.float64), np.zeros(w.shape), np.zeros(w.shape)
+    for t, g in ((1, g1), (2, g2)):
+        gt = torch.from_numpy(g).cuda()
+        assert ms.lib.cnn_adam(32, ms._ptr(wt), ms._ptr(b), ms._ptr(mw), ms._ptr(vw), ms._ptr(mb),
+                               ms._ptr(vb), ms._ptr(gt), ms._ptr(gb), ms._ptr(wf), ms._ptr(wd),
+                               ctypes.c_float(1e-3), t, None) == 0
+        pw = cnn.adam_step(pw, g.astype(np.float64), m, v, t)
+    np.testing.assert_allclose(wt.cpu().numpy(), pw, rtol=1e-5, atol=1e-7)
+    # the BF16 copies are the rounded master weights, in both layouts
+    assert np.array_equal(wf.float().cpu().numpy(), cnn.round_bf16(wt.cpu().numpy()).ravel())
+    wdn = wd.float().cpu().numpy().reshape(27, 32, 32)
+    assert np.array_equal(np.transpose(wdn, (0, 2, 1)), cnn.round_bf16(wt.cpu().numpy()))
+
+
+def test_features_match_oracle():
+    nx, ny, nz = 20, 12, 9
+    u = synth.dirichlet_uniform(nx, ny, nz, 3)
+    f = synth.gaussian_sources(nx, ny, nz, 3, 4)
+    net = wsm.WarmStart(nx, ny, nz, seed=1)
+    net.features(dev(u), dev(f))
+    want, s = cnn.features(u, f)
+    assert net.scale.item() == s
+    got = net.act_numpy(net.feat, 8)[:2]
+    assert np.array_equal(got, cnn.round_bf16(want))
+
+
+def test_full_network_step_matches_oracle():
+    """Forward, loss gradient and every weight gradient of the whole network
+    against the oracle's BF16-emulating network (cosine >= 0.999, relative
+    L2 <= 1e-2)."""
+    note("case: warm-start network step 33x10x8")
+    nx, ny, nz = 33, 10, 8
+    u = synth.dirichlet_uniform(nx, ny, nz, 5)
+    f = synth.gaussian_sources(nx, ny, nz, 4, 6)
+    target = synth.rng(7).standard_normal((nz, ny, nx)).astype(np.float32)
+    net = wsm.WarmStart(nx, ny, nz, seed=11)
+    params0 = net.params()
+    du, df = dev(u), dev(f)
+    tt = torch.zeros((nz + 2, ny + 2, nx + 2), dtype=torch.float32, device="cuda")
+    tt[1:-1, 1:-1, 1:-1] = torch.from_numpy(target)
+    out = net.forward(du, df)
+    loss = net.backward(tt).item()
+    torch.cuda.synchronize()
+    feats, s = cnn.features(u, f)
+    oparams = [(wsm.to_oracle_weights(w, cin, cout), b[:cout].astype(np.float64))
+               for (w, b), (cin, _, cout, _) in zip(params0, wsm.LAYERS)]
+    onet = cnn.Net(oparams, bf16=True)
+    ref = onet.forward(feats)[0]
+    _close(out[1:-1, 1:-1, 1:-1].cpu().numpy().astype(np.float64), ref)
+    ref_loss, gout = cnn.mse_and_grad(ref, target.astype(np.float64))
+    assert loss == pytest.approx(ref_loss, rel=1e-2)
+    grads = onet.backward(gout[None])
+    for li, ((cin, cinp, cout, _), (gw, gb)) in enumerate(zip(wsm.LAYERS, grads)):
+        got_w = wsm.to_oracle_weights(net.gw[li].cpu().numpy(), cin, cout)
+        _close(got_w, gw, tol=3e-2)
+        _close(net.gb[li].cpu().numpy()[:cout].astype(np.float64), gb, tol=3e-2)
+
+
+def test_training_reduces_the_loss_on_one_instance():
+    nx, ny, nz = 32, 32, 16
+    u = synth.zeros(nx, ny, nz)
+    f = synth.gaussian_sources(nx, ny, nz, 3, 9)
+    du, df = dev(u), dev(f)
+    x = dev(u)
+    ms.jacobi_solve(x, df, rel_tol=1e-8)
+    net = wsm.WarmStart(nx, ny, nz, seed=2)
+    net.features(du, df)
+    tgt = net.target(x)
+    losses = [net.train_step(du, df, tgt, lr=3e-3).item() for _ in range(60)]
+    assert losses[-1] < 0.5 * losses[0]

@@ -228,3 +228,19 @@ def test_temporal_blocking_at_benchmark_size():
         del u, t
     assert torch.equal(outs[0][0], outs[1][0])
     np.testing.assert_allclose(host(outs[0][1]), host(outs[1][1]), rtol=NORM_RTOL)
+
+
+def test_autotuned_shape_is_used_and_bit_exact():
+    nx, ny, nz = 200, 40, 30
+    u, f = _problem(nx, ny, nz, seed=17)
+    du, dt, df = ms.field_from(u), ms.field_from(u), ms.field_from(f)
+    ms.tuning_clear()
+    best = ms.autotune_sweeps(du, dt, df, sweeps_per_trial=2)
+    assert best["nx"] == nx and best["us_per_sweep"] > 0
+    assert ms.tuning_table() == [best]
+    du, dt = ms.field_from(u), ms.field_from(u)
+    res = torch.zeros(4, dtype=torch.float64, device="cuda")
+    out = ms.jacobi_sweeps(du, dt, 3, f=df, res=res)
+    want, hist = oracle.jacobi_sweeps(u, f, 3)
+    assert np.array_equal(host(out), want)
+    ms.tuning_clear()
