@@ -12,7 +12,9 @@ three solves to a 1e-8 relative residual on the same GPU:
   A plain FP64 Jacobi from the zero interior,
   B FP32-refined Jacobi from the zero interior,
   C the network's guess, then FP32-refined Jacobi (falls back to the zero
-    interior when the guess's residual is not below the zero guess's).
+    interior when the guess's residual is not below the zero guess's),
+  D the network's guess, then FP32-refined Jacobi, without the fallback.
+The report also gives the guess's relative error against A's answer.
 """
 
 from __future__ import annotations
@@ -64,6 +66,9 @@ def solve_targets(ms, wsm, net, n, seeds, batch, tol):
     return fs, targets
 
 
+NAMES = ("A_fp64", "B_fp32_refined", "C_cnn_fp32_refined", "D_cnn_always")
+
+
 def evaluate(ms, wsm, net, n, seeds, tol):
     import torch
     rows = []
@@ -71,33 +76,40 @@ def evaluate(ms, wsm, net, n, seeds, tol):
         u, f = instance(n, s)
         fd = ms.field_from(f)
         row = {"seed": s}
-        for name in ("A_fp64", "B_fp32_refined", "C_cnn_fp32_refined"):
+        xa = None
+        for name in NAMES:
             x = ms.field_from(u)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             used_guess = False
-            if name == "C_cnn_fp32_refined":
+            if name in ("C_cnn_fp32_refined", "D_cnn_always"):
                 net.guess(x, fd, x)
                 r_guess = ms.residual_norm(x, fd)
                 r_zero = ms.residual_norm(ms.field_from(u), fd)
-                used_guess = r_guess < r_zero
+                used_guess = name == "D_cnn_always" or r_guess < r_zero
                 if not used_guess:
                     x.copy_(ms.field_from(u))
+                if xa is not None and name == "D_cnn_always":
+                    gi, ai = x[1:-1, 1:-1, 1:-1], xa[1:-1, 1:-1, 1:-1]
+                    row["guess_rel_error"] = float(torch.linalg.norm(gi - ai) /
+                                                   torch.linalg.norm(ai))
             prec = ms.MS_SOLVE_F64 if name == "A_fp64" else ms.MS_SOLVE_F32_REFINED
             info = ms.jacobi_solve(x, fd, precision=prec, rel_tol=tol)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             row[name] = {"seconds": dt, "sweeps": info.sweeps, "rel_final": info.rel_final,
                          "outer": info.outer_iters}
-            if name == "C_cnn_fp32_refined":
+            if name == "A_fp64":
+                xa = x
+            if name in ("C_cnn_fp32_refined", "D_cnn_always"):
                 row[name]["guess_used"] = used_guess
                 row[name]["guess_rel_residual"] = r_guess / r_zero if r_zero > 0 else 0.0
         rows.append(row)
         log(f"[eval] seed {s}: " + ", ".join(
-            f"{k} {row[k]['seconds']:.3f}s/{row[k]['sweeps']}" for k in
-            ("A_fp64", "B_fp32_refined", "C_cnn_fp32_refined")))
+            f"{k} {row[k]['seconds']:.3f}s/{row[k]['sweeps']}" for k in NAMES)
+            + f"; guess rel error {row.get('guess_rel_error', float('nan')):.3e}")
     summ = {}
-    for k in ("A_fp64", "B_fp32_refined", "C_cnn_fp32_refined"):
+    for k in NAMES:
         ts = [r[k]["seconds"] for r in rows]
         sw = [r[k]["sweeps"] for r in rows]
         summ[k] = {"mean_seconds": statistics.mean(ts), "median_seconds": statistics.median(ts),
@@ -106,6 +118,8 @@ def evaluate(ms, wsm, net, n, seeds, tol):
     summ["C_guess_used_fraction"] = sum(r["C_cnn_fp32_refined"]["guess_used"] for r in rows) / len(rows)
     summ["C_mean_guess_rel_residual"] = statistics.mean(
         r["C_cnn_fp32_refined"]["guess_rel_residual"] for r in rows)
+    summ["mean_guess_rel_error"] = statistics.mean(r.get("guess_rel_error", float("nan"))
+                                                   for r in rows)
     return summ, rows
 
 
