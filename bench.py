@@ -8,11 +8,13 @@ of its input fused in, plus the trailing residual of the last iterate.
 Inputs are generated on the host, copied to HBM, and resident before the
 timed region. Prints ONE JSON line on stdout (progress goes to stderr).
 
-    python bench.py [--steps K] [--warmup W] [--mode jacobi|f32|advect|solve]
+    python bench.py [--steps K] [--warmup W] [--mode jacobi|f32|advect|solve|batched]
 
 Other modes time the FP32-storage sweeps (same grid), the advection source
-term (512 x 512 x 256, one pass per step) and the time to a 1e-8 relative
-residual at 128^3 for plain FP64 vs FP32-refined solves.
+term (512 x 512 x 256, one pass per step), the time to a 1e-8 relative
+residual at 128^3 for plain FP64 vs FP32-refined solves, and the batched
+persistent solve of 64 uneven instances (FP32-refined to 1e-8; one step =
+one batch).
 """
 
 from __future__ import annotations
@@ -248,40 +250,230 @@ def bench_advect(args):
     }
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2310_01882_amd", "weights", "warmstart_128.npz")
+
+
 def bench_solve(args):
-    """Time to a 1e-8 relative residual at 128^3 (8 Gaussian sources, zero
-    Dirichlet boundary, zero start): plain FP64 vs FP32-refined."""
+    """Time to a 1e-8 relative residual at 128^3 (8 Gaussian sources, seed 1,
+    zero Dirichlet boundary, zero start) on aligned fields, median of
+    --solve-reps timed solves after one warm-up each:
+      fp64                     plain FP64 Jacobi (one sweep per launch)
+      fp64_tb2                 the same with two sweeps per pass
+      fp32_refined(_tb2)       FP32 sweeps inside FP64 refinement
+      fp32_refined_persistent  the same through the persistent batched kernel
+      cnn_fp32_refined         the trained warm start's guess (zero interior
+                               if its residual is not smaller), then the
+                               fastest FP32-refined variant; the guess's
+                               features and forward pass are inside the
+                               timed region (needs the committed weights)
+    `value` is cnn_fp32_refined when the weights are present, else the
+    fastest FP32-refined variant; `fp64` is the plain baseline."""
+    import statistics
     import torch
     import paper_2310_01882_amd as ms
     import synth
 
     n = args.solve_n
     f_h = synth.gaussian_sources(n, n, n, 8, 1)
-    dev = torch.device("cuda:0")
-    f = torch.from_numpy(f_h).to(dev)
+    u_h = synth.zeros(n, n, n)
+    f = ms.field_from(f_h)
+    u0 = ms.field_from(u_h)
+    F64, F32R = ms.MS_SOLVE_F64, ms.MS_SOLVE_F32_REFINED
+    variants = [("fp64", dict(precision=F64)),
+                ("fp64_tb2", dict(precision=F64, temporal_block=2)),
+                ("fp32_refined", dict(precision=F32R)),
+                ("fp32_refined_tb2", dict(precision=F32R, temporal_block=2))]
     rows = {}
-    for name, kw in (("fp64", dict(precision=ms.MS_SOLVE_F64)),
-                     ("fp32_refined", dict(precision=ms.MS_SOLVE_F32_REFINED, inner_eta=1e-4))):
-        u = torch.zeros((n + 2,) * 3, dtype=torch.float64, device=dev)
-        work = ms.jacobi_workspace(u, ms.solve_opts(**kw))
-        ms.jacobi_solve(u.clone(), f, work=work, rel_tol=1e-3, **kw)  # warm-up (graphs, caches)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        info = ms.jacobi_solve(u, f, work=work, rel_tol=1e-8, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        rows[name] = {"seconds": round(dt, 4), "sweeps": info.sweeps,
-                      "outer": info.outer_iters, "rel_final": info.rel_final,
+
+    def record(name, times, info):
+        dt = statistics.median(times)
+        rows[name] = {"seconds": round(dt, 4), "seconds_all": [round(t, 4) for t in times],
+                      "sweeps": info.sweeps, "outer": info.outer_iters,
+                      "rel_final": info.rel_final,
                       "glups": round(n ** 3 * info.sweeps / dt / 1e9, 2)}
         log(f"[bench] {name}: {dt:.3f} s, {info.sweeps} sweeps, rel {info.rel_final:.3e}")
+
+    for name, kw in variants:
+        work = ms.jacobi_workspace(u0, ms.solve_opts(**kw))
+        ms.jacobi_solve(u0.clone(), f, work=work, rel_tol=1e-3, **kw)  # warm-up (graphs, caches)
+        times = []
+        for _ in range(args.solve_reps):
+            u = u0.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            info = ms.jacobi_solve(u, f, work=work, rel_tol=1e-8, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        record(name, times, info)
+    times = []
+    for rep in range(args.solve_reps + 1):
+        u = u0.clone()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = ms.jacobi_solve_batched([u], [f], precision=F32R, rel_tol=1e-8 if rep else 1e-3)[0]
+        torch.cuda.synchronize()
+        if rep:
+            times.append(time.perf_counter() - t)
+    record("fp32_refined_persistent", times, info)
+    fp32_names = ["fp32_refined", "fp32_refined_tb2", "fp32_refined_persistent"]
+    best32 = min(fp32_names, key=lambda k: rows[k]["seconds"])
+    value_name = best32
+    if os.path.exists(WEIGHTS):
+        from paper_2310_01882_amd import warmstart as wsm
+        net = wsm.WarmStart(n, n, n, params=wsm.WarmStart.load_params(WEIGHTS))
+        kw = dict(variants)[best32] if best32 != "fp32_refined_persistent" else None
+        times, used = [], []
+        for rep in range(args.solve_reps + 1):
+            x = u0.clone()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            net.guess(x, f, x)
+            use = ms.residual_norm(x, f) < ms.residual_norm(u0, f)
+            if not use:
+                x.copy_(u0)
+            tol = 1e-8 if rep else 1e-3
+            if kw is None:
+                info = ms.jacobi_solve_batched([x], [f], precision=F32R, rel_tol=tol)[0]
+            else:
+                info = ms.jacobi_solve(x, f, rel_tol=tol, **kw)
+            torch.cuda.synchronize()
+            if rep:
+                times.append(time.perf_counter() - t)
+                used.append(bool(use))
+        record("cnn_fp32_refined", times, info)
+        rows["cnn_fp32_refined"]["solver"] = best32
+        rows["cnn_fp32_refined"]["guess_used"] = used
+        value_name = "cnn_fp32_refined"
+    v = rows[value_name]["seconds"]
     return {
-        "metric": "seconds to 1e-8 relative residual (128^3 Poisson)",
-        "value": rows["fp32_refined"]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
-        "warmup": 1, "ms_per_step": rows["fp32_refined"]["seconds"] * 1e3,
-        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": f"poisson_{n}cubed_to_1e-8", "rhs": "8 Gaussian sources (seed 1)"},
+        "metric": "seconds to 1e-8 relative residual (128^3 Poisson): learned/FP32 vs plain FP64",
+        "value": v, "unit": "s", "n_gpus": 1, "steps": args.solve_reps, "warmup": 1,
+        "ms_per_step": round(v * 1e3, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"poisson_{n}cubed_to_1e-8", "rhs": "8 Gaussian sources (seed 1)",
+                   "boundary": "zero Dirichlet", "value_is": value_name,
+                   "parallelism": "single GPU"},
+        "speedup_vs_fp64": round(rows["fp64"]["seconds"] / v, 3),
         "solves": rows,
+    }
+
+
+def bench_batched(args):
+    """64 instances, per-axis sizes log-uniform in [32, 256] (seed 4), each with
+    8 Gaussian sources (seed 4000 + i) and a zero Dirichlet boundary, solved
+    from zero to a 1e-8 relative residual by FP32 sweeps inside FP64
+    refinement, all in one persistent launch per step. The tile shapes come
+    from the batched autotuner, run once before the timed region."""
+    import numpy as np
+    import torch
+    import paper_2310_01882_amd as ms
+    import synth
+
+    dims = synth.batch_sizes(64, 4)
+    log(f"[bench] generating 64 batched instances ({sum(a * b * c for a, b, c in dims) / 1e6:.1f}"
+        " M cells)")
+    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 4000 + i)) for i, d in enumerate(dims)]
+    x0 = [ms.field_from(u) for u, _ in probs]
+    xs = [ms.field_from(u) for u, _ in probs]
+    fs = [ms.field_from(f) for _, f in probs]
+    opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, max_outer=40)
+    stream = torch.cuda.current_stream()
+    cells = np.array([a * b * c for a, b, c in dims], dtype=np.float64)
+
+    def reset():
+        for x, a in zip(xs, x0):
+            x.copy_(a)
+        torch.cuda.synchronize()
+
+    def timed_batch(label):
+        reset()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        infos = ms.jacobi_solve_batched(xs, fs, stream=stream, **opts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        dt = e0.elapsed_time(e1) / 1e3
+        log(f"[bench] {label}: {dt:.3f} s, sweeps {min(i.sweeps for i in infos)}.."
+            f"{max(i.sweeps for i in infos)}, worst rel {max(i.rel_final for i in infos):.3e}")
+        return dt, infos
+
+    ms.batch_tuning_clear()
+    untuned_s, _ = timed_batch("default tile shapes")
+    t = time.perf_counter()
+    best = ms.batched_autotune(xs, fs, sweeps_per_trial=20, **opts)
+    tune_s = time.perf_counter() - t
+    shapes = {}
+    for b in best:
+        key = f"{b['tx']}x{b['zsplit']}"
+        shapes[key] = shapes.get(key, 0) + 1
+    log(f"[bench] autotune {tune_s:.2f} s; shapes (tx x zsplit): {shapes}")
+    for _ in range(args.warmup):
+        timed_batch("warm-up")
+    secs, infos = [], None
+    for k in range(args.steps):
+        dt, infos = timed_batch(f"step {k + 1}/{args.steps}")
+        secs.append(dt)
+    mean_s = sum(secs) / len(secs)
+    sweeps = np.array([i.sweeps for i in infos], dtype=np.float64)
+    outer = np.array([i.outer_iters for i in infos], dtype=np.float64)
+    lups = float((cells * sweeps).sum())
+    glups = lups / mean_s / 1e9
+    # algorithmic HBM bytes: 12 per FP32 inner update (e, rhat in; e out);
+    # per outer step 16 (norm: x, f) + 24 (rhat: x, f in; rhat, e0 out) + 20
+    # (update: x, e in; x out) per cell; 16 per cell for the first norm
+    nbytes = float((cells * (12 * sweeps + 60 * outer + 16)).sum())
+    achieved = nbytes / mean_s / 1e9
+    # the same instances one by one through the single-instance solve
+    seq = None
+    if not args.no_sequential:
+        reset()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for x, f in zip(xs, fs):
+            ms.jacobi_solve(x, f, stream=stream, **opts)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        seq = round(t0.elapsed_time(t1) / 1e3, 4)
+        log(f"[bench] the same 64 solves one by one: {seq:.3f} s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = probs[:6]
+        t = time.perf_counter()
+        lup = 0
+        for u, f in sample:
+            uf, ff = u.astype(np.float32), f.astype(np.float32)
+            for _ in range(2):
+                oracle.residual_norm_f32_storage(uf, ff)
+                uf = oracle.sweep_f32(uf, ff)
+            lup += 2 * (u.shape[0] - 2) * (u.shape[1] - 2) * (u.shape[2] - 2)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(lup / dt / 1e9, 5), "unit": "GLUP/s", "cores": 1, "kind": "oracle",
+               "sample": "2 FP32 sweeps + FP64 norms of each of the first 6 instances "
+                         "(numpy, one thread)", "seconds": round(dt, 2)}
+    return {
+        "metric": "GLUP/s (batched persistent FP32-refined Poisson solves to 1e-8, 64 instances)",
+        "value": round(glups, 3), "unit": "GLUP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(mean_s * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "batched_poisson_64x_loguniform_32_256_to_1e-8",
+                   "instances": 64, "size_seed": 4, "cells": int(cells.sum()),
+                   "rhs": "8 Gaussian sources per instance (seed 4000+i)",
+                   "boundary": "zero Dirichlet", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_for("batched_64x"),
+                     "kernel": "batched_kernel (one persistent launch per step)",
+                     "bytes_per_launch_algorithmic": nbytes,
+                     "avg_launch_us": round(mean_s * 1e6, 1)},
+        "cpu_baseline": cpu,
+        "batch": {"seconds_tuned": round(mean_s, 4), "seconds_default_shapes": round(untuned_s, 4),
+                  "autotune_seconds": round(tune_s, 3), "shapes": shapes,
+                  "seconds_one_by_one": seq, "total_inner_sweeps": int(sweeps.sum()),
+                  "max_sweeps": int(sweeps.max()), "outer_max": int(outer.max()),
+                  "worst_rel_final": max(i.rel_final for i in infos)},
     }
 
 
@@ -290,12 +482,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", choices=["jacobi", "f32", "advect", "solve"], default="jacobi")
+    ap.add_argument("--mode", choices=["jacobi", "f32", "advect", "solve", "batched"],
+                    default="jacobi")
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--solve-n", type=int, default=128)
+    ap.add_argument("--solve-reps", type=int, default=3)
     ap.add_argument("--cpu-sweeps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="batched mode: skip the one-by-one comparison")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -312,6 +508,8 @@ def main():
         out = bench_jacobi(args, "f32")
     elif args.mode == "advect":
         out = bench_advect(args)
+    elif args.mode == "batched":
+        out = bench_batched(args)
     else:
         out = bench_solve(args)
     out["device"] = torch.cuda.get_device_name(0)

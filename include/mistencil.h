@@ -257,6 +257,41 @@ int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
 int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
                         int* team_sizes, int* grid_blocks);
 
+/* ---- autotuning of the batched tile shapes ----------------------------------
+ * A team walks its instance in tiles of tx x-cells (one row of tx lanes;
+ * a 64-lane wave covers 64/tx rows, a block four times that) and splits
+ * each tile column into zsplit chunks along z. Candidates: tx in {64, 32,
+ * 16} x zsplit in {1, 2, 4, 8}. The shape moves work between lanes and
+ * blocks only: fields are the same for every shape; the norms' summation
+ * order changes with it (see the batched solve on iteration counts).
+ *
+ * jacobi_batched_autotune times every candidate on this batch: one launch
+ * per candidate with the solve's team plan, each team running
+ * sweeps_per_trial sweeps of its instance (precision o->precision, with the
+ * per-sweep norm and team barrier) on workspace buffers, all teams at once.
+ * Each instance's fastest shape goes into a process-wide table keyed by
+ * (precision, nx, ny, nz, team size) that jacobi_solve_batched consults
+ * (untuned default: tx 64 and the fewest z chunks that give every block of
+ * the team a tile). The instances' x are not read or written; f
+ * is read in FP64 trials. best: host array of n entries or NULL. Blocks
+ * until done. Workspace from jacobi_batched_autotune_workspace_bytes.
+ * ms_batch_tuning_get copies up to cap entries and returns the count;
+ * ms_batch_tuning_set validates and inserts (MS_EINVAL on a bad entry, none
+ * inserted); ms_batch_tuning_clear empties the table. */
+typedef struct {
+  int32_t precision, nx, ny, nz, team, tx, zsplit, reserved;
+  double us_per_sweep; /* measured under the batch's contention */
+} ms_batch_tuning;
+
+size_t jacobi_batched_autotune_workspace_bytes(int n, const ms_instance* inst,
+                                               const ms_solve_opts* o);
+int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_solve_opts* o,
+                            int sweeps_per_trial, void* work, size_t work_bytes,
+                            ms_batch_tuning* best, void* stream);
+int ms_batch_tuning_get(ms_batch_tuning* out, int cap);
+int ms_batch_tuning_set(const ms_batch_tuning* in, int n);
+void ms_batch_tuning_clear(void);
+
 /* ---- advection source term ------------------------------------------------
  * The fused three-field Piacsek-Williams advection source term of Section
  * 4.1 (three stencils over u, v, w fused into one pass, 63 flops per cell).

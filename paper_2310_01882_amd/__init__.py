@@ -83,6 +83,13 @@ class Instance(ctypes.Structure):
     _fields_ = [("grid", Grid), ("x", ctypes.c_void_p), ("f", ctypes.c_void_p)]
 
 
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("nz", ctypes.c_int32), ("team", ctypes.c_int32), ("tx", ctypes.c_int32),
+                ("zsplit", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("us_per_sweep", ctypes.c_double)]
+
+
 _P = ctypes.c_void_p
 _D = ctypes.c_double
 _I = ctypes.c_int
@@ -115,6 +122,13 @@ SIGNATURES = {
     "ms_tuning_get": (_I, [ctypes.POINTER(Tuning), _I]),
     "ms_tuning_set": (_I, [ctypes.POINTER(Tuning), _I]),
     "ms_tuning_clear": (None, []),
+    "jacobi_batched_autotune_workspace_bytes": (_SZ, [_I, ctypes.POINTER(Instance),
+                                                      ctypes.POINTER(SolveOpts)]),
+    "jacobi_batched_autotune": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts), _I,
+                                     _P, _SZ, ctypes.POINTER(BatchTuning), _P]),
+    "ms_batch_tuning_get": (_I, [ctypes.POINTER(BatchTuning), _I]),
+    "ms_batch_tuning_set": (_I, [ctypes.POINTER(BatchTuning), _I]),
+    "ms_batch_tuning_clear": (None, []),
     "conv3d_bf16_fwd": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P, _I, _P]),
     "conv3d_bf16_dgrad": (_I, [_I, _I, _I, _I, _P, _P, _P, _P, _P]),
     "conv3d_bf16_wgrad_workspace_bytes": (_SZ, [_I]),
@@ -475,3 +489,42 @@ def tuning_load_json(path) -> None:
 
 def tuning_clear() -> None:
     lib.ms_tuning_clear()
+
+
+_BATCH_TUNING_FIELDS = [name for name, _ in BatchTuning._fields_ if name != "reserved"]
+
+
+def batched_autotune(xs, fs, sweeps_per_trial=20, work=None, stream=None, **opts) -> list:
+    """Time every batched tile shape on this batch (the xs are not touched),
+    keep each instance's fastest for later batched solves with the same
+    options, and return them (one dict per instance)."""
+    arr = _instances(xs, fs)
+    o = solve_opts(**opts)
+    if work is None:
+        nbytes = lib.jacobi_batched_autotune_workspace_bytes(len(xs), arr, ctypes.byref(o))
+        if nbytes == 0:
+            raise MsError(MS_EINVAL, last_error())
+        work = _workspace(nbytes, xs[0].device)
+    best = (BatchTuning * len(xs))()
+    _check(lib.jacobi_batched_autotune(len(xs), arr, ctypes.byref(o), int(sweeps_per_trial),
+                                       _ptr(work), work.numel(), best, _stream(stream)))
+    return [{k: getattr(b, k) for k in _BATCH_TUNING_FIELDS} for b in best]
+
+
+def batch_tuning_table() -> list:
+    n = lib.ms_batch_tuning_get(None, 0)
+    arr = (BatchTuning * max(n, 1))()
+    lib.ms_batch_tuning_get(arr, n)
+    return [{k: getattr(arr[i], k) for k in _BATCH_TUNING_FIELDS} for i in range(n)]
+
+
+def batch_tuning_load(entries) -> None:
+    arr = (BatchTuning * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        for k in _BATCH_TUNING_FIELDS:
+            setattr(arr[i], k, e.get(k, 0.0) if k == "us_per_sweep" else e[k])
+    _check(lib.ms_batch_tuning_set(arr, len(entries)))
+
+
+def batch_tuning_clear() -> None:
+    lib.ms_batch_tuning_clear()

@@ -15,11 +15,26 @@
 //
 // The per-cell arithmetic is the single-instance path's (same operation
 // order), so each instance's iterates are those of jacobi_solve.
+//
+// Tile shapes. A team walks its instance in tiles of tx x-cells by 4 * 64/tx
+// rows (each wave covers 64/tx rows of tx lanes), split into zs chunks along
+// z; tiles go round-robin over the team's blocks. Narrow tiles waste fewer
+// lanes on an x extent that is not a multiple of 64; z chunks even out the
+// last round when the tile count is not a multiple of the team size. The
+// shape only moves work between lanes and blocks: each cell's arithmetic is
+// the same, so every shape gives the same fields (the norms' summation order
+// changes with the shape). jacobi_batched_autotune times every shape on the
+// real batch (all teams at once, so under the real bandwidth contention) and
+// keeps each instance's fastest in a table keyed by (precision, extents,
+// team size) that jacobi_solve_batched consults.
 #include "ms_internal.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <tuple>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -27,8 +42,11 @@
 namespace ms {
 namespace {
 
-constexpr int kBatchTX = 64, kBatchTY = kWavesY;  // 64 x 4 columns per tile
+constexpr int kBatchTX = 64, kBatchTY = kWavesY;  // default tile: 64 x 4 columns, whole z
 constexpr int kStallMax = 1024;                    // longest stagnation window
+// Candidate tile shapes for the autotuner: lanes per row x z chunks.
+constexpr int kShapeTX[] = {64, 32, 16};
+constexpr int kShapeZS[] = {1, 2, 4, 8};
 
 // Per-instance description and state (device memory).
 struct Inst {
@@ -43,7 +61,9 @@ struct Inst {
   double* part;       // team partials: [2][team]
   unsigned* bar;      // [0] arrivals, [1] generation
   int team0, team;    // first block of the team in team order, team size
+  int tx, zs;         // tile shape: lanes per row (16, 32 or 64), z chunks
   int tiles_x, tiles_y;
+  int64_t tune_ticks; // autotuning: real-time clock ticks of the timed sweeps
   // results
   double res0, res_final, rel_final;
   int64_t sweeps;
@@ -66,6 +86,24 @@ struct BatchK {
 __device__ __forceinline__ int64_t off3(const Inst& q, int i, int j, int k) {
   return (int64_t)(k + 1) * q.sz + (int64_t)(j + 1) * q.sy + (i + 1);
 }
+
+// Coordinates of this thread's column in tile `tile` of the instance:
+// x index i, y index j and the z range [k0, k1). False if the column lies
+// outside the interior.
+__device__ __forceinline__ bool tile_column(const Inst& q, int tile, int& i, int& j, int& k0,
+                                            int& k1) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int rw = 64 / q.tx;  // rows per wave
+  const int txy = q.tiles_x * q.tiles_y;
+  const int c = tile / txy, t = tile - c * txy;
+  i = (t % q.tiles_x) * q.tx + lane % q.tx;
+  j = (t / q.tiles_x) * (kWavesY * rw) + w * rw + lane / q.tx;
+  k0 = (int)((int64_t)c * q.nz / q.zs);
+  k1 = (int)((int64_t)(c + 1) * q.nz / q.zs);
+  return i < q.nx && j < q.ny;
+}
+
+__device__ __forceinline__ int num_tiles(const Inst& q) { return q.tiles_x * q.tiles_y * q.zs; }
 
 // Team barrier. Returns false if the batch failed (time limit or another
 // team's error); every thread of the block gets the same answer.
@@ -127,16 +165,14 @@ template <typename T>
 __device__ double sweep_tiles(const Inst& q, int rank, const T* __restrict__ src,
                               T* __restrict__ dst, const T* __restrict__ f) {
   double acc = 0.0;
-  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-  const int ntiles = q.tiles_x * q.tiles_y;
+  const int ntiles = num_tiles(q);
   const T c6 = T(1) / T(6);
   for (int tile = rank; tile < ntiles; tile += q.team) {
-    const int i = (tile % q.tiles_x) * kBatchTX + lane;
-    const int j = (tile / q.tiles_x) * kBatchTY + wy;
-    if (i >= q.nx || j >= q.ny) continue;
-    int64_t p = off3(q, i, j, 0);
+    int i, j, k0, k1;
+    if (!tile_column(q, tile, i, j, k0, k1) || k0 >= k1) continue;
+    int64_t p = off3(q, i, j, k0);
     T zm = src[p - q.sz], zc = src[p];
-    for (int k = 0; k < q.nz; ++k, p += q.sz) {
+    for (int k = k0; k < k1; ++k, p += q.sz) {
       const T zp = src[p + q.sz];
       const T xp = src[p + 1], xm = src[p - 1], yp = src[p + q.sy], ym = src[p - q.sy];
       const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
@@ -159,16 +195,14 @@ __device__ double sweep_tiles(const Inst& q, int rank, const T* __restrict__ src
 __device__ double residual_tiles(const Inst& q, int rank, bool zero_int, float* rhat,
                                  double inv_s) {
   double acc = 0.0;
-  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-  const int ntiles = q.tiles_x * q.tiles_y;
+  const int ntiles = num_tiles(q);
   const double* __restrict__ x = q.x;
   for (int tile = rank; tile < ntiles; tile += q.team) {
-    const int i = (tile % q.tiles_x) * kBatchTX + lane;
-    const int j = (tile / q.tiles_x) * kBatchTY + wy;
-    if (i >= q.nx || j >= q.ny) continue;
+    int i, j, k0, k1;
+    if (!tile_column(q, tile, i, j, k0, k1)) continue;
     const bool xlo = i == 0, xhi = i == q.nx - 1, ylo = j == 0, yhi = j == q.ny - 1;
-    int64_t p = off3(q, i, j, 0);
-    for (int k = 0; k < q.nz; ++k, p += q.sz) {
+    int64_t p = off3(q, i, j, k0);
+    for (int k = k0; k < k1; ++k, p += q.sz) {
       double xp = x[p + 1], xm = x[p - 1], yp = x[p + q.sy], ym = x[p - q.sy];
       double zp = x[p + q.sz], zm = x[p - q.sz], c = x[p];
       if (zero_int) {  // keep halo values only
@@ -194,14 +228,12 @@ __device__ double residual_tiles(const Inst& q, int rank, bool zero_int, float* 
 }
 
 __device__ void update_tiles(const Inst& q, int rank, const float* __restrict__ e, double s) {
-  const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-  const int ntiles = q.tiles_x * q.tiles_y;
+  const int ntiles = num_tiles(q);
   for (int tile = rank; tile < ntiles; tile += q.team) {
-    const int i = (tile % q.tiles_x) * kBatchTX + lane;
-    const int j = (tile / q.tiles_x) * kBatchTY + wy;
-    if (i >= q.nx || j >= q.ny) continue;
-    int64_t p = off3(q, i, j, 0);
-    for (int k = 0; k < q.nz; ++k, p += q.sz) q.x[p] = q.x[p] + s * (double)e[p];
+    int i, j, k0, k1;
+    if (!tile_column(q, tile, i, j, k0, k1)) continue;
+    int64_t p = off3(q, i, j, k0);
+    for (int k = k0; k < k1; ++k, p += q.sz) q.x[p] = q.x[p] + s * (double)e[p];
   }
 }
 
@@ -285,14 +317,12 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
     if (K < 0) return;
     // the answer is buffer K % 2; bring it into x
     if (K & 1) {
-      const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-      const int ntiles = q.tiles_x * q.tiles_y;
+      const int ntiles = num_tiles(q);
       for (int tile = rank; tile < ntiles; tile += q.team) {
-        const int i = (tile % q.tiles_x) * kBatchTX + lane;
-        const int j = (tile / q.tiles_x) * kBatchTY + wy;
-        if (i >= q.nx || j >= q.ny) continue;
-        int64_t p = off3(q, i, j, 0);
-        for (int k = 0; k < q.nz; ++k, p += q.sz) q.x[p] = q.xb[p];
+        int i, j, k0, k1;
+        if (!tile_column(q, tile, i, j, k0, k1)) continue;
+        int64_t p = off3(q, i, j, k0);
+        for (int k = k0; k < k1; ++k, p += q.sz) q.x[p] = q.xb[p];
       }
     }
     if (rank == 0 && threadIdx.x == 0) {
@@ -355,6 +385,40 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
   }
 }
 
+// Autotuning trial: every team runs `nsweeps` sweeps of its instance with
+// the real loop's per-sweep norm and team barrier, on scratch buffers, and
+// its rank-0 block records the elapsed real-time clock ticks.
+template <typename T>
+__device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
+                          int nsweeps, double* red, int* s_flag) {
+  if (!team_barrier(a, q, s_flag)) return;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  double chk = 0.0;
+  for (int j = 0; j < nsweeps; ++j) {
+    const T* src = (j & 1) ? b1 : b0;
+    T* dst = (j & 1) ? b0 : b1;
+    const double mine = block_sum(sweep_tiles<T>(q, rank, src, dst, f), red);
+    if (threadIdx.x == 0) q.part[(int64_t)(j & 1) * q.team + rank] = mine;
+    if (!team_barrier(a, q, s_flag)) return;
+    chk += team_sum(q, j & 1, red);
+  }
+  if (rank == 0 && threadIdx.x == 0) {
+    q.tune_ticks = (int64_t)(__builtin_amdgcn_s_memrealtime() - t0);
+    q.res_final = chk;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void batched_tune_kernel(BatchK a, int nsweeps) {
+  __shared__ double red[kWavesY];
+  __shared__ int s_flag;
+  Inst& q = a.inst[a.block_team[blockIdx.x]];
+  const int rank = a.block_rank[blockIdx.x];
+  if (a.mode == MS_SOLVE_F64)
+    tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag);
+  else
+    tune_team<float>(a, q, rank, q.e0, q.e1, q.rhat, nsweeps, red, &s_flag);
+}
+
 // ------------------------------------------------------------------ host
 
 struct Plan {
@@ -375,8 +439,48 @@ int tiles_of(const ms_grid& g) {
   return ((g.nx + kBatchTX - 1) / kBatchTX) * ((g.ny + kBatchTY - 1) / kBatchTY);
 }
 
+bool valid_shape(int tx, int zs) {
+  return (tx == 16 || tx == 32 || tx == 64) && (zs == 1 || zs == 2 || zs == 4 || zs == 8);
+}
+
+void set_shape(Inst& q, int tx, int zs) {
+  q.tx = tx;
+  q.zs = zs;
+  const int ty = kWavesY * (64 / tx);
+  q.tiles_x = (q.nx + tx - 1) / tx;
+  q.tiles_y = (q.ny + ty - 1) / ty;
+}
+
+// Tuned shapes, keyed by (precision, nx, ny, nz, team size).
+using ShapeKey = std::tuple<int, int, int, int, int>;
+struct ShapeRec {
+  int tx, zs;
+  double us;
+};
+std::mutex g_shape_mu;
+std::map<ShapeKey, ShapeRec>& shape_table() {
+  static std::map<ShapeKey, ShapeRec> t;
+  return t;
+}
+
+// Untuned default: 64-lane rows and the fewest z chunks that give every
+// block of the team a tile.
+ShapeRec default_shape(const ms_grid& g, int team) {
+  int zs = 1;
+  while (zs < 8 && tiles_of(g) * zs < team) zs *= 2;
+  return ShapeRec{kBatchTX, zs, 0.0};
+}
+
+ShapeRec lookup_shape(int prec, const ms_grid& g, int team) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  auto it = shape_table().find(ShapeKey{prec, g.nx, g.ny, g.nz, team});
+  if (it == shape_table().end()) return default_shape(g, team);
+  return it->second;
+}
+
 // Splits G blocks into teams proportional to estimated work (at least one
-// block, at most one per tile column), then lays the teams out XCD by XCD.
+// block, at most one per default tile split into the most z chunks), then
+// lays the teams out XCD by XCD.
 void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
   std::vector<double> w(n);
   for (int i = 0; i < n; ++i) w[i] = est_work(inst[i].grid, tol);
@@ -390,7 +494,7 @@ void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
     int best = -1;
     double bd = 0.0;
     for (int i = 0; i < n; ++i) {
-      if (P.team[i] >= tiles_of(inst[i].grid)) continue;
+      if (P.team[i] >= tiles_of(inst[i].grid) * kShapeZS[3]) continue;
       const double d = want[i] - P.team[i];
       if (best < 0 || d > bd) {
         best = i;
@@ -424,16 +528,18 @@ void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
   }
 }
 
-int resident_blocks() {
+template <typename K>
+int resident_blocks_of(K kernel) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batched_kernel, kThreads, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess)
     return 0;
   return cus * per;
 }
+
+int resident_blocks() { return resident_blocks_of(batched_kernel); }
 
 size_t inst_bytes(const ms_grid& g, int mode, int team) {
   const size_t span = (size_t)field_span(g);
@@ -524,8 +630,8 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
     q.f = inst[i].f;
     q.team0 = P.first[i];
     q.team = P.team[i];
-    q.tiles_x = (g.nx + kBatchTX - 1) / kBatchTX;
-    q.tiles_y = (g.ny + kBatchTY - 1) / kBatchTY;
+    const ShapeRec sh = lookup_shape(o->precision, g, q.team);
+    set_shape(q, sh.tx, sh.zs);
     q.part = ws.take<double>(2 * (size_t)q.team);
     q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
     const size_t span = (size_t)field_span(g);
@@ -618,4 +724,171 @@ extern "C" int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solv
   if (team_sizes) std::copy(P.team.begin(), P.team.end(), team_sizes);
   if (grid_blocks) *grid_blocks = P.G;
   return MS_OK;
+}
+
+// ------------------------------------------------------------ autotuning
+
+namespace {
+
+size_t tune_inst_bytes(const ms_grid& g, int team) {
+  const size_t span = (size_t)field_span(g);
+  return align_up(2 * (size_t)team * sizeof(double), 256) + 256 + 2 * align_up(span * 8, 256);
+}
+
+}  // namespace
+
+extern "C" size_t jacobi_batched_autotune_workspace_bytes(int n, const ms_instance* inst,
+                                                          const ms_solve_opts* o) {
+  if (check_batch(n, inst, o)) return 0;
+  const int G = resident_blocks();
+  if (G <= 0) return 0;
+  Plan P;
+  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
+  size_t t = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
+  for (int i = 0; i < n; ++i) t += tune_inst_bytes(inst[i].grid, P.team[i]);
+  return t;
+}
+
+extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_solve_opts* o,
+                                       int sweeps_per_trial, void* work, size_t work_bytes,
+                                       ms_batch_tuning* best, void* stream) {
+  clear_error();
+  if (int rc = check_batch(n, inst, o)) return rc;
+  if (sweeps_per_trial < 1 || sweeps_per_trial > 100000)
+    return set_error(MS_EINVAL, "jacobi_batched_autotune: sweeps_per_trial must be in [1, 1e5]");
+  const int G = resident_blocks();
+  const int Gt = resident_blocks_of(batched_tune_kernel);
+  if (G <= 0 || Gt <= 0)
+    return set_error(MS_EHIP, "jacobi_batched_autotune: occupancy query failed");
+  if (G < n)
+    return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: %d instances need %d resident "
+                     "blocks, the device holds %d", n, n, G);
+  Plan P;
+  plan_teams(n, inst, o->rel_tol, G, P);
+  if (P.G > Gt)
+    return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: the timing kernel holds only %d "
+                     "resident blocks, the plan has %d", Gt, P.G);
+  size_t need = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
+  for (int i = 0; i < n; ++i) need += tune_inst_bytes(inst[i].grid, P.team[i]);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "jacobi_batched_autotune: workspace needs %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws{static_cast<char*>(work), work_bytes};
+  Inst* dinst = ws.take<Inst>(n);
+  int* dmap = ws.take<int>(2 * (size_t)P.G);
+  int* derr = ws.take<int>(64);
+  std::vector<Inst> h(n);
+  for (int i = 0; i < n; ++i) {
+    const ms_grid& g = inst[i].grid;
+    Inst& q = h[i];
+    q = Inst{};
+    q.nx = g.nx; q.ny = g.ny; q.nz = g.nz;
+    q.sy = g.sy; q.sz = g.sz;
+    q.f = inst[i].f;  // read only (FP64 trials)
+    q.team0 = P.first[i];
+    q.team = P.team[i];
+    q.part = ws.take<double>(2 * (size_t)q.team);
+    q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
+    const size_t span = (size_t)field_span(g);
+    double* A = ws.take<double>(span);
+    double* B = ws.take<double>(span);
+    if (!q.part || !q.bar || !A || !B)
+      return set_error(MS_EWORKSPACE, "jacobi_batched_autotune: workspace carve failed");
+    // scratch iterates (the caller's x is never touched)
+    q.x = A;
+    q.xb = B;
+    q.e0 = reinterpret_cast<float*>(A);
+    q.rhat = reinterpret_cast<float*>(A) + span;
+    q.e1 = reinterpret_cast<float*>(B);
+    MS_HIP_TRY(hipMemsetAsync(A, 0, span * 8, s));
+    MS_HIP_TRY(hipMemsetAsync(B, 0, span * 8, s));
+  }
+  std::vector<int> map(2 * (size_t)P.G);
+  std::copy(P.block_team.begin(), P.block_team.end(), map.begin());
+  std::copy(P.block_rank.begin(), P.block_rank.end(), map.begin() + P.G);
+  MS_HIP_TRY(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, s));
+  BatchK a{};
+  a.inst = dinst;
+  a.block_team = dmap;
+  a.block_rank = dmap + P.G;
+  a.error = derr;
+  a.ninst = n;
+  a.mode = o->precision;
+  a.spin_ticks = (int64_t)100000000 * 20;
+
+  std::vector<ShapeRec> bestv(n, ShapeRec{kBatchTX, 1, -1.0});
+  // the first trial (default shape) is a warm-up and is timed again later
+  std::vector<std::pair<int, int>> trials{{kBatchTX, 1}};
+  for (int tx : kShapeTX)
+    for (int zs : kShapeZS) trials.emplace_back(tx, zs);
+  for (size_t t = 0; t < trials.size(); ++t) {
+    for (int i = 0; i < n; ++i) set_shape(h[i], trials[t].first, trials[t].second);
+    MS_HIP_TRY(hipMemcpyAsync(dinst, h.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s));
+    MS_HIP_TRY(hipMemsetAsync(derr, 0, 256, s));
+    for (int i = 0; i < n; ++i) MS_HIP_TRY(hipMemsetAsync(h[i].bar, 0, 256, s));
+    hipLaunchKernelGGL(batched_tune_kernel, dim3(P.G), dim3(kThreads), 0, s, a, sweeps_per_trial);
+    MS_HIP_TRY(hipGetLastError());
+    MS_HIP_TRY(hipStreamSynchronize(s));
+    int herr = 0;
+    std::vector<Inst> r(n);
+    MS_HIP_TRY(hipMemcpy(&herr, derr, sizeof(int), hipMemcpyDeviceToHost));
+    MS_HIP_TRY(hipMemcpy(r.data(), dinst, sizeof(Inst) * n, hipMemcpyDeviceToHost));
+    if (herr) return set_error(MS_EHIP, "jacobi_batched_autotune: a team barrier timed out");
+    if (t == 0) continue;
+    for (int i = 0; i < n; ++i) {
+      const double us = (double)r[i].tune_ticks / 100.0 / sweeps_per_trial;  // 100 MHz clock
+      if (bestv[i].us < 0.0 || us < bestv[i].us)
+        bestv[i] = ShapeRec{trials[t].first, trials[t].second, us};
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    for (int i = 0; i < n; ++i) {
+      const ms_grid& g = inst[i].grid;
+      shape_table()[ShapeKey{o->precision, g.nx, g.ny, g.nz, P.team[i]}] = bestv[i];
+    }
+  }
+  if (best)
+    for (int i = 0; i < n; ++i) {
+      const ms_grid& g = inst[i].grid;
+      best[i] = ms_batch_tuning{o->precision, g.nx, g.ny, g.nz, P.team[i], bestv[i].tx,
+                                bestv[i].zs, 0, bestv[i].us};
+    }
+  return MS_OK;
+}
+
+extern "C" int ms_batch_tuning_get(ms_batch_tuning* out, int cap) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  int k = 0;
+  for (const auto& kv : shape_table()) {
+    if (out && k < cap) {
+      const auto& [prec, nx, ny, nz, team] = kv.first;
+      out[k] = ms_batch_tuning{prec, nx, ny, nz, team, kv.second.tx, kv.second.zs, 0, kv.second.us};
+    }
+    ++k;
+  }
+  return k;
+}
+
+extern "C" int ms_batch_tuning_set(const ms_batch_tuning* in, int n) {
+  clear_error();
+  if (n < 0 || (n > 0 && !in)) return set_error(MS_EINVAL, "ms_batch_tuning_set: bad arguments");
+  for (int i = 0; i < n; ++i) {
+    const ms_batch_tuning& e = in[i];
+    if ((e.precision != MS_SOLVE_F64 && e.precision != MS_SOLVE_F32_REFINED) || e.nx < 1 ||
+        e.ny < 1 || e.nz < 1 || e.team < 1 || !valid_shape(e.tx, e.zsplit))
+      return set_error(MS_EINVAL, "ms_batch_tuning_set: entry %d is not a valid shape", i);
+  }
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  for (int i = 0; i < n; ++i) {
+    const ms_batch_tuning& e = in[i];
+    shape_table()[ShapeKey{e.precision, e.nx, e.ny, e.nz, e.team}] =
+        ShapeRec{e.tx, e.zsplit, e.us_per_sweep};
+  }
+  return MS_OK;
+}
+
+extern "C" void ms_batch_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  shape_table().clear();
 }

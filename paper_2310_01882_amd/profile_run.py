@@ -1,15 +1,21 @@
 """Small, fixed workloads for rocprofv3 runs (kernel traces and HBM counters).
 
-    python -m paper_2310_01882_amd.profile_run sweep  [--dtype f64|f32] [--sweeps N]
-    python -m paper_2310_01882_amd.profile_run advect [--passes N]
-    python -m paper_2310_01882_amd.profile_run copy   [--mib M]
+    python -m paper_2310_01882_amd.profile_run sweep   [--dtype f64|f32] [--sweeps N] [--tb 1|2]
+    python -m paper_2310_01882_amd.profile_run advect  [--passes N]
+    python -m paper_2310_01882_amd.profile_run batched
+    python -m paper_2310_01882_amd.profile_run cnn     [--steps N]
+    python -m paper_2310_01882_amd.profile_run copy    [--mib M]
 
 `sweep` runs N sweeps of the 512^3 Poisson workload (8 Gaussian sources,
 seed 1, zero start) on aligned fields, with the launch geometry the
-benchmark uses. `advect` runs N passes of the 512 x 512 x 256 advection
-term. `copy` is the calibration kernel of known size: one device-to-device
-tensor copy of M MiB (reads M MiB, writes M MiB), used to scale the
-FETCH_SIZE / WRITE_SIZE counters.
+benchmark uses (--tb 2: two sweeps per pass). `advect` runs N passes of the
+512 x 512 x 256 advection term. `batched` autotunes and then solves the
+benchmark's batch (64 instances, sizes log-uniform in [32, 256], seed 4,
+FP32-refined to 1e-8) once. `cnn` runs N training steps (forward, backward,
+Adam) of the warm-start network on a 128^3 instance. `copy` is the
+calibration kernel of known size: one device-to-device tensor copy of M MiB
+(reads M MiB, writes M MiB), used to scale the FETCH_SIZE / WRITE_SIZE
+counters.
 """
 
 from __future__ import annotations
@@ -25,7 +31,9 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "advect", "copy"])
+    ap.add_argument("what", choices=["sweep", "advect", "batched", "cnn", "copy"])
+    ap.add_argument("--tb", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--sweeps", type=int, default=10)
     ap.add_argument("--passes", type=int, default=5)
@@ -54,10 +62,32 @@ def main():
         u = ms.alloc_field(n, n, n, dt)
         tmp = ms.alloc_field(n, n, n, dt)
         res = torch.zeros(args.sweeps + 1, dtype=torch.float64, device="cuda")
-        ms.jacobi_sweeps(u, tmp, args.sweeps, f=f, res=res)
+        ms.jacobi_sweeps(u, tmp, args.sweeps, f=f, res=res, temporal_block=args.tb)
         torch.cuda.synchronize()
-        print(f"{args.sweeps} sweeps of {n}^3 ({args.dtype}) done; "
+        print(f"{args.sweeps} sweeps (temporal block {args.tb}) of {n}^3 ({args.dtype}) done; "
               f"final residual {res[-1].item():.6e}", flush=True)
+        return
+    if args.what == "batched":
+        dims = synth.batch_sizes(64, 4)
+        xs = [ms.field_from(synth.zeros(*d)) for d in dims]
+        fs = [ms.field_from(synth.gaussian_sources(*d, 8, 4000 + i)) for i, d in enumerate(dims)]
+        opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, max_outer=40)
+        ms.batched_autotune(xs, fs, sweeps_per_trial=20, **opts)
+        print("batched autotune done", flush=True)
+        infos = ms.jacobi_solve_batched(xs, fs, **opts)
+        print(f"batched solve done: {sum(i.sweeps for i in infos)} inner sweeps", flush=True)
+        return
+    if args.what == "cnn":
+        from paper_2310_01882_amd import warmstart as wsm
+        n = 128
+        net = wsm.WarmStart(n, n, n, seed=0)
+        u = ms.alloc_field(n, n, n)
+        f = ms.field_from(synth.gaussian_sources(n, n, n, 4, 7))
+        target = torch.zeros_like(net.out32)
+        for _ in range(args.steps):
+            net.train_step(u, f, target)
+        torch.cuda.synchronize()
+        print(f"{args.steps} warm-start training steps at {n}^3 done", flush=True)
         return
     nx, ny, nz = 512, 512, 256
     u, v, w = (ms.field_from(a) for a in synth.velocity_fields(nx, ny, nz, 2))

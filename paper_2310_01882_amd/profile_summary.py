@@ -29,11 +29,13 @@ PROFILES = os.path.join(ROOT, "profiles")
 SOURCES = {
     "jacobi7": ["jacobi.hip", "ms_internal.hpp", "common.hip"],
     "advect": ["advect.hip"],
+    "batched": ["batched.hip", "ms_internal.hpp"],
+    "conv": ["cnn.hip"],
 }
 
 
 def source_hash(key: str) -> str:
-    names = SOURCES["advect" if key.startswith("advect") else "jacobi7"]
+    names = SOURCES[next((k for k in SOURCES if key.startswith(k)), "jacobi7")]
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(HERE, "csrc", n), "rb") as fh:

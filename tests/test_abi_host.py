@@ -150,3 +150,18 @@ def test_tuning_table_round_trip_without_a_device():
         ms.tuning_load([bad])
     ms.tuning_clear()
     assert ms.tuning_table() == []
+
+
+def test_batch_tuning_table_round_trip_without_a_device():
+    import paper_2310_01882_amd as ms
+    ms.batch_tuning_clear()
+    e = dict(precision=ms.MS_SOLVE_F32_REFINED, nx=69, ny=240, nz=221, team=37, tx=32, zsplit=4,
+             us_per_sweep=3.5)
+    ms.batch_tuning_load([e])
+    assert ms.batch_tuning_table() == [e]
+    for bad in (dict(e, tx=48), dict(e, zsplit=3), dict(e, team=0), dict(e, precision=7)):
+        with pytest.raises(ms.MsError):
+            ms.batch_tuning_load([bad])
+    assert ms.batch_tuning_table() == [e]  # a rejected load inserts nothing
+    ms.batch_tuning_clear()
+    assert ms.batch_tuning_table() == []

@@ -82,3 +82,63 @@ def test_plan_gives_every_instance_a_team():
     work = [np.prod(d) * max(d) ** 2 for d in dims[:8]]
     order = np.argsort(work)
     assert teams[order[-1]] >= teams[order[0]]
+
+
+def _solve_with_shape(probs, shape, precision):
+    """Batched solve with every instance's tile shape forced to `shape`
+    ((tx, zsplit), or None for the library default)."""
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    ms.batch_tuning_clear()
+    if shape is not None:
+        teams, _ = ms.batched_plan(xs, fs, precision=precision, rel_tol=1e-8)
+        ms.batch_tuning_load([dict(precision=precision, nx=x.shape[2] - 2, ny=x.shape[1] - 2,
+                                   nz=x.shape[0] - 2, team=t, tx=shape[0], zsplit=shape[1])
+                              for x, t in zip(xs, teams)])
+    infos = ms.jacobi_solve_batched(xs, fs, precision=precision, rel_tol=1e-8)
+    ms.batch_tuning_clear()
+    return infos, [host(x) for x in xs]
+
+
+@pytest.mark.parametrize("precision", [ms.MS_SOLVE_F32_REFINED, ms.MS_SOLVE_F64])
+def test_every_tile_shape_gives_the_same_fields(precision):
+    note(f"case: batched tile shapes precision={precision}")
+    probs = _instances(DIMS, 90, halo=True)
+    ref_infos, ref = _solve_with_shape(probs, None, precision)
+    for shape in [(64, 8), (32, 1), (32, 4), (16, 2), (16, 8)]:
+        infos, got = _solve_with_shape(probs, shape, precision)
+        for a, b, fa, fb in zip(ref_infos, infos, ref, got):
+            assert b.status == ms.MS_OK
+            # the norms' summation order changes with the shape; the iterates do not
+            assert (a.sweeps, a.outer_iters) == (b.sweeps, b.outer_iters), shape
+            assert np.array_equal(fa, fb), shape
+
+
+def test_autotune_picks_valid_shapes_and_leaves_x_alone():
+    note("case: batched autotune 16 instances")
+    dims = synth.batch_sizes(16, 4, lo=16, hi=96)
+    probs = _instances(dims, 500)
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    before = [host(x) for x in xs]
+    ms.batch_tuning_clear()
+    best = ms.batched_autotune(xs, fs, sweeps_per_trial=8, precision=ms.MS_SOLVE_F32_REFINED,
+                               rel_tol=1e-8)
+    assert all(np.array_equal(host(x), b) for x, b in zip(xs, before))
+    teams, _ = ms.batched_plan(xs, fs, precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8)
+    assert [b["team"] for b in best] == teams
+    for b, d in zip(best, dims):
+        assert (b["nx"], b["ny"], b["nz"]) == d
+        assert b["tx"] in (16, 32, 64) and b["zsplit"] in (1, 2, 4, 8)
+        assert b["us_per_sweep"] > 0
+    assert len(ms.batch_tuning_table()) == len(set((b["nx"], b["ny"], b["nz"], b["team"])
+                                                   for b in best))
+    infos = ms.jacobi_solve_batched(xs, fs, precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8)
+    tuned = [host(x) for x in xs]
+    ms.batch_tuning_clear()
+    ref_infos, ref = _solve_with_shape(probs, None, ms.MS_SOLVE_F32_REFINED)
+    for a, b, fa, fb, (u, f) in zip(ref_infos, infos, ref, tuned, probs):
+        assert (a.sweeps, a.outer_iters) == (b.sweeps, b.outer_iters)
+        assert np.array_equal(fa, fb)
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        assert oracle.residual_norm(fb, f) <= 1e-8 * res0 * (1 + 1e-9)
