@@ -278,6 +278,10 @@ def bench_solve(args):
     u_h = synth.zeros(n, n, n)
     f = ms.field_from(f_h)
     u0 = ms.field_from(u_h)
+
+    def fresh():  # a new aligned field holding the zero start (clone() drops the padding)
+        return ms.field_from(u_h)
+
     F64, F32R = ms.MS_SOLVE_F64, ms.MS_SOLVE_F32_REFINED
     variants = [("fp64", dict(precision=F64)),
                 ("fp64_tb2", dict(precision=F64, temporal_block=2)),
@@ -295,10 +299,10 @@ def bench_solve(args):
 
     for name, kw in variants:
         work = ms.jacobi_workspace(u0, ms.solve_opts(**kw))
-        ms.jacobi_solve(u0.clone(), f, work=work, rel_tol=1e-3, **kw)  # warm-up (graphs, caches)
+        ms.jacobi_solve(fresh(), f, work=work, rel_tol=1e-3, **kw)  # warm-up (graphs, caches)
         times = []
         for _ in range(args.solve_reps):
-            u = u0.clone()
+            u = fresh()
             torch.cuda.synchronize()
             t = time.perf_counter()
             info = ms.jacobi_solve(u, f, work=work, rel_tol=1e-8, **kw)
@@ -307,7 +311,7 @@ def bench_solve(args):
         record(name, times, info)
     times = []
     for rep in range(args.solve_reps + 1):
-        u = u0.clone()
+        u = fresh()
         torch.cuda.synchronize()
         t = time.perf_counter()
         info = ms.jacobi_solve_batched([u], [f], precision=F32R, rel_tol=1e-8 if rep else 1e-3)[0]
@@ -324,7 +328,7 @@ def bench_solve(args):
         kw = dict(variants)[best32] if best32 != "fp32_refined_persistent" else None
         times, used = [], []
         for rep in range(args.solve_reps + 1):
-            x = u0.clone()
+            x = fresh()
             torch.cuda.synchronize()
             t = time.perf_counter()
             net.guess(x, f, x)
@@ -415,6 +419,13 @@ def bench_batched(args):
         dt, infos = timed_batch(f"step {k + 1}/{args.steps}")
         secs.append(dt)
     mean_s = sum(secs) / len(secs)
+    # per-team finish times (device clock): the batch ends with its slowest team
+    fin = np.array([i.seconds for i in infos])
+    teams, grid_blocks = ms.batched_plan(xs, fs, **opts)
+    order = np.argsort(-fin)
+    for i in order[:4]:
+        log(f"[bench]   slowest: instance {i} dims {dims[i]} team {teams[i]} sweeps "
+            f"{infos[i].sweeps} finished at {fin[i]:.2f} s")
     sweeps = np.array([i.sweeps for i in infos], dtype=np.float64)
     outer = np.array([i.outer_iters for i in infos], dtype=np.float64)
     lups = float((cells * sweeps).sum())
@@ -473,7 +484,13 @@ def bench_batched(args):
                   "autotune_seconds": round(tune_s, 3), "shapes": shapes,
                   "seconds_one_by_one": seq, "total_inner_sweeps": int(sweeps.sum()),
                   "max_sweeps": int(sweeps.max()), "outer_max": int(outer.max()),
-                  "worst_rel_final": max(i.rel_final for i in infos)},
+                  "worst_rel_final": max(i.rel_final for i in infos),
+                  "grid_blocks": grid_blocks,
+                  "team_finish_seconds": {"min": round(float(fin.min()), 3),
+                                          "median": round(float(np.median(fin)), 3),
+                                          "max": round(float(fin.max()), 3)},
+                  "block_seconds_busy_fraction": round(float(
+                      (fin * np.array(teams)).sum() / (fin.max() * grid_blocks)), 3)},
     }
 
 

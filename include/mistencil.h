@@ -191,6 +191,9 @@ typedef struct {
   double res0;         /* ||r(u^0)|| */
   double res_final;    /* ||r(u_K)|| (FP64, recomputed for refined) */
   double rel_final;    /* res_final / res0 */
+  double seconds;      /* jacobi_solve: host wall time of the call; batched:
+                          device real-time clock from the earliest team start
+                          of the launch to this instance's team finish */
 } ms_solve_result;
 
 /* Fill `o` with the library defaults (rel_tol 1e-8, F64, auto chunks). */

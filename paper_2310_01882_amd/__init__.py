@@ -69,7 +69,8 @@ class SolveOpts(ctypes.Structure):
 class SolveResult(ctypes.Structure):
     _fields_ = [("sweeps", ctypes.c_int64), ("outer_iters", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("res0", ctypes.c_double),
-                ("res_final", ctypes.c_double), ("rel_final", ctypes.c_double)]
+                ("res_final", ctypes.c_double), ("rel_final", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):
@@ -329,6 +330,7 @@ class SolveInfo:
     res_final: float
     rel_final: float
     hist: list
+    seconds: float = 0.0
 
 
 def solve_opts(**kw) -> SolveOpts:
@@ -375,7 +377,7 @@ def jacobi_solve(u, f=None, work=None, want_hist=False, stream=None, **opts) -> 
     if want_hist:
         cnt = (r.sweeps + 1) if o.precision == MS_SOLVE_F64 else (r.outer_iters + 1)
         h = list(hist[:cnt])
-    return SolveInfo(rc, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, h)
+    return SolveInfo(rc, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, h, r.seconds)
 
 
 def advect_source(u, v, w, tzc1, tzc2, tcx, tcy, su, sv, sw, stream=None):
@@ -433,8 +435,8 @@ def jacobi_solve_batched(xs, fs, work=None, stream=None, **opts):
     rc = lib.jacobi_solve_batched(len(xs), arr, ctypes.byref(o), _ptr(work), work.numel(), res,
                                   _stream(stream))
     _check(rc, allow=(MS_OK, MS_NOT_CONVERGED))
-    return [SolveInfo(r.status, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, [])
-            for r in res]
+    return [SolveInfo(r.status, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, [],
+                      r.seconds) for r in res]
 
 
 # ------------------------------------------------------------------ tuning

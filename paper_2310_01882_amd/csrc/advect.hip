@@ -12,9 +12,10 @@
 // z-chunk. Planes of u, v, w (tile plus a one-cell ring, corners included)
 // pass through a ring of four LDS buffers: at level k the block reads level
 // k (all in-plane neighbours) and level k+1 (the four off-column values the
-// upper face needs), writes level k+2 that it prefetched into registers one
-// step earlier, and issues the global loads of level k+3. Four buffers
-// leave one barrier per level. The level-(k-1) values (five per cell) are
+// upper face needs), writes level k+2 that it loaded into registers two
+// steps earlier, and issues the global loads of level k+4, so two levels of
+// loads are in flight behind the compute. Four buffers leave one barrier
+// per level. The level-(k-1) values (five per cell) are
 // carried in registers from the previous level. Every input element is read
 // from HBM once per z-chunk plus the ring; outputs are nontemporal stores.
 //
@@ -144,16 +145,18 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
     load_level(c, rg, z0 + 1);
     store_level(c, rg, 1);
   }
-  double pc[3][kAdvRows], prg[3];  // prefetched level k+2
-  if (z0 + 1 < z1) load_level(pc, prg, z0 + 2);
+  // Two register sets of prefetched levels: at step k the set of parity
+  // (k - z0) holds level k+2 (stored to LDS at step k, then refilled with
+  // level k+4); the other set's level k+3 is in flight meanwhile.
+  double pa[3][kAdvRows], pra[3], pb[3][kAdvRows], prb[3];
+  if (z0 + 2 <= z1) load_level(pa, pra, z0 + 2);
+  if (z0 + 3 <= z1) load_level(pb, prb, z0 + 3);
 
   const double tcx = a.tcx, tcy = a.tcy;
-  for (int k = z0; k < z1; ++k) {
+  auto step = [&](int k, double (&pc)[3][kAdvRows], double (&prg)[3]) {
     const int b = (k - z0) & 3, nb = (b + 1) & 3, wb = (b + 2) & 3;
-    if (k + 1 < z1) {
-      store_level(pc, prg, wb);
-      if (k + 2 < z1) load_level(pc, prg, k + 3);
-    }
+    if (k + 2 <= z1) store_level(pc, prg, wb);
+    if (k + 4 <= z1) load_level(pc, prg, k + 4);
     __syncthreads();
     const double c1 = a.t1[k], c2 = a.t2[k];
 #pragma unroll
@@ -193,6 +196,10 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
       wm1x[r] = Lw(0, 1);
       wm1y[r] = Lw(1, 0);
     }
+  };
+  for (int k = z0; k < z1; k += 2) {
+    step(k, pa, pra);
+    if (k + 1 < z1) step(k + 1, pb, prb);
   }
 }
 

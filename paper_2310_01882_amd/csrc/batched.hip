@@ -64,6 +64,7 @@ struct Inst {
   int tx, zs;         // tile shape: lanes per row (16, 32 or 64), z chunks
   int tiles_x, tiles_y;
   int64_t tune_ticks; // autotuning: real-time clock ticks of the timed sweeps
+  int64_t t_start, t_end;  // real-time clock at the team's start and finish
   // results
   double res0, res_final, rel_final;
   int64_t sweeps;
@@ -107,34 +108,51 @@ __device__ __forceinline__ int num_tiles(const Inst& q) { return q.tiles_x * q.t
 
 // Team barrier. Returns false if the batch failed (time limit or another
 // team's error); every thread of the block gets the same answer.
-__device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag) {
+//
+// Ordering: each block releases its writes (agent-scope release fence)
+// before it increments the arrival counter; the last arriver's acquire-
+// release fence then orders all of them before its generation bump, and a
+// waiter's acquire fence after it sees the bump orders them before its
+// later reads. The spin itself uses relaxed loads: on this GPU an
+// agent-scope acquire invalidates the XCD's L2, and doing that on every
+// spin would evict the data of every other team on the XCD. The expected
+// generation is the block's own barrier count (`epoch`, thread 0 only), so
+// the generation word is never read before the arrival. A one-block team
+// needs only the workgroup barrier.
+__device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag, unsigned* epoch) {
+  if (q.team == 1) {
+    __syncthreads();
+    return true;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    __threadfence();  // release this block's writes to the team
     unsigned* cnt = q.bar;
     unsigned* gen = q.bar + 1;
-    const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned arrived = atomicAdd(cnt, 1u);
+    const unsigned e = ++*epoch;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == (unsigned)q.team - 1) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
       __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != e) {
         if (__hip_atomic_load(a.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
           ok = 0;
           break;
         }
         if ((int64_t)(__builtin_amdgcn_s_memrealtime() - t0) > a.spin_ticks) {
-          atomicExch(a.error, 1);
+          __hip_atomic_store(a.error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
         __builtin_amdgcn_s_sleep(2);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
-    __threadfence();  // acquire the team's writes
     *s_flag = ok;
   }
   __syncthreads();
@@ -160,31 +178,49 @@ __device__ double bcast(double v, double* cell) {
 }
 
 // One sweep of the tiles owned by this block: dst = (S(src) - f) * fl(1/6)
-// on the interior; returns this thread's sum of r(src)^2 (FP64).
+// on the interior; returns this thread's sum of r(src)^2 (FP64). The z-march
+// issues the loads of several levels before it computes them, so that a
+// lane keeps several memory round trips in flight (one level at a time
+// would leave each block waiting on one round trip per level).
 template <typename T>
 __device__ double sweep_tiles(const Inst& q, int rank, const T* __restrict__ src,
                               T* __restrict__ dst, const T* __restrict__ f) {
+  constexpr int kUnroll = sizeof(T) == 4 ? 4 : 2;  // within 128 VGPRs
   double acc = 0.0;
   const int ntiles = num_tiles(q);
   const T c6 = T(1) / T(6);
+  const int64_t sy = q.sy, sz = q.sz;
   for (int tile = rank; tile < ntiles; tile += q.team) {
     int i, j, k0, k1;
     if (!tile_column(q, tile, i, j, k0, k1) || k0 >= k1) continue;
     int64_t p = off3(q, i, j, k0);
-    T zm = src[p - q.sz], zc = src[p];
-    for (int k = k0; k < k1; ++k, p += q.sz) {
-      const T zp = src[p + q.sz];
-      const T xp = src[p + 1], xm = src[p - 1], yp = src[p + q.sy], ym = src[p - q.sy];
-      const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
-      const T fv = f ? f[p] : T(0);
-      dst[p] = f ? (s - fv) * c6 : s * c6;
-      const double sd = ((((double(xp) + double(xm)) + double(yp)) + double(ym)) + double(zp)) +
-                        double(zm);
-      const double lap = sd - double(zc) * 6.0;
-      const double r = f ? double(fv) - lap : -lap;
-      acc += r * r;
-      zm = zc;
-      zc = zp;
+    T zm = src[p - sz], zc = src[p];
+    for (int k = k0; k < k1; k += kUnroll, p += kUnroll * sz) {
+      T xp[kUnroll], xm[kUnroll], yp[kUnroll], ym[kUnroll], zp[kUnroll], fv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t r = p + u * sz;
+        const bool in = k + u < k1;
+        xp[u] = in ? src[r + 1] : T(0);
+        xm[u] = in ? src[r - 1] : T(0);
+        yp[u] = in ? src[r + sy] : T(0);
+        ym[u] = in ? src[r - sy] : T(0);
+        zp[u] = in ? src[r + sz] : T(0);
+        fv[u] = (in && f) ? f[r] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        if (k + u >= k1) break;
+        const T s = ((((xp[u] + xm[u]) + yp[u]) + ym[u]) + zp[u]) + zm;
+        dst[p + u * sz] = f ? (s - fv[u]) * c6 : s * c6;
+        const double sd = ((((double(xp[u]) + double(xm[u])) + double(yp[u])) + double(ym[u])) +
+                           double(zp[u])) + double(zm);
+        const double lap = sd - double(zc) * 6.0;
+        const double r = f ? double(fv[u]) - lap : -lap;
+        acc += r * r;
+        zm = zc;
+        zc = zp[u];
+      }
     }
   }
   return acc;
@@ -261,14 +297,14 @@ template <typename T>
 __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
                                double tol_rel, double ref_fixed, bool ref_from_first,
                                int64_t cap, double* red, double* cell, double* hist,
-                               int* s_flag, int* status) {
+                               int* s_flag, unsigned* epoch, int* status) {
   double ref = ref_fixed;
   for (int64_t j = 0;; ++j) {
     const T* src = (j & 1) ? b1 : b0;
     T* dst = (j & 1) ? b0 : b1;
     const double mine = block_sum(sweep_tiles<T>(q, rank, src, dst, f), red);
     if (threadIdx.x == 0) q.part[(int64_t)(j & 1) * q.team + rank] = mine;
-    if (!team_barrier(a, q, s_flag)) return -1;
+    if (!team_barrier(a, q, s_flag, epoch)) return -1;
     const double norm = bcast(sqrt(team_sum(q, (int)(j & 1), red)), cell);
     if (ref_from_first && j == 0) ref = norm;
     if (threadIdx.x == 0) hist[j % (kStallMax + 1)] = norm;
@@ -286,16 +322,21 @@ __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1,
   }
 }
 
-__global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
+// At most 128 VGPRs: four waves per SIMD (four resident blocks per CU).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void batched_kernel(BatchK a) {
   __shared__ double red[kWavesY];
   __shared__ double cell;
   __shared__ double hist[kStallMax + 1];
   __shared__ int s_flag;
+  __shared__ unsigned s_epoch;  // barriers passed (thread 0 only)
+  if (threadIdx.x == 0) s_epoch = 0;
   const int qi = a.block_team[blockIdx.x];
   const int rank = a.block_rank[blockIdx.x];
   Inst& q = a.inst[qi];
   const double ncells = (double)q.nx * q.ny * q.nz;
   int status = MS_OK;
+  if (rank == 0 && threadIdx.x == 0) q.t_start = (int64_t)__builtin_amdgcn_s_memrealtime();
 
   // reference norm ||r(u^0)|| (interior zeroed)
   {
@@ -306,14 +347,14 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
       zero_span<float>(q, rank, q.e0);
       zero_span<float>(q, rank, q.e1);
     }
-    if (!team_barrier(a, q, &s_flag)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
   }
   const double res0 = bcast(sqrt(team_sum(q, 0, red)), &cell);
-  if (!team_barrier(a, q, &s_flag)) return;  // partial slot 0 is reused below
+  if (!team_barrier(a, q, &s_flag, &s_epoch)) return;  // partial slot 0 is reused below
 
   if (a.mode == MS_SOLVE_F64) {
     int64_t K = team_jacobi<double>(a, q, rank, q.x, q.xb, q.f, a.tol, res0, false,
-                                    a.max_sweeps, red, &cell, hist, &s_flag, &status);
+                                    a.max_sweeps, red, &cell, hist, &s_flag, &s_epoch, &status);
     if (K < 0) return;
     // the answer is buffer K % 2; bring it into x
     if (K & 1) {
@@ -333,6 +374,7 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
       q.sweeps = K;
       q.outer = 0;
       q.status = status;
+      q.t_end = (int64_t)__builtin_amdgcn_s_memrealtime();
     }
     return;
   }
@@ -343,10 +385,10 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
   for (;;) {
     const double mine = block_sum(residual_tiles(q, rank, false, nullptr, 0.0), red);
     if (threadIdx.x == 0) q.part[rank] = mine;
-    if (!team_barrier(a, q, &s_flag)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
     nr = bcast(sqrt(team_sum(q, 0, red)), &cell);
     rel = res0 > 0.0 ? nr / res0 : 0.0;
-    if (!team_barrier(a, q, &s_flag)) return;  // slot 0 is rewritten below
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;  // slot 0 is rewritten below
     if (!isfinite(nr)) {
       status = MS_ENONFINITE;
       break;
@@ -358,20 +400,20 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
     }
     const double sc = pow2_scale_dev(nr, ncells);
     residual_tiles(q, rank, false, q.rhat, 1.0 / sc);
-    if (!team_barrier(a, q, &s_flag)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
     const double eta = fmax(a.eta, 0.5 * a.tol / rel);
     int64_t cap = a.max_inner;
     if (a.max_sweeps - total < cap) cap = a.max_sweeps - total;
     int inner_status = MS_OK;
     const int64_t K = team_jacobi<float>(a, q, rank, q.e0, q.e1, q.rhat, eta, 0.0, true, cap,
-                                         red, &cell, hist, &s_flag, &inner_status);
+                                         red, &cell, hist, &s_flag, &s_epoch, &inner_status);
     if (K < 0) return;
     if (inner_status == MS_ENONFINITE) {
       status = MS_ENONFINITE;
       break;
     }
     update_tiles(q, rank, (K & 1) ? q.e1 : q.e0, sc);
-    if (!team_barrier(a, q, &s_flag)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
     total += K;
     ++outer;
   }
@@ -382,6 +424,7 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
     q.sweeps = total;
     q.outer = outer;
     q.status = status;
+    q.t_end = (int64_t)__builtin_amdgcn_s_memrealtime();
   }
 }
 
@@ -390,8 +433,8 @@ __global__ __launch_bounds__(kThreads) void batched_kernel(BatchK a) {
 // its rank-0 block records the elapsed real-time clock ticks.
 template <typename T>
 __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
-                          int nsweeps, double* red, int* s_flag) {
-  if (!team_barrier(a, q, s_flag)) return;
+                          int nsweeps, double* red, int* s_flag, unsigned* epoch) {
+  if (!team_barrier(a, q, s_flag, epoch)) return;
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   double chk = 0.0;
   for (int j = 0; j < nsweeps; ++j) {
@@ -399,7 +442,7 @@ __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, cons
     T* dst = (j & 1) ? b0 : b1;
     const double mine = block_sum(sweep_tiles<T>(q, rank, src, dst, f), red);
     if (threadIdx.x == 0) q.part[(int64_t)(j & 1) * q.team + rank] = mine;
-    if (!team_barrier(a, q, s_flag)) return;
+    if (!team_barrier(a, q, s_flag, epoch)) return;
     chk += team_sum(q, j & 1, red);
   }
   if (rank == 0 && threadIdx.x == 0) {
@@ -408,15 +451,18 @@ __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, cons
   }
 }
 
-__global__ __launch_bounds__(kThreads) void batched_tune_kernel(BatchK a, int nsweeps) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void batched_tune_kernel(BatchK a, int nsweeps) {
   __shared__ double red[kWavesY];
   __shared__ int s_flag;
+  __shared__ unsigned s_epoch;
+  if (threadIdx.x == 0) s_epoch = 0;
   Inst& q = a.inst[a.block_team[blockIdx.x]];
   const int rank = a.block_rank[blockIdx.x];
   if (a.mode == MS_SOLVE_F64)
-    tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag);
+    tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag, &s_epoch);
   else
-    tune_team<float>(a, q, rank, q.e0, q.e1, q.rhat, nsweeps, red, &s_flag);
+    tune_team<float>(a, q, rank, q.e0, q.e1, q.rhat, nsweeps, red, &s_flag, &s_epoch);
 }
 
 // ------------------------------------------------------------------ host
@@ -697,7 +743,10 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   MS_HIP_TRY(hipMemcpy(h.data(), dinst, sizeof(Inst) * n, hipMemcpyDeviceToHost));
   if (herr) return set_error(MS_EHIP, "jacobi_solve_batched: a team barrier timed out");
   int worst = MS_OK;
+  int64_t t0 = h[0].t_start;
+  for (int i = 1; i < n; ++i) t0 = std::min(t0, h[i].t_start);
   for (int i = 0; i < n; ++i) {
+    res[i].seconds = (double)(h[i].t_end - t0) * 1e-8;  // 100 MHz clock
     res[i].sweeps = h[i].sweeps;
     res[i].outer_iters = h[i].outer;
     res[i].status = h[i].status;

@@ -11,6 +11,8 @@
 // being written).
 #include "ms_internal.hpp"
 
+#include <chrono>
+
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -591,8 +593,12 @@ extern "C" int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,
     return set_error(MS_EINVAL, "jacobi_solve: workspace overlaps a field");
   Workspace ws{static_cast<char*>(work), work_bytes};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o->precision == MS_SOLVE_F64) return solve_f64(*g, *o, u, f, ws, hist_host, res, s);
-  return solve_refined(*g, *o, u, f, ws, hist_host, res, s);
+  const auto t0 = std::chrono::steady_clock::now();
+  *res = ms_solve_result{};
+  const int rc = o->precision == MS_SOLVE_F64 ? solve_f64(*g, *o, u, f, ws, hist_host, res, s)
+                                              : solve_refined(*g, *o, u, f, ws, hist_host, res, s);
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return rc;
 }
 
 // ---------------------------------------------------------------- autotuner

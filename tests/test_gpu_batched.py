@@ -142,3 +142,34 @@ def test_autotune_picks_valid_shapes_and_leaves_x_alone():
         assert np.array_equal(fa, fb)
         res0 = oracle.residual_norm(oracle.zero_interior(u), f)
         assert oracle.residual_norm(fb, f) <= 1e-8 * res0 * (1 + 1e-9)
+
+
+def test_full_batch_of_64_uneven_instances_after_autotuning():
+    """The benchmark's batch at full size: 64 instances, per-axis sizes
+    log-uniform in [32, 256] (seed 4), 8 Gaussian sources each, FP32-refined
+    to 1e-8 with autotuned tile shapes. Every instance's final residual is
+    recomputed by the oracle; the three smallest are compared bit for bit
+    with single-instance solves."""
+    note("case: batched 64 instances, sizes log-uniform [32, 256], seed 4")
+    dims = synth.batch_sizes(64, 4)
+    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 4000 + i))
+             for i, d in enumerate(dims)]
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, max_outer=40)
+    ms.batch_tuning_clear()
+    ms.batched_autotune(xs, fs, sweeps_per_trial=10, **opts)
+    infos = ms.jacobi_solve_batched(xs, fs, **opts)
+    ms.batch_tuning_clear()
+    for (u, f), x, info in zip(probs, xs, infos):
+        assert info.status == ms.MS_OK
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        assert info.res0 == pytest.approx(res0, rel=1e-12)
+        assert oracle.residual_norm(host(x), f) <= 1e-8 * res0 * (1 + 1e-9)
+    small = sorted(range(len(dims)), key=lambda i: np.prod(dims[i]))[:3]
+    for i in small:
+        u, f = probs[i]
+        single = dev(u)
+        s = ms.jacobi_solve(single, dev(f), **opts)
+        assert (s.sweeps, s.outer_iters) == (infos[i].sweeps, infos[i].outer_iters)
+        assert np.array_equal(host(single), host(xs[i]))
