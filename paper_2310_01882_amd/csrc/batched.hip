@@ -16,7 +16,7 @@
 // The per-cell arithmetic is the single-instance path's (same operation
 // order), so each instance's iterates are those of jacobi_solve.
 //
-// Tile shapes. A team walks its instance in tiles of tx x-cells by 4 * 64/tx
+// Tile shapes. A team walks its instance in tiles of tx x-cells by 16 * 64/tx
 // rows (each wave covers 64/tx rows of tx lanes), split into zs chunks along
 // z; tiles go round-robin over the team's blocks. Narrow tiles waste fewer
 // lanes on an x extent that is not a multiple of 64; z chunks even out the
@@ -42,7 +42,11 @@
 namespace ms {
 namespace {
 
-constexpr int kBatchTX = 64, kBatchTY = kWavesY;  // default tile: 64 x 4 columns, whole z
+// Blocks of 16 waves: a one-block team still keeps a whole CU's worth of
+// loads in flight, and big teams have few blocks to synchronise.
+constexpr int kBatchWaves = 16;
+constexpr int kBatchThreads = 64 * kBatchWaves;
+constexpr int kBatchTX = 64, kBatchTY = kBatchWaves;  // default tile: 64 x 16 columns, whole z
 constexpr int kStallMax = 1024;                    // longest stagnation window
 // Candidate tile shapes for the autotuner: lanes per row x z chunks.
 constexpr int kShapeTX[] = {64, 32, 16};
@@ -98,7 +102,7 @@ __device__ __forceinline__ bool tile_column(const Inst& q, int tile, int& i, int
   const int txy = q.tiles_x * q.tiles_y;
   const int c = tile / txy, t = tile - c * txy;
   i = (t % q.tiles_x) * q.tx + lane % q.tx;
-  j = (t / q.tiles_x) * (kWavesY * rw) + w * rw + lane / q.tx;
+  j = (t / q.tiles_x) * (kBatchWaves * rw) + w * rw + lane / q.tx;
   k0 = (int)((int64_t)c * q.nz / q.zs);
   k1 = (int)((int64_t)(c + 1) * q.nz / q.zs);
   return i < q.nx && j < q.ny;
@@ -323,9 +327,9 @@ __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1,
 }
 
 // At most 128 VGPRs: four waves per SIMD (four resident blocks per CU).
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void batched_kernel(BatchK a) {
-  __shared__ double red[kWavesY];
+  __shared__ double red[kBatchWaves];
   __shared__ double cell;
   __shared__ double hist[kStallMax + 1];
   __shared__ int s_flag;
@@ -451,9 +455,9 @@ __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, cons
   }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void batched_tune_kernel(BatchK a, int nsweeps) {
-  __shared__ double red[kWavesY];
+  __shared__ double red[kBatchWaves];
   __shared__ int s_flag;
   __shared__ unsigned s_epoch;
   if (threadIdx.x == 0) s_epoch = 0;
@@ -492,7 +496,7 @@ bool valid_shape(int tx, int zs) {
 void set_shape(Inst& q, int tx, int zs) {
   q.tx = tx;
   q.zs = zs;
-  const int ty = kWavesY * (64 / tx);
+  const int ty = kBatchWaves * (64 / tx);
   q.tiles_x = (q.nx + tx - 1) / tx;
   q.tiles_y = (q.ny + ty - 1) / ty;
 }
@@ -580,7 +584,7 @@ int resident_blocks_of(K kernel) {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBatchThreads, 0) != hipSuccess)
     return 0;
   return cus * per;
 }
@@ -724,7 +728,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   MS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(batched_kernel, dim3(P.G), dim3(kThreads), 0, cap, a);
+    hipLaunchKernelGGL(batched_kernel, dim3(P.G), dim3(kBatchThreads), 0, cap, a);
     e = hipStreamEndCapture(cap, &graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -875,7 +879,8 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
     MS_HIP_TRY(hipMemcpyAsync(dinst, h.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s));
     MS_HIP_TRY(hipMemsetAsync(derr, 0, 256, s));
     for (int i = 0; i < n; ++i) MS_HIP_TRY(hipMemsetAsync(h[i].bar, 0, 256, s));
-    hipLaunchKernelGGL(batched_tune_kernel, dim3(P.G), dim3(kThreads), 0, s, a, sweeps_per_trial);
+    hipLaunchKernelGGL(batched_tune_kernel, dim3(P.G), dim3(kBatchThreads), 0, s, a,
+                       sweeps_per_trial);
     MS_HIP_TRY(hipGetLastError());
     MS_HIP_TRY(hipStreamSynchronize(s));
     int herr = 0;
