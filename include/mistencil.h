@@ -232,10 +232,12 @@ void ms_tuning_clear(void);
 /* ---- batched solves ---------------------------------------------------------
  * Many independent instances of jacobi_solve, each with its own grid,
  * solved in ONE persistent kernel launch (captured in a hipGraph). The
- * device's resident blocks are split into teams, one per instance, sized by
- * the instance's estimated work (cells x Jacobi sweeps to rel_tol from the
- * spectral radius); a team runs its instance's whole solve with team
- * barriers and never waits for another team. precision: MS_SOLVE_F64 or
+ * device's resident blocks are split into teams, one per instance, so that
+ * the longest estimated finish time is as short as possible (estimate:
+ * cells x Jacobi sweeps to rel_tol from the spectral radius, split over the
+ * team, plus a per-sweep barrier cost for teams of more than one block); a
+ * team runs its instance's whole solve with team barriers and never waits
+ * for another team. precision: MS_SOLVE_F64 or
  * MS_SOLVE_F32_REFINED with the refinement rules of jacobi_solve (same
  * per-cell arithmetic, same stopping rules; norms are summed per team, so an
  * iteration count may differ from jacobi_solve's by one only when a norm

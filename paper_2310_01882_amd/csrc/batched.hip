@@ -2,9 +2,10 @@
 // persistent launch.
 //
 // The grid holds G blocks, no more than can be resident at once. Blocks are
-// split into teams, one per instance, sized by the instance's estimated
-// work (cells x Jacobi sweeps to the tolerance, from the spectral radius)
-// and placed XCD by XCD so that a team shares an L2 where it can. A team
+// split into teams, one per instance, balancing the instances' estimated
+// finish times (cells x Jacobi sweeps to the tolerance, from the spectral
+// radius, over the team size, plus a barrier cost per sweep), and placed
+// XCD by XCD so that a team shares an L2 where it can. A team
 // runs its instance's whole solve -- FP64 Jacobi, or FP32-storage Jacobi
 // inside FP64 iterative refinement -- with team barriers (a counter and a
 // generation word in device memory) between dependent steps; it never waits
@@ -477,12 +478,23 @@ struct Plan {
   size_t bytes = 0;
 };
 
-double est_work(const ms_grid& g, double tol) {
+// Estimated Jacobi sweeps to the tolerance: the decay of the slowest mode,
+// whose factor per sweep is the spectral radius (mean of cos(pi/(n+1))).
+double est_sweeps(const ms_grid& g, double tol) {
   const double pi = 3.14159265358979323846;
   const double rho =
       (std::cos(pi / (g.nx + 1)) + std::cos(pi / (g.ny + 1)) + std::cos(pi / (g.nz + 1))) / 3.0;
   const double k = std::log(std::max(tol, 1e-300)) / std::log(std::min(rho, 1.0 - 1e-16));
-  return (double)g.nx * g.ny * g.nz * std::max(k, 1.0);
+  return std::max(k, 1.0);
+}
+
+// Estimated solve time on a team of t blocks, in units of one block's time
+// per cell update: the sweeps split over the team, plus one team barrier per
+// sweep when t > 1, worth kBarrierCells cell updates (measured: about 5 us
+// against about 1.3e9 FP32 updates per second for one block).
+constexpr double kBarrierCells = 8192.0;
+double est_time(double cells, double sweeps, int t) {
+  return cells * sweeps / t + (t > 1 ? sweeps * kBarrierCells : 0.0);
 }
 
 int tiles_of(const ms_grid& g) {
@@ -528,30 +540,33 @@ ShapeRec lookup_shape(int prec, const ms_grid& g, int team) {
   return it->second;
 }
 
-// Splits G blocks into teams proportional to estimated work (at least one
-// block, at most one per default tile split into the most z chunks), then
-// lays the teams out XCD by XCD.
+// Splits up to G blocks into teams, one block at a time to the instance
+// whose estimated finish time (est_time) is the longest and would shrink
+// with one more block -- greedy makespan balancing; every team has at least
+// one block and at most one per default tile split into the most z chunks.
+// Then lays the teams out XCD by XCD.
 void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
-  std::vector<double> w(n);
-  for (int i = 0; i < n; ++i) w[i] = est_work(inst[i].grid, tol);
-  const double W = std::accumulate(w.begin(), w.end(), 0.0);
+  std::vector<double> cells(n), sweeps(n);
+  for (int i = 0; i < n; ++i) {
+    const ms_grid& g = inst[i].grid;
+    cells[i] = (double)g.nx * g.ny * g.nz;
+    sweeps[i] = est_sweeps(g, tol);
+  }
   P.team.assign(n, 1);
   int used = n;
-  std::vector<double> want(n);
-  for (int i = 0; i < n; ++i) want[i] = G * w[i] / W;
-  // largest deficit first, one block at a time
   while (used < G) {
     int best = -1;
-    double bd = 0.0;
+    double bt = 0.0;
     for (int i = 0; i < n; ++i) {
       if (P.team[i] >= tiles_of(inst[i].grid) * kShapeZS[3]) continue;
-      const double d = want[i] - P.team[i];
-      if (best < 0 || d > bd) {
+      const double cur = est_time(cells[i], sweeps[i], P.team[i]);
+      if (est_time(cells[i], sweeps[i], P.team[i] + 1) >= cur) continue;
+      if (best < 0 || cur > bt) {
         best = i;
-        bd = d;
+        bt = cur;
       }
     }
-    if (best < 0 || bd <= 0.0) break;
+    if (best < 0) break;
     ++P.team[best];
     ++used;
   }
