@@ -282,6 +282,14 @@ def bench_solve(args):
     def fresh():  # a new aligned field holding the zero start (clone() drops the padding)
         return ms.field_from(u_h)
 
+    # tile shapes from the autotuner for both storage precisions (the FP32
+    # inner sweeps run on workspace grids with the same extents and alignment)
+    t0 = time.perf_counter()
+    tuned = {"f64": ms.autotune_sweeps(fresh(), fresh(), f)}
+    f32 = ms.field_from(f_h, torch.float32)
+    tuned["f32"] = ms.autotune_sweeps(ms.field_from(u_h, torch.float32),
+                                      ms.field_from(u_h, torch.float32), f32)
+    log(f"[bench] autotuned sweep shapes in {time.perf_counter() - t0:.2f} s: {tuned}")
     F64, F32R = ms.MS_SOLVE_F64, ms.MS_SOLVE_F32_REFINED
     variants = [("fp64", dict(precision=F64)),
                 ("fp64_tb2", dict(precision=F64, temporal_block=2)),
@@ -357,6 +365,7 @@ def bench_solve(args):
         "config": {"workload": f"poisson_{n}cubed_to_1e-8", "rhs": "8 Gaussian sources (seed 1)",
                    "boundary": "zero Dirichlet", "value_is": value_name,
                    "parallelism": "single GPU"},
+        "sweep_shapes": tuned,
         "speedup_vs_fp64": round(rows["fp64"]["seconds"] / v, 3),
         "solves": rows,
     }

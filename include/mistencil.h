@@ -225,6 +225,13 @@ int ms_autotune_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const 
                        int sweeps_per_trial, void* work, size_t work_bytes,
                        ms_tuning* best, void* stream);
 /* Copies up to cap entries into out; returns the number of entries. */
+/* The sweep shape jacobi_sweeps / jacobi_solve would use for a grid of this
+ * dtype whose buffers are `bufs` (host-side query, no device work): vec_ok
+ * is the vector width the buffers' alignment allows, vec / wx / rows the
+ * shape, target_blocks the block count of one sweep launch, us_per_sweep
+ * the tuned time if the shape came from the tuning table, else 0. */
+int ms_sweep_shape(const ms_grid* g, int dtype, const void* const* bufs, int nbufs,
+                   ms_tuning* out);
 int ms_tuning_get(ms_tuning* out, int cap);
 int ms_tuning_set(const ms_tuning* in, int n);
 void ms_tuning_clear(void);

@@ -120,6 +120,8 @@ SIGNATURES = {
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "ms_autotune_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I, _P, _SZ,
                                 ctypes.POINTER(Tuning), _P]),
+    "ms_sweep_shape": (_I, [ctypes.POINTER(Grid), _I, ctypes.POINTER(ctypes.c_void_p), _I,
+                            ctypes.POINTER(Tuning)]),
     "ms_tuning_get": (_I, [ctypes.POINTER(Tuning), _I]),
     "ms_tuning_set": (_I, [ctypes.POINTER(Tuning), _I]),
     "ms_tuning_clear": (None, []),

@@ -630,7 +630,7 @@ extern "C" int ms_autotune_sweeps(const ms_grid* g, int dtype, void* u, void* u_
     if (vec > vec_ok) continue;
     for (int wx : {1, 2, 4})
       for (int rows : {2, 4, 8})
-        for (int64_t tb : {256, 512, 1024, 2048}) {
+        for (int64_t tb : {64, 128, 256, 512, 1024, 2048}) {
           const SweepGeom geo = geom_register(*g, dtype, vec_ok, vec, wx, rows, 0, tb);
           if (geo.vec != vec || geo.nblocks > kMaxBlocks) continue;
           // one untimed sweep, then the timed trial
@@ -659,6 +659,26 @@ extern "C" int ms_autotune_sweeps(const ms_grid* g, int dtype, void* u, void* u_
   if (rc) return rc;
   tuned_store(out);
   *best = out;
+  return MS_OK;
+}
+
+extern "C" int ms_sweep_shape(const ms_grid* g, int dtype, const void* const* bufs, int nbufs,
+                              ms_tuning* out) {
+  clear_error();
+  if (int rc = check_grid(g, "ms_sweep_shape")) return rc;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "ms_sweep_shape: dtype %d", dtype);
+  if (!out || nbufs < 0 || (nbufs > 0 && !bufs))
+    return set_error(MS_EINVAL, "ms_sweep_shape: bad arguments");
+  const int vec_ok = vec_alignment(*g, dtype, bufs, nbufs);
+  const SweepGeom geo = sweep_geom(*g, dtype, vec_ok);
+  ms_tuning t{};
+  const bool tuned = tuned_lookup(*g, dtype, vec_ok, &t);
+  *out = ms_tuning{};
+  out->dtype = dtype; out->nx = g->nx; out->ny = g->ny; out->nz = g->nz;
+  out->vec_ok = vec_ok; out->vec = geo.vec; out->wx = geo.wx; out->rows = geo.rows;
+  out->target_blocks = geo.nblocks;
+  out->us_per_sweep = tuned ? t.us_per_sweep : 0.0;
   return MS_OK;
 }
 

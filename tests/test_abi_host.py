@@ -165,3 +165,31 @@ def test_batch_tuning_table_round_trip_without_a_device():
     assert ms.batch_tuning_table() == [e]  # a rejected load inserts nothing
     ms.batch_tuning_clear()
     assert ms.batch_tuning_table() == []
+
+
+def test_sweep_shape_query_follows_the_tuning_table_and_alignment():
+    import paper_2310_01882_amd as ms
+    n, sy = 128, 160
+    g = ms.Grid(n, n, n, 0, sy, sy * 130)
+    base = 0x7F0000000000
+    aligned = [base + k * (1 << 24) + 124 for k in range(4)]  # one float before 128 B
+
+    def shape(ptrs):
+        arr = (ctypes.c_void_p * len(ptrs))(*ptrs)
+        out = ms.Tuning()
+        assert ms.lib.ms_sweep_shape(ctypes.byref(g), ms.MS_F32, arr, len(ptrs),
+                                     ctypes.byref(out)) == ms.MS_OK
+        return out
+
+    ms.tuning_clear()
+    d = shape(aligned)
+    assert d.vec_ok == 4 and d.us_per_sweep == 0.0  # untuned default
+    e = dict(dtype=ms.MS_F32, nx=n, ny=n, nz=n, vec_ok=4, vec=1, wx=2, rows=2,
+             target_blocks=1024, us_per_sweep=8.4)
+    ms.tuning_load([e])
+    t = shape(aligned)
+    assert (t.vec, t.wx, t.rows, t.target_blocks, t.us_per_sweep) == (1, 2, 2, 1024, 8.4)
+    # one buffer off the 16-byte phase: narrower lanes, a different table key
+    m = shape(aligned[:3] + [aligned[3] + 4])
+    assert m.vec_ok == 1 and m.us_per_sweep == 0.0
+    ms.tuning_clear()
