@@ -514,7 +514,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=1000)
     ap.add_argument("--solve-n", type=int, default=128)
     ap.add_argument("--solve-reps", type=int, default=3)
-    ap.add_argument("--cpu-sweeps", type=int, default=2)
+    ap.add_argument("--cpu-sweeps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true",
                     help="batched mode: skip the one-by-one comparison")
