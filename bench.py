@@ -244,7 +244,7 @@ def bench_advect(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_for("advect_512x512x256"),
-                     "kernel": "advect_kernel", "bytes_per_launch_algorithmic": 48 * cells,
+                     "kernel": "advect_staged_kernel", "bytes_per_launch_algorithmic": 48 * cells,
                      "avg_launch_us": round(secs / passes * 1e6, 3)},
         "cpu_baseline": cpu,
     }

@@ -8,7 +8,8 @@
 // where P on each side is phi at the neighbour on that side times the sum of
 // the two samples of the advecting velocity that straddle that face.
 //
-// Staged kernel (default): a block owns a 64 x 8 (x, y) tile and marches a
+// Staged kernel (default): a block owns a 64 x 4 (x, y) tile (one row per
+// thread; 64 x 8 with two rows per thread is the alternative) and marches a
 // z-chunk. Planes of u, v, w (tile plus a one-cell ring, corners included)
 // pass through a ring of four LDS buffers: at level k the block reads level
 // k (all in-plane neighbours) and level k+1 (the four off-column values the
@@ -53,13 +54,15 @@ __device__ __forceinline__ double combine(double tcx, double tcy, double c1, dou
 // ------------------------------------------------------------ staged kernel
 
 constexpr int kAdvTX = 64;
-constexpr int kAdvRows = 2;                  // rows per thread
-constexpr int kAdvTY = kWavesY * kAdvRows;   // 8
-constexpr int kAdvLX = kAdvTX + 2;           // 66
-constexpr int kAdvLY = kAdvTY + 2;           // 10
-constexpr int kAdvRing = 2 * kAdvLX + 2 * kAdvTY;  // 148 ring cells per field
+constexpr int kAdvLX = kAdvTX + 2;  // 66
 
+// kAdvRows rows per thread: tile 64 x 4*kAdvRows, LDS 4 x 3 x (tile + ring).
+template <int kAdvRows>
 __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
+  constexpr int kAdvTY = kWavesY * kAdvRows;
+  constexpr int kAdvLY = kAdvTY + 2;
+  constexpr int kAdvRing = 2 * kAdvLX + 2 * kAdvTY;  // ring cells per field
+  static_assert(kAdvRing <= kThreads, "one ring cell per thread");
   __shared__ double L[4][3][kAdvLY][kAdvLX];
 
   const int tile = xcd_tile(blockIdx.x, a.nblocks);
@@ -279,13 +282,19 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
     MS_LAUNCH_CHECK();
     return MS_OK;
   }
-  // Staged kernel: about two resident blocks per CU, each marching long z.
+  // Staged kernel: one block round of long z marches. MS_ADVECT_ROWS (1 or
+  // 2 rows per thread) and MS_ADVECT_BLOCKS (target grid) are tuning knobs.
+  // Measured at 512 x 512 x 256: one row per thread (38 KB of LDS, four
+  // resident blocks per CU) and 1024 blocks beat two rows (63 KB, two per CU)
+  // by 7%.
+  const int rows = env_int("MS_ADVECT_ROWS") == 2 ? 2 : 1;
+  const int64_t want = env_int("MS_ADVECT_BLOCKS") > 0 ? env_int("MS_ADVECT_BLOCKS") : 1024;
   a.tiles_x = (g->nx + kAdvTX - 1) / kAdvTX;
-  a.tiles_y = (g->ny + kAdvTY - 1) / kAdvTY;
+  a.tiles_y = (g->ny + kWavesY * rows - 1) / (kWavesY * rows);
   const int64_t tiles2d = (int64_t)a.tiles_x * a.tiles_y;
   int zc = env_int("MS_ADVECT_ZC");
   if (zc <= 0) {
-    int64_t chunks = (512 + tiles2d - 1) / tiles2d;
+    int64_t chunks = (want + tiles2d - 1) / tiles2d;
     zc = (int)((g->nz + chunks - 1) / chunks);
     if (zc < 4) zc = 4;
   }
@@ -294,7 +303,10 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   if (nb > 0x7fffffffLL) return set_error(MS_EUNSUPPORTED, "advect_source: grid too large");
   a.zc = zc;
   a.nblocks = (int)nb;
-  hipLaunchKernelGGL(advect_staged_kernel, dim3(a.nblocks), dim3(kThreads), 0, s, a);
+  if (rows == 1)
+    hipLaunchKernelGGL(advect_staged_kernel<1>, dim3(a.nblocks), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(advect_staged_kernel<2>, dim3(a.nblocks), dim3(kThreads), 0, s, a);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

@@ -24,13 +24,16 @@ def _advect_gpu(u, v, w, t1, t2, tcx, tcy, pad=(0, 0)):
 
 @pytest.mark.parametrize("dims", [(1, 1, 1), (5, 4, 3), (64, 16, 8), (67, 19, 13), (130, 70, 9),
                                   (64, 8, 40)])
-@pytest.mark.parametrize("variant", ["staged", "direct", "staged-zc3"])
+@pytest.mark.parametrize("variant", ["staged", "direct", "staged-zc3", "staged-rows2",
+                                     "staged-rows2-zc3"])
 def test_advection_bit_exact(dims, variant, monkeypatch):
     note(f"case: advect {dims} {variant}")
     if variant == "direct":
         monkeypatch.setenv("MS_ADVECT_VARIANT", "0")
-    if variant == "staged-zc3":
+    if variant.endswith("zc3"):
         monkeypatch.setenv("MS_ADVECT_ZC", "3")
+    if "rows2" in variant:
+        monkeypatch.setenv("MS_ADVECT_ROWS", "2")
     nx, ny, nz = dims
     u, v, w = synth.velocity_fields(nx, ny, nz, 2)
     t1, t2 = synth.tzc_arrays(nz, 3)
