@@ -565,9 +565,13 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
       store_a(r, k);
     }
   }
-  T pre[QA];
+  // Two register sets of prefetched u_k levels: at step z the set of parity
+  // (z - z0 + 1) holds level z+2, is stored to LDS and refilled with level
+  // z+4, so two levels of loads are in flight behind the compute.
+  T preA[QA], preB[QA];
   const int klast = min(z1 + 1, nz);  // last u_k level stage A needs
-  load_a(pre, z0 + 1);                // z0 + 1 <= nz always
+  load_a(preA, z0 + 1);               // z0 + 1 <= nz always
+  if (z0 + 2 <= klast) load_a(preB, z0 + 2);
   __syncthreads();
 
   double acc_a = 0.0, acc_b = 0.0;
@@ -620,11 +624,11 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
 #pragma unroll
   for (int q = 0; q < QO; ++q) fb[q] = T(0);
 
-  for (int z = z0 - 1; z <= z1; ++z) {
-    // 1. publish level z+2 of u_k (read from step z+1 on), prefetch z+3
+  auto step = [&](int z, T (&pre)[QA]) {
+    // 1. publish level z+2 of u_k (read from step z+1 on), prefetch z+4
     if (z + 2 <= klast) {
       store_a(pre, z + 2);
-      if (z + 3 <= klast) load_a(pre, z + 3);
+      if (z + 4 <= klast) load_a(pre, z + 4);
     }
     T fa_n[QB], fb_n[QO];
     ld_fa(fa_n, z + 1);
@@ -677,6 +681,10 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     for (int q = 0; q < QB; ++q) fa[q] = fa_n[q];
 #pragma unroll
     for (int q = 0; q < QO; ++q) fb[q] = fb_n[q];
+  };
+  for (int z = z0 - 1; z <= z1; z += 2) {
+    step(z, preA);
+    if (z + 1 <= z1) step(z + 1, preB);
   }
 
   const double ta = block_sum(acc_a, red);
@@ -792,7 +800,7 @@ int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
 
 int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 
-SweepGeom tb2_geom(const ms_grid& g) {
+SweepGeom tb2_geom(const ms_grid& g, int dtype) {
   SweepGeom s{};
   s.variant = kVariantLds;
   s.vec = 1;
@@ -801,10 +809,11 @@ SweepGeom tb2_geom(const ms_grid& g) {
   s.tiles_x = (g.nx + kTbX - 1) / kTbX;
   s.tiles_y = (g.ny + kTbY - 1) / kTbY;
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
-  // about eight blocks per CU (measured best at 512^3 FP64), marches of at
-  // least 8 levels; MS_TB_BLOCKS overrides the target for tuning
+  // Block targets measured at 512^3 (three FP64 / four FP32 blocks are
+  // resident per CU): 1536 for FP64, 1024 for FP32; marches of at least 8
+  // levels. MS_TB_BLOCKS overrides the target for tuning.
   const char* ev = getenv("MS_TB_BLOCKS");
-  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 2048;
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : (dtype == MS_F64 ? 1536 : 1024);
   int64_t chunks = (want + tiles2d - 1) / tiles2d;
   int zc = (int)((g.nz + chunks - 1) / chunks);
   if (zc < 8) zc = 8;
@@ -818,12 +827,12 @@ SweepGeom tb2_geom(const ms_grid& g) {
   return s;
 }
 
-int tb2_blocks(const ms_grid& g) { return tb2_geom(g).nblocks; }
+int tb2_blocks(const ms_grid& g, int dtype) { return tb2_geom(g, dtype).nblocks; }
 
 int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
                      const void* f, double* partials, double* hist, Ctl* ctl, int64_t k_off,
                      hipStream_t s) {
-  const SweepGeom geo = tb2_geom(g);
+  const SweepGeom geo = tb2_geom(g, dtype);
   if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
     return set_error(MS_EUNSUPPORTED, "two-sweep geometry with %d blocks", geo.nblocks);
   const dim3 grid(geo.nblocks), block(kThreads);

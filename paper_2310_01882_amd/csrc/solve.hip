@@ -354,8 +354,8 @@ extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tm
         return rc;
     if (res_dev && nl >= 1)
       for (int64_t k = 2 * nl - 2; k < 2 * nl; ++k)
-        if (int rc = launch_finalize(partials, (int)(k & 3), tb2_blocks(*g), nullptr, nullptr,
-                                     res_dev, k, s))
+        if (int rc = launch_finalize(partials, (int)(k & 3), tb2_blocks(*g, dtype), nullptr,
+                                     nullptr, res_dev, k, s))
           return rc;
     last = bufs[nl % 2];
     if (n & 1) {
