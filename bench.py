@@ -116,6 +116,8 @@ def bench_jacobi(args, dtype_name="f64"):
         f"{launch_s * 1e6:.1f} us per sweep launch; final residual {res[-1].item():.6e}")
     key = f"jacobi7_{dtype_name}_{n}"
     traffic = traffic_for(key)
+    tb_traffic = traffic_for(f"jacobi7tb2_{dtype_name}_{n}")
+    ceiling = copy_ceiling()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_jacobi(u_h, f_h, np_dt, args.cpu_sweeps)
@@ -166,10 +168,35 @@ def bench_jacobi(args, dtype_name="f64"):
             "glups": round(tb_glups, 3),
             "ms_per_step": round(tb_secs / args.steps * 1e3, 4),
             "gb_per_s_algorithmic": round(bpl / 2 * n ** 3 * sweeps * args.steps / tb_secs / 1e9, 1),
+            "traffic_per_pass": tb_traffic,
+            "gb_per_s_measured": (round(tb_traffic * (sweeps // 2) * args.steps / tb_secs / 1e9, 1)
+                                  if tb_traffic else None),
             "note": "two sweeps per pass over memory: 12 B/LUP (FP64) algorithmic",
         },
+        "hbm_copy_ceiling_gbs": ceiling,
     }
     return out
+
+
+def copy_ceiling(mib=1024, reps=10):
+    """Practical HBM ceiling on this device: GB/s of a plain device-to-device
+    copy of `mib` MiB (read + write bytes), timed with events."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbs, 1)
 
 
 def cpu_baseline_jacobi(u_h, f_h, np_dt, nsweeps):
@@ -295,17 +322,26 @@ def bench_solve(args):
                                       ms.field_from(u_h, torch.float32), f32)
     log(f"[bench] autotuned sweep shapes in {time.perf_counter() - t0:.2f} s: {tuned}")
     F64, F32R = ms.MS_SOLVE_F64, ms.MS_SOLVE_F32_REFINED
+    # reference answer for the field errors: FP64 Jacobi to a 1e-10 relative residual
+    x_ref = fresh()
+    ms.jacobi_solve(x_ref, f, precision=F64, rel_tol=1e-10)
+    ref_norm = torch.linalg.vector_norm(x_ref).item()
+
+    def field_error(x):
+        return torch.linalg.vector_norm(x - x_ref).item() / ref_norm
+
     variants = [("fp64", dict(precision=F64)),
                 ("fp64_tb2", dict(precision=F64, temporal_block=2)),
                 ("fp32_refined", dict(precision=F32R)),
                 ("fp32_refined_tb2", dict(precision=F32R, temporal_block=2))]
     rows = {}
 
-    def record(name, times, info):
+    def record(name, times, info, x):
         dt = statistics.median(times)
         rows[name] = {"seconds": round(dt, 4), "seconds_all": [round(t, 4) for t in times],
                       "sweeps": info.sweeps, "outer": info.outer_iters,
                       "rel_final": info.rel_final,
+                      "field_rel_error_vs_fp64_1e-10": field_error(x),
                       "glups": round(n ** 3 * info.sweeps / dt / 1e9, 2)}
         log(f"[bench] {name}: {dt:.3f} s, {info.sweeps} sweeps, rel {info.rel_final:.3e}")
 
@@ -320,7 +356,7 @@ def bench_solve(args):
             info = ms.jacobi_solve(u, f, work=work, rel_tol=1e-8, **kw)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
-        record(name, times, info)
+        record(name, times, info, u)
     times = []
     for rep in range(args.solve_reps + 1):
         u = fresh()
@@ -330,7 +366,7 @@ def bench_solve(args):
         torch.cuda.synchronize()
         if rep:
             times.append(time.perf_counter() - t)
-    record("fp32_refined_persistent", times, info)
+    record("fp32_refined_persistent", times, info, u)
     fp32_names = ["fp32_refined", "fp32_refined_tb2", "fp32_refined_persistent"]
     best32 = min(fp32_names, key=lambda k: rows[k]["seconds"])
     value_name = best32
@@ -356,7 +392,7 @@ def bench_solve(args):
             if rep:
                 times.append(time.perf_counter() - t)
                 used.append(bool(use))
-        record("cnn_fp32_refined", times, info)
+        record("cnn_fp32_refined", times, info, x)
         rows["cnn_fp32_refined"]["solver"] = best32
         rows["cnn_fp32_refined"]["guess_used"] = used
         value_name = "cnn_fp32_refined"
@@ -377,7 +413,7 @@ def bench_solve(args):
 
 def bench_batched(args):
     """64 instances, per-axis sizes log-uniform in [32, 256] (seed 4), each with
-    8 Gaussian sources (seed 4000 + i) and a zero Dirichlet boundary, solved
+    8 Gaussian sources (seed 1000 + i) and a zero Dirichlet boundary, solved
     from zero to a 1e-8 relative residual by FP32 sweeps inside FP64
     refinement, all in one persistent launch per step. The tile shapes come
     from the batched autotuner, run once before the timed region."""
@@ -389,7 +425,8 @@ def bench_batched(args):
     dims = synth.batch_sizes(64, 4)
     log(f"[bench] generating 64 batched instances ({sum(a * b * c for a, b, c in dims) / 1e6:.1f}"
         " M cells)")
-    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 4000 + i)) for i, d in enumerate(dims)]
+    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 1000 + i))
+             for i, d in enumerate(dims)]
     x0 = [ms.field_from(u) for u, _ in probs]
     xs = [ms.field_from(u) for u, _ in probs]
     fs = [ms.field_from(f) for _, f in probs]
@@ -484,7 +521,7 @@ def bench_batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "batched_poisson_64x_loguniform_32_256_to_1e-8",
                    "instances": 64, "size_seed": 4, "cells": int(cells.sum()),
-                   "rhs": "8 Gaussian sources per instance (seed 4000+i)",
+                   "rhs": "8 Gaussian sources per instance (seed 1000+i)",
                    "boundary": "zero Dirichlet", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -70,7 +70,7 @@ def main():
     if args.what == "batched":
         dims = synth.batch_sizes(64, 4)
         xs = [ms.field_from(synth.zeros(*d)) for d in dims]
-        fs = [ms.field_from(synth.gaussian_sources(*d, 8, 4000 + i)) for i, d in enumerate(dims)]
+        fs = [ms.field_from(synth.gaussian_sources(*d, 8, 1000 + i)) for i, d in enumerate(dims)]
         opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, max_outer=40)
         ms.batched_autotune(xs, fs, sweeps_per_trial=20, **opts)
         print("batched autotune done", flush=True)

@@ -152,7 +152,7 @@ def test_full_batch_of_64_uneven_instances_after_autotuning():
     with single-instance solves."""
     note("case: batched 64 instances, sizes log-uniform [32, 256], seed 4")
     dims = synth.batch_sizes(64, 4)
-    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 4000 + i))
+    probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 1000 + i))
              for i, d in enumerate(dims)]
     xs = [dev(u) for u, _ in probs]
     fs = [dev(f) for _, f in probs]
