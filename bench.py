@@ -118,6 +118,7 @@ def bench_jacobi(args, dtype_name="f64"):
     traffic = traffic_for(key)
     tb_traffic = traffic_for(f"jacobi7tb2_{dtype_name}_{n}")
     ceiling = copy_ceiling()
+    slab = slab_share(n, tdt, f_h)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_jacobi(u_h, f_h, np_dt, args.cpu_sweeps)
@@ -174,8 +175,35 @@ def bench_jacobi(args, dtype_name="f64"):
             "note": "two sweeps per pass over memory: 12 B/LUP (FP64) algorithmic",
         },
         "hbm_copy_ceiling_gbs": ceiling,
+        "per_rank_slab": slab,
     }
     return out
+
+
+def slab_share(n, tdt, f_full, ranks=8, sweeps=200):
+    """One rank's share of the same grid split into `ranks` z-slabs
+    (n x n x n/ranks interior, the same sources cut to the slab), swept alone:
+    the kernel time a multi-GPU sweep would overlap its halo exchange with.
+    A z-slab's halo is one contiguous plane (plane pitch sz), so no pack or
+    unpack kernel is needed; the exchange itself is not part of this build."""
+    import torch
+    import paper_2310_01882_amd as ms
+    import synth
+    nz = n // ranks
+    f_h = f_full[: nz + 2]
+    u = ms.field_from(synth.zeros(n, n, nz), tdt)
+    tmp = ms.field_from(synth.zeros(n, n, nz), tdt)
+    f = ms.field_from(f_h, tdt)
+    work = ms.jacobi_sweeps_workspace(u)
+    stream = torch.cuda.current_stream()
+    secs = event_time(lambda: ms.jacobi_sweeps(u, tmp, sweeps, f=f, work=work, stream=stream),
+                      1, 1, stream)
+    us = secs / sweeps * 1e6
+    plane_bytes = u.stride(0) * u.element_size()
+    return {"interior": [n, n, nz], "us_per_sweep": round(us, 2),
+            "glups": round(n * n * nz / us / 1e3, 2),
+            "halo_plane_bytes": plane_bytes,
+            "halo_plane_us_at_153_gbs_xgmi": round(plane_bytes / 153e3, 2)}
 
 
 def copy_ceiling(mib=1024, reps=10):
