@@ -165,6 +165,124 @@ __global__ __launch_bounds__(256) void conv_dgrad_kernel(DgK a) {
   }
 }
 
+// ------------------------------------------- row-blocked 32-channel kernel
+//
+// Forward (kDgrad = false) and input gradient (kDgrad = true) of a layer
+// with 32 input channels, register-blocked over kRows output rows: a wave
+// owns 32 voxels along x (M) on kRows consecutive rows y0..y0+kRows-1 of
+// one z level, all 32 output channels (N), with one accumulator per row.
+// K is walked in 18 groups (dz, dx, half of the channels); a group loads
+// the kRows+2 input rows that its rows can reach (one 16-byte load per lane
+// each) and the three weight fragments of dy = -1, 0, 1 (from LDS), then
+// issues 3 kRows MFMAs: input row k feeds output row r through
+// dy = sgn*(k - 1 - r), so each load serves up to three MFMAs and each
+// weight fragment all kRows rows. The next group's input rows are loaded
+// while the current group's MFMAs run. Forward reads input voxel
+// v + d for tap d, the input gradient reads output-gradient voxel q - d
+// (sgn = -1). Epilogues as in the one-row kernels above.
+struct RowK {
+  Vol v;
+  const bf16* src;    // forward: layer input; dgrad: gradient of the pre-activation
+  const bf16* w;      // forward: [27][32][32] (tap, co, ci); dgrad: [27][32][32] (tap, ci, co)
+  const float* bias;  // forward only
+  bf16* out;          // forward hidden layers: output, C = 32
+  float* out32;       // forward last layer: channel 0 in FP32
+  const bf16* mask;   // dgrad: the layer input (ReLU mask), C = 32, or null
+  bf16* din;          // dgrad: output, C = 32
+  int relu;
+  int nseg;           // (X/32 rounded up) * (Y/kRows rounded up) * Z
+};
+
+constexpr int kConvRows = 4;
+
+template <bool kDgrad>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_rows_kernel(RowK a) {
+  constexpr int C = 32;
+  constexpr int R = kConvRows;
+  constexpr int sgn = kDgrad ? -1 : 1;
+  __shared__ bf16x8 wl[kTaps * kCo * C / 8];
+  for (int t = threadIdx.x; t < kTaps * kCo * C / 8; t += blockDim.x)
+    wl[t] = reinterpret_cast<const bf16x8*>(a.w)[t];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + 31) / 32, sy = (a.v.Y + R - 1) / R;
+  const float bj = kDgrad ? 0.0f : a.bias[m];
+  for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
+    const int x0 = (seg % sx) * 32, y0 = ((seg / sx) % sy) * R, z = seg / (sx * sy);
+    const bool mok = x0 + m < a.v.X;
+    f32x16 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = f32x16{};
+    // input rows y0 - 1 + k, k = 0 .. R+1, of group g = (dz, dx, channel half)
+    auto load_rows = [&](bf16x8 (&av)[R + 2], int g) {
+      const int dz = g / 6 - 1, dx = (g / 2) % 3 - 1, c0 = (g % 2) * 16 + 8 * h;
+#pragma unroll
+      for (int k = 0; k < R + 2; ++k) {
+        const int yy = y0 - 1 + k;
+        av[k] = zero8();
+        if (mok && yy <= a.v.Y)
+          av[k] = *reinterpret_cast<const bf16x8*>(
+              a.src + a.v.vox(x0 + m + sgn * dx, yy, z + sgn * dz) * C + c0);
+      }
+    };
+    bf16x8 cur[R + 2], nxt[R + 2];
+    load_rows(cur, 0);
+#pragma unroll
+    for (int g = 0; g < 18; ++g) {
+      if (g + 1 < 18) load_rows(nxt, g + 1);
+      const int dz = g / 6 - 1, dx = (g / 2) % 3 - 1, c0 = (g % 2) * 16 + 8 * h;
+      bf16x8 bv[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int t = (dx + 1) + 3 * d + 9 * (dz + 1);  // dy = d - 1
+        bv[d] = wl[((t * kCo + m) * C + c0) / 8];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int k = r + 1 + sgn * (d - 1);  // input row feeding row r at dy = d - 1
+          acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(cur[k], bv[d], acc[r], 0, 0, 0);
+        }
+#pragma unroll
+      for (int k = 0; k < R + 2; ++k) cur[k] = nxt[k];
+    }
+    // keep the epilogue's loads (the ReLU mask) below the MFMA chain
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = y0 + r;
+      if (y >= a.v.Y) break;
+      // dgrad: the row's 16 mask values first, so their loads overlap
+      float mk[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int x = x0 + 8 * (q / 4) + 4 * h + (q % 4);
+        mk[q] = 1.0f;
+        if (kDgrad && a.mask && x < a.v.X) mk[q] = (float)a.mask[a.v.vox(x, y, z) * C + m];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = 8 * (q / 4) + 4 * h + (q % 4);
+        const int x = x0 + i;
+        if (x >= a.v.X) continue;
+        const int64_t p = a.v.vox(x, y, z);
+        if constexpr (kDgrad) {
+          const float gv = mk[q] > 0.0f ? acc[r][q] : 0.0f;
+          a.din[p * C + m] = (bf16)gv;
+        } else {
+          float val = acc[r][q] + bj;
+          if (a.relu) val = fmaxf(val, 0.0f);
+          if (a.out) a.out[p * kCo + m] = (bf16)val;
+          if (a.out32 && m == 0) a.out32[p] = val;
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- wgrad
 
 struct WgK {
@@ -249,14 +367,23 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgK a) {
   if (w == 0 && h == 0) out[kTaps * kCo * CIN + m] = dbacc;
 }
 
-// Sums block partials in block order: dw[27*32*CIN], db[32].
+// Sums block partials: dw[27*32*CIN], db[32]. Eight interleaved running
+// sums (block b goes to sum b % 8) keep eight loads in flight per thread;
+// they are combined in a fixed order, so the result does not depend on the
+// launch.
 __global__ void wgrad_reduce_kernel(const float* part, int nblocks, int n, float* dw, float* db) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n + kCo) return;
-  float s = 0.0f;
-  for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * (n + kCo) + i];
-  if (i < n) dw[i] = s;
-  else db[i - n] = s;
+  const int64_t stride = n + kCo;
+  float s[8] = {};
+  int b = 0;
+  for (; b + 8 <= nblocks; b += 8)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += part[(int64_t)(b + e) * stride + i];
+  for (int e = 0; b < nblocks; ++b, ++e) s[e] += part[(int64_t)b * stride + i];
+  const float t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  if (i < n) dw[i] = t;
+  else db[i - n] = t;
 }
 
 // ------------------------------------------------- loss, Adam, features
@@ -422,6 +549,13 @@ __global__ void target_kernel(ms_grid g, const double* u, Vol v, const double* s
 
 int conv_grid_blocks() { return 1024; }
 
+// 32-channel layers use the row-blocked kernel; MS_CONV_ROWS=0 selects the
+// one-row kernels instead (a cross-check).
+bool row_blocked() {
+  const char* e = getenv("MS_CONV_ROWS");
+  return !(e && atoi(e) == 0);
+}
+
 bool cin_ok(int cin) { return cin == 8 || cin == 32; }
 
 }  // namespace
@@ -440,10 +574,16 @@ extern "C" int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, con
   FwdK a{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
          static_cast<bf16*>(out), out32, relu, ((X + 31) / 32) * Y * Z};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (cin == 8)
+  if (cin == 8) {
     hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
-  else
+  } else if (row_blocked()) {
+    const RowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
+                 static_cast<bf16*>(out), out32, nullptr, nullptr, relu,
+                 ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
+    hipLaunchKernelGGL(conv_rows_kernel<false>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+  } else {
     hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  }
   MS_LAUNCH_CHECK();
   return MS_OK;
 }
@@ -456,10 +596,17 @@ extern "C" int conv3d_bf16_dgrad(int X, int Y, int Z, int cin, const void* dout,
   DgK a{{X, Y, Z}, static_cast<const bf16*>(dout), static_cast<const bf16*>(wd),
         static_cast<const bf16*>(mask), static_cast<bf16*>(din), ((X + 31) / 32) * Y * Z};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (cin == 8)
+  if (cin == 8) {
     hipLaunchKernelGGL(conv_dgrad_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
-  else
+  } else if (row_blocked()) {
+    const RowK r{{X, Y, Z}, static_cast<const bf16*>(dout), static_cast<const bf16*>(wd),
+                 nullptr, nullptr, nullptr, static_cast<const bf16*>(mask),
+                 static_cast<bf16*>(din), 0,
+                 ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
+    hipLaunchKernelGGL(conv_rows_kernel<true>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+  } else {
     hipLaunchKernelGGL(conv_dgrad_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
+  }
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

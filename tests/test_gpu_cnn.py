@@ -51,8 +51,17 @@ def _close(got, want, tol=1e-2):
     assert cos >= 0.999 and rel <= tol, (cos, rel)
 
 
+@pytest.fixture(params=["row-blocked", "one-row"])
+def conv_kernel(request, monkeypatch):
+    """The 32-channel layers have a row-blocked kernel (default) and the
+    one-row kernels (MS_CONV_ROWS=0); both are checked."""
+    if request.param == "one-row":
+        monkeypatch.setenv("MS_CONV_ROWS", "0")
+    return request.param
+
+
 @pytest.mark.parametrize("cin,cinp,relu", [(2, 8, True), (32, 32, True), (32, 32, False)])
-def test_forward_conv_matches_oracle(cin, cinp, relu):
+def test_forward_conv_matches_oracle(cin, cinp, relu, conv_kernel):
     x = cnn.round_bf16(synth.rng(1).standard_normal((cin, Z, Y, X)))
     w, wf, wd = _weights(cin, cinp, 32, 2)
     b = (0.1 * synth.rng(3).standard_normal(32)).astype(np.float32)
@@ -80,7 +89,7 @@ def test_forward_conv_matches_oracle(cin, cinp, relu):
 
 
 @pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
-def test_dgrad_and_wgrad_match_oracle(cin, cinp):
+def test_dgrad_and_wgrad_match_oracle(cin, cinp, conv_kernel):
     r = synth.rng(4)
     x = cnn.round_bf16(np.maximum(r.standard_normal((cin, Z, Y, X)), 0.0))  # a ReLU output
     g = cnn.round_bf16(r.standard_normal((32, Z, Y, X)))
@@ -184,3 +193,32 @@ def test_training_reduces_the_loss_on_one_instance():
     tgt = net.target(x)
     losses = [net.train_step(du, df, tgt, lr=3e-3).item() for _ in range(60)]
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_row_blocked_conv_on_ragged_extents():
+    """x not a multiple of 32 and y not a multiple of the 4-row block, both
+    directions, against the oracle."""
+    nx, ny, nz = 70, 9, 3
+    r = synth.rng(11)
+    x = cnn.round_bf16(np.maximum(r.standard_normal((32, nz, ny, nx)), 0.0))
+    g = cnn.round_bf16(r.standard_normal((32, nz, ny, nx)))
+    w, wf, wd = _weights(32, 32, 32, 12)
+    wo = cnn.round_bf16(wsm.to_oracle_weights(w, 32, 32))
+    b = torch.zeros(32, dtype=torch.float32, device="cuda")
+    xin, gin = _bf16_act(x, 32), _bf16_act(g, 32)
+    out = torch.zeros_like(xin)
+    din = torch.zeros_like(xin)
+    assert ms.lib.conv3d_bf16_fwd(nx, ny, nz, 32, ms._ptr(xin), ms._ptr(wf), ms._ptr(b),
+                                  ms._ptr(out), None, 0, None) == 0
+    assert ms.lib.conv3d_bf16_dgrad(nx, ny, nz, 32, ms._ptr(gin), ms._ptr(wd), ms._ptr(xin),
+                                    ms._ptr(din), None) == 0
+    torch.cuda.synchronize()
+    shape = (nx, ny, nz)
+    ref = cnn.conv3d(x, wo, np.zeros(32))
+    mag = cnn.conv3d(np.abs(x), np.abs(wo), np.zeros(32))
+    got = _act_np(out, 32, 32, shape)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 2e-5 * mag)
+    _close(_act_np(din, 32, 32, shape), cnn.conv3d_dgrad(g, wo) * (x > 0))
+    # halos stay zero
+    o = out.float().view(nz + 2, ny + 2, nx + 2, 32)
+    assert torch.all(o[:, -1] == 0) and torch.all(o[:, :, -1] == 0) and torch.all(o[-1] == 0)
