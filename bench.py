@@ -118,7 +118,6 @@ def bench_jacobi(args, dtype_name="f64"):
     traffic = traffic_for(key)
     tb_traffic = traffic_for(f"jacobi7tb2_{dtype_name}_{n}")
     ceiling = copy_ceiling()
-    slab = slab_share(n, tdt, f_h)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_jacobi(u_h, f_h, np_dt, args.cpu_sweeps)
@@ -175,9 +174,25 @@ def bench_jacobi(args, dtype_name="f64"):
             "note": "two sweeps per pass over memory: 12 B/LUP (FP64) algorithmic",
         },
         "hbm_copy_ceiling_gbs": ceiling,
-        "per_rank_slab": slab,
     }
     return out
+
+
+def bench_slab(args):
+    """One rank's z-slab share of the 512^3 FP64 sweep (design only: the
+    multi-GPU exchange is not built). Its own mode, so that the headline
+    run's kernel statistics cover the 512^3 sweep alone."""
+    import torch
+    import synth
+    n = args.n
+    f_h = synth.gaussian_sources(n, n, n, 8, 1)
+    out = slab_share(n, torch.float64, f_h)
+    return {"metric": "GLUP/s (one rank's 512x512x64 z-slab of the 512^3 FP64 sweep)",
+            "value": out["glups"], "unit": "GLUP/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": round(out["us_per_sweep"] * 200 / 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "jacobi7_f64_512x512x64_slab", "parallelism": "single GPU"},
+            "slab": out}
 
 
 def slab_share(n, tdt, f_full, ranks=8, sweeps=200):
@@ -651,7 +666,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", choices=["jacobi", "f32", "advect", "solve", "batched",
-                                       "refined512"], default="jacobi")
+                                       "refined512", "slab"], default="jacobi")
     ap.add_argument("--tb", type=int, default=1, choices=[1, 2],
                     help="refined512 mode: sweeps per pass")
     ap.add_argument("--n", type=int, default=512)
@@ -682,6 +697,8 @@ def main():
         out = bench_batched(args)
     elif args.mode == "refined512":
         out = bench_refined512(args)
+    elif args.mode == "slab":
+        out = bench_slab(args)
     else:
         out = bench_solve(args)
     out["device"] = torch.cuda.get_device_name(0)
