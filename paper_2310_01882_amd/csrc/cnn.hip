@@ -251,18 +251,33 @@ void conv_rows_kernel(RowK a) {
     }
     // keep the epilogue's loads (the ReLU mask) below the MFMA chain
     __builtin_amdgcn_sched_barrier(0);
+    // dgrad: all R x 16 mask values of the task first (the operand buffers
+    // are dead by now), so that their loads share one round trip
+    // Loads are unconditional (coordinates past the interior are clamped to
+    // the halo, whose outputs are not stored): a conditional load would
+    // have to complete before its branch joins, one round trip per value.
+    bf16 mk[kDgrad ? R : 1][16];
+    if constexpr (kDgrad) {
+      if (a.mask) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int x = min(x0 + 8 * (q / 4) + 4 * h + (q % 4), a.v.X);
+            const int y = min(y0 + r, a.v.Y);
+            mk[r][q] = a.mask[a.v.vox(x, y, z) * C + m];
+          }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) mk[r][q] = (bf16)1.0f;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int y = y0 + r;
       if (y >= a.v.Y) break;
-      // dgrad: the row's 16 mask values first, so their loads overlap
-      float mk[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int x = x0 + 8 * (q / 4) + 4 * h + (q % 4);
-        mk[q] = 1.0f;
-        if (kDgrad && a.mask && x < a.v.X) mk[q] = (float)a.mask[a.v.vox(x, y, z) * C + m];
-      }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = 8 * (q / 4) + 4 * h + (q % 4);
@@ -270,7 +285,7 @@ void conv_rows_kernel(RowK a) {
         if (x >= a.v.X) continue;
         const int64_t p = a.v.vox(x, y, z);
         if constexpr (kDgrad) {
-          const float gv = mk[q] > 0.0f ? acc[r][q] : 0.0f;
+          const float gv = (float)mk[r][q] > 0.0f ? acc[r][q] : 0.0f;
           a.din[p * C + m] = (bf16)gv;
         } else {
           float val = acc[r][q] + bj;
@@ -304,30 +319,63 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgK a) {
 #pragma unroll
   for (int q = 0; q < 7; ++q) acc[q] = f32x16{};
   float dbacc = 0.0f;
-  for (int seg = blockIdx.x; seg < a.nseg16; seg += gridDim.x) {
+  // Operands of one segment, 16-byte chunks spread over the block: dPre
+  // (16 voxels x 32 channels, 64 chunks) and the input rows of the 9 (dy, dz)
+  // offsets (18 voxels from x0 - 1, CIN channels). The next segment's chunks
+  // are loaded into registers while the current segment computes.
+  constexpr int ND = 16 * kCo / 8, NI = 9 * 18 * CIN / 8;
+  constexpr int QD = (ND + 255) / 256, QI = (NI + 255) / 256;
+  bf16x8 pd[QD], pi[QI];
+  auto load_seg = [&](int seg) {
     const int x0 = (seg % sx) * 16, y = (seg / sx) % a.v.Y, z = seg / (sx * a.v.Y);
-    __syncthreads();  // previous segment's reads are done
-    // dPre: 16 voxels x 32 channels (voxels past X read as 0)
-    for (int e = threadIdx.x; e < 16 * kCo / 8; e += blockDim.x) {
-      const int vx = e / (kCo / 8), c8 = (e % (kCo / 8)) * 8;
-      bf16x8 val = zero8();
-      if (x0 + vx < a.v.X)
-        val = *reinterpret_cast<const bf16x8*>(a.dpre + a.v.vox(x0 + vx, y, z) * kCo + c8);
-      *reinterpret_cast<bf16x8*>(&dp[vx][c8]) = val;
+#pragma unroll
+    for (int q = 0; q < QD; ++q) {
+      const int e = threadIdx.x + q * 256;
+      pd[q] = zero8();
+      if (e < ND && seg < a.nseg16) {
+        const int vx = e / (kCo / 8), c8 = (e % (kCo / 8)) * 8;
+        if (x0 + vx < a.v.X)  // voxels past X read as 0
+          pd[q] = *reinterpret_cast<const bf16x8*>(a.dpre + a.v.vox(x0 + vx, y, z) * kCo + c8);
+      }
     }
-    // input rows for the 9 (dy, dz) offsets, x from x0-1 to x0+16
-    for (int e = threadIdx.x; e < 9 * 18 * CIN / 8; e += blockDim.x) {
-      const int c8 = (e % (CIN / 8)) * 8;
-      const int vx = (e / (CIN / 8)) % 18;
-      const int row = e / (CIN / 8) / 18;
-      const int dy = row % 3 - 1, dz = row / 3 - 1;
-      const int x = x0 - 1 + vx;
-      bf16x8 val = zero8();
-      if (x <= a.v.X)  // the halo voxel x = X exists (zero)
-        val = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x, y + dy, z + dz) * CIN + c8);
-      *reinterpret_cast<bf16x8*>(&inr[row][vx][c8]) = val;
+#pragma unroll
+    for (int q = 0; q < QI; ++q) {
+      const int e = threadIdx.x + q * 256;
+      pi[q] = zero8();
+      if (e < NI && seg < a.nseg16) {
+        const int c8 = (e % (CIN / 8)) * 8;
+        const int vx = (e / (CIN / 8)) % 18;
+        const int row = e / (CIN / 8) / 18;
+        const int dy = row % 3 - 1, dz = row / 3 - 1;
+        const int x = x0 - 1 + vx;
+        if (x <= a.v.X)  // the halo voxel x = X exists (zero)
+          pi[q] = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x, y + dy, z + dz) * CIN + c8);
+      }
     }
+  };
+  auto store_seg = [&]() {
+#pragma unroll
+    for (int q = 0; q < QD; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < ND) *reinterpret_cast<bf16x8*>(&dp[e / (kCo / 8)][(e % (kCo / 8)) * 8]) = pd[q];
+    }
+#pragma unroll
+    for (int q = 0; q < QI; ++q) {
+      const int e = threadIdx.x + q * 256;
+      if (e < NI) {
+        const int c8 = (e % (CIN / 8)) * 8;
+        const int vx = (e / (CIN / 8)) % 18;
+        const int row = e / (CIN / 8) / 18;
+        *reinterpret_cast<bf16x8*>(&inr[row][vx][c8]) = pi[q];
+      }
+    }
+  };
+  load_seg(blockIdx.x);
+  for (int seg = blockIdx.x; seg < a.nseg16; seg += gridDim.x) {
+    __syncthreads();  // the previous segment's LDS reads are done
+    store_seg();
     __syncthreads();
+    load_seg(seg + gridDim.x);  // in flight while this segment computes
     bf16x8 av;
 #pragma unroll
     for (int e = 0; e < 8; ++e) av[e] = dp[8 * h + e][m];  // A[co = m][voxel]
