@@ -81,21 +81,19 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(FwdK a) {
   const float bj = a.bias[m];
   for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
     const int x0 = (seg % sx) * 32, y = (seg / sx) % a.v.Y, z = seg / (sx * a.v.Y);
-    const bool mok = x0 + m < a.v.X;
     f32x16 acc = {};
 #pragma unroll 2
     for (int s = 0; s < KS; ++s) {
       const int k0 = s * 16 + 8 * h;
       const int t = k0 / CIN, c0 = k0 % CIN;
-      bf16x8 av = zero8(), bv = zero8();
-      if (t < kTaps) {
-        int dx, dy, dz;
-        tap_offset(t, dx, dy, dz);
-        if (mok)
-          av = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x0 + m + dx, y + dy, z + dz) * CIN +
-                                                c0);
-        bv = wl[((t * kCo + m) * CIN + c0) / 8];
-      }
+      // Unconditional load from a clamped tap and x (a lane past the interior
+      // feeds only outputs that are not stored; a tap past the last gets a
+      // zero weight), so that the loads pipeline.
+      int dx, dy, dz;
+      tap_offset(t < kTaps ? t : kTaps - 1, dx, dy, dz);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(
+          a.in + a.v.vox(min(x0 + m + dx, a.v.X), y + dy, z + dz) * CIN + c0);
+      const bf16x8 bv = t < kTaps ? wl[((t * kCo + m) * CIN + c0) / 8] : zero8();
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
@@ -211,20 +209,21 @@ void conv_rows_kernel(RowK a) {
   const float bj = kDgrad ? 0.0f : a.bias[m];
   for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
     const int x0 = (seg % sx) * 32, y0 = ((seg / sx) % sy) * R, z = seg / (sx * sy);
-    const bool mok = x0 + m < a.v.X;
     f32x16 acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = f32x16{};
-    // input rows y0 - 1 + k, k = 0 .. R+1, of group g = (dz, dx, channel half)
+    // input rows y0 - 1 + k, k = 0 .. R+1, of group g = (dz, dx, channel half).
+    // The loads are unconditional, from coordinates clamped into the volume
+    // (halo included): a clamped lane (x past the interior) or row (y past
+    // the halo) feeds only outputs that are not stored, and a conditional
+    // load would have to complete before its branch joins.
     auto load_rows = [&](bf16x8 (&av)[R + 2], int g) {
       const int dz = g / 6 - 1, dx = (g / 2) % 3 - 1, c0 = (g % 2) * 16 + 8 * h;
+      const int x = min(x0 + m + sgn * dx, a.v.X);
 #pragma unroll
       for (int k = 0; k < R + 2; ++k) {
-        const int yy = y0 - 1 + k;
-        av[k] = zero8();
-        if (mok && yy <= a.v.Y)
-          av[k] = *reinterpret_cast<const bf16x8*>(
-              a.src + a.v.vox(x0 + m + sgn * dx, yy, z + sgn * dz) * C + c0);
+        const int yy = min(y0 - 1 + k, a.v.Y);
+        av[k] = *reinterpret_cast<const bf16x8*>(a.src + a.v.vox(x, yy, z + sgn * dz) * C + c0);
       }
     };
     bf16x8 cur[R + 2], nxt[R + 2];

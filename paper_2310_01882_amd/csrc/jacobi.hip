@@ -525,9 +525,6 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   auto off = [&](int i, int j, int k) {
     return (int64_t)(k + 1) * sz + (int64_t)(j + 1) * sy + (i + 1);
   };
-  auto exists = [&](int i, int j, int k) {
-    return i >= -1 && i <= nx && j >= -1 && j <= ny && k >= -1 && k <= nz;
-  };
   auto abuf = [&](int k) { return (k - z0 + 8) & 3; };
 
   // u_k region cells owned by this thread (LDS staging): c = t + 256 q.
@@ -538,13 +535,20 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     ca = c % kTbAX;
     return c < kTbACells;
   };
+  // Loads are unconditional, from coordinates clamped into the field (halo
+  // included): cells outside the field feed no output and no residual, and
+  // a conditional load would have to complete before its branch joins,
+  // which serialises the loads.
+  auto clampx = [&](int i) { return min(max(i, -1), nx); };
+  auto clampy = [&](int j) { return min(max(j, -1), ny); };
+  auto clampz = [&](int k) { return min(max(k, -1), nz); };
   auto load_a = [&](T (&r)[QA], int k) {
+    const int kc = clampz(k);
 #pragma unroll
     for (int q = 0; q < QA; ++q) {
       int ra, ca;
-      const bool own = a_cell(q, ra, ca);
-      const int i = i0 - 2 + ca, j = j0 - 2 + ra;
-      r[q] = (own && exists(i, j, k)) ? src[off(i, j, k)] : T(0);
+      (void)a_cell(q, ra, ca);
+      r[q] = src[off(clampx(i0 - 2 + ca), clampy(j0 - 2 + ra), kc)];
     }
   };
   auto store_a = [&](const T (&r)[QA], int k) {
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   constexpr int QO = kTbOut / kThreads;
   // Loop-invariant cell bookkeeping. Stage A: cells of the 66 x 10 region.
   int arb[QB], acb[QB];
-  int64_t aoff[QB];
+  int64_t aoff[QB];  // clamped into the field (for the f loads)
   bool aown[QB], ain[QB], atile[QB];
 #pragma unroll
   for (int q = 0; q < QB; ++q) {
@@ -591,7 +595,7 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     const int i = i0 - 1 + acb[q], j = j0 - 1 + arb[q];
     ain[q] = aown[q] && i >= 0 && i < nx && j >= 0 && j < ny;
     atile[q] = arb[q] >= 1 && arb[q] <= kTbY && acb[q] >= 1 && acb[q] <= kTbX;
-    aoff[q] = (int64_t)(j + 1) * sy + (i + 1);
+    aoff[q] = (int64_t)(clampy(j) + 1) * sy + (clampx(i) + 1);
   }
   // Stage B: cells of the 64 x 8 tile.
   int brt[QO], bct[QO];
@@ -604,20 +608,21 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     bct[q] = c % kTbX;
     const int i = i0 + bct[q], j = j0 + brt[q];
     bin[q] = i < nx && j < ny;
-    boff[q] = (int64_t)(j + 1) * sy + (i + 1);
+    boff[q] = (int64_t)(clampy(j) + 1) * sy + (clampx(i) + 1);  // clamped
   }
   auto zin = [&](int z) { return z >= 0 && z < nz; };
   // f for stage A at level z and for stage B at level z-1, prefetched one
   // step ahead.
+  // (unconditional and clamped as above; only interior cells use them)
   auto ld_fa = [&](T (&d)[QB], int z) {
+    const int64_t pz = (int64_t)(clampz(z) + 1) * sz;
 #pragma unroll
-    for (int q = 0; q < QB; ++q)
-      d[q] = (HAS_F && ain[q] && zin(z)) ? f[(int64_t)(z + 1) * sz + aoff[q]] : T(0);
+    for (int q = 0; q < QB; ++q) d[q] = HAS_F ? f[pz + aoff[q]] : T(0);
   };
   auto ld_fb = [&](T (&d)[QO], int z) {
+    const int64_t pz = (int64_t)(clampz(z) + 1) * sz;
 #pragma unroll
-    for (int q = 0; q < QO; ++q)
-      d[q] = (HAS_F && bin[q] && z >= z0 && z < z1) ? f[(int64_t)(z + 1) * sz + boff[q]] : T(0);
+    for (int q = 0; q < QO; ++q) d[q] = HAS_F ? f[pz + boff[q]] : T(0);
   };
   T fa[QB], fb[QO];
   ld_fa(fa, z0 - 1);
@@ -810,10 +815,10 @@ SweepGeom tb2_geom(const ms_grid& g, int dtype) {
   s.tiles_y = (g.ny + kTbY - 1) / kTbY;
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
   // Block targets measured at 512^3 (three FP64 / four FP32 blocks are
-  // resident per CU): 1536 for FP64, 1024 for FP32; marches of at least 8
+  // resident per CU): 2048 for FP64, 1024 for FP32; marches of at least 8
   // levels. MS_TB_BLOCKS overrides the target for tuning.
   const char* ev = getenv("MS_TB_BLOCKS");
-  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : (dtype == MS_F64 ? 1536 : 1024);
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : (dtype == MS_F64 ? 2048 : 1024);
   int64_t chunks = (want + tiles2d - 1) / tiles2d;
   int zc = (int)((g.nz + chunks - 1) / chunks);
   if (zc < 8) zc = 8;
