@@ -202,16 +202,18 @@ __device__ double sweep_tiles(const Inst& q, int rank, const T* __restrict__ src
     T zm = src[p - sz], zc = src[p];
     for (int k = k0; k < k1; k += kUnroll, p += kUnroll * sz) {
       T xp[kUnroll], xm[kUnroll], yp[kUnroll], ym[kUnroll], zp[kUnroll], fv[kUnroll];
+      // Unconditional loads (levels past the chunk re-read its last level;
+      // their values are not used): a conditional load would have to
+      // complete before its branch joins, which serialises the loads.
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int64_t r = p + u * sz;
-        const bool in = k + u < k1;
-        xp[u] = in ? src[r + 1] : T(0);
-        xm[u] = in ? src[r - 1] : T(0);
-        yp[u] = in ? src[r + sy] : T(0);
-        ym[u] = in ? src[r - sy] : T(0);
-        zp[u] = in ? src[r + sz] : T(0);
-        fv[u] = (in && f) ? f[r] : T(0);
+        const int64_t r = p + (int64_t)min(u, k1 - 1 - k) * sz;
+        xp[u] = src[r + 1];
+        xm[u] = src[r - 1];
+        yp[u] = src[r + sy];
+        ym[u] = src[r - sy];
+        zp[u] = src[r + sz];
+        fv[u] = f ? f[r] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
