@@ -331,8 +331,8 @@ def bench_solve(args):
     """Time to a 1e-8 relative residual at 128^3 (8 Gaussian sources, seed 1,
     zero Dirichlet boundary, zero start) on aligned fields, median of
     --solve-reps timed solves after one warm-up each:
-      fp64                     plain FP64 Jacobi (one sweep per launch)
-      fp64_tb2                 the same with two sweeps per pass
+      fp64                     plain FP64 Jacobi, one sweep per pass
+      fp64_tb2                 the same with two sweeps per pass (the library default)
       fp32_refined(_tb2)       FP32 sweeps inside FP64 refinement
       fp32_refined_persistent  the same through the persistent batched kernel
       cnn_fp32_refined         the trained warm start's guess (zero interior
@@ -341,7 +341,8 @@ def bench_solve(args):
                                features and forward pass are inside the
                                timed region (needs the committed weights)
     `value` is cnn_fp32_refined when the weights are present, else the
-    fastest FP32-refined variant; `fp64` is the plain baseline."""
+    fastest FP32-refined variant; `speedup_vs_fp64` compares it with the
+    faster plain FP64 schedule."""
     import statistics
     import torch
     import paper_2310_01882_amd as ms
@@ -373,9 +374,9 @@ def bench_solve(args):
     def field_error(x):
         return torch.linalg.vector_norm(x - x_ref).item() / ref_norm
 
-    variants = [("fp64", dict(precision=F64)),
+    variants = [("fp64", dict(precision=F64, temporal_block=1)),
                 ("fp64_tb2", dict(precision=F64, temporal_block=2)),
-                ("fp32_refined", dict(precision=F32R)),
+                ("fp32_refined", dict(precision=F32R, temporal_block=1)),
                 ("fp32_refined_tb2", dict(precision=F32R, temporal_block=2))]
     rows = {}
 
@@ -449,7 +450,8 @@ def bench_solve(args):
                    "boundary": "zero Dirichlet", "value_is": value_name,
                    "parallelism": "single GPU"},
         "sweep_shapes": tuned,
-        "speedup_vs_fp64": round(rows["fp64"]["seconds"] / v, 3),
+        "speedup_vs_fp64": round(min(rows["fp64"]["seconds"],
+                                     rows["fp64_tb2"]["seconds"]) / v, 3),
         "solves": rows,
     }
 

@@ -157,7 +157,7 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
  *   inner sweeps.
  * check_every: sweeps per device-side chunk between host checks (0 = auto).
  * temporal_block: sweeps fused per pass over memory: 0 or 1 = one,
- *   2 = two (as jacobi_sweeps_tb; same iterates, same K).
+ *   2 = two (as jacobi_sweeps_tb; same iterates, same K; the default).
  * use_graph: 1 = replay chunks as hipGraphs (default), 0 = plain launches.
  *
  * u: device, in: initial guess + Dirichlet halo; out: the answer u_K.
@@ -196,7 +196,8 @@ typedef struct {
                           of the launch to this instance's team finish */
 } ms_solve_result;
 
-/* Fill `o` with the library defaults (rel_tol 1e-8, F64, auto chunks). */
+/* Fill `o` with the library defaults (rel_tol 1e-8, F64, auto chunks, two
+ * sweeps per pass, graphs on, inner_eta 1e-5, max_outer 20, stall 256). */
 void ms_solve_opts_default(ms_solve_opts* o);
 size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* o);
 int jacobi_solve(const ms_grid* g, const ms_solve_opts* o, double* u,

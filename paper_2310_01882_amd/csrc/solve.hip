@@ -396,7 +396,7 @@ extern "C" void ms_solve_opts_default(ms_solve_opts* o) {
   o->max_outer = 20;
   o->max_inner = 5000000;
   o->stall_window = 256;
-  o->temporal_block = 0;
+  o->temporal_block = 2;
   o->use_graph = 1;
   o->reserved = 0;
 }
