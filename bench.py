@@ -106,6 +106,10 @@ def bench_jacobi(args, dtype_name="f64"):
                                                   stream=stream, temporal_block=2),
                          args.steps, args.warmup, stream)
     tb_glups = n ** 3 * sweeps * args.steps / tb_secs / 1e9
+    # red-black Gauss-Seidel sweeps on the same inputs (one sweep per pass)
+    gs_secs = event_time(lambda: ms.rbgs_sweeps(u, tmp, sweeps, f=f, res=res, work=work,
+                                                stream=stream),
+                         args.steps, args.warmup, stream)
     cells = n ** 3
     lups = cells * sweeps * args.steps
     glups = lups / secs / 1e9
@@ -117,6 +121,8 @@ def bench_jacobi(args, dtype_name="f64"):
     key = f"jacobi7_{dtype_name}_{n}"
     traffic = traffic_for(key)
     tb_traffic = traffic_for(f"jacobi7tb2_{dtype_name}_{n}")
+    gs_traffic = traffic_for(f"jacobi7rbgs_{dtype_name}_{n}")
+    gs_launch = gs_secs / (sweeps * args.steps)
     ceiling = copy_ceiling()
     cpu = None
     if not args.no_cpu_baseline:
@@ -172,6 +178,19 @@ def bench_jacobi(args, dtype_name="f64"):
             "gb_per_s_measured": (round(tb_traffic * (sweeps // 2) * args.steps / tb_secs / 1e9, 1)
                                   if tb_traffic else None),
             "note": "two sweeps per pass over memory: 12 B/LUP (FP64) algorithmic",
+        },
+        "red_black_gauss_seidel": {
+            "kernel": "sweep_tb2_kernel<%s, true, true>" % ("double" if dtype_name == "f64"
+                                                           else "float"),
+            "glups": round(cells * sweeps * args.steps / gs_secs / 1e9, 3),
+            "ms_per_step": round(gs_secs / args.steps * 1e3, 4),
+            "avg_launch_us": round(gs_launch * 1e6, 3),
+            "gb_per_s_algorithmic": round(bpl * cells / gs_launch / 1e9, 1),
+            "traffic_per_sweep": gs_traffic,
+            "gb_per_s_measured": round(gs_traffic / gs_launch / 1e9, 1) if gs_traffic else None,
+            "note": ("one red-black Gauss-Seidel sweep per pass over memory, "
+                     f"{bpl} B/LUP algorithmic; asymptotically one such sweep reduces the "
+                     "error as much as two Jacobi sweeps (rate rho_J^2)"),
         },
         "hbm_copy_ceiling_gbs": ceiling,
     }
@@ -335,6 +354,10 @@ def bench_solve(args):
       fp64_tb2                 the same with two sweeps per pass (the library default)
       fp32_refined(_tb2)       FP32 sweeps inside FP64 refinement
       fp32_refined_persistent  the same through the persistent batched kernel
+      fp64_rbgs, fp32_refined_rbgs
+                               red-black Gauss-Seidel sweeps instead of Jacobi
+                               (plain FP64, and inside the refinement); reported
+                               beside the Jacobi variants, not used for `value`
       cnn_fp32_refined         the trained warm start's guess (zero interior
                                if its residual is not smaller), then the
                                fastest FP32-refined variant; the guess's
@@ -374,10 +397,13 @@ def bench_solve(args):
     def field_error(x):
         return torch.linalg.vector_norm(x - x_ref).item() / ref_norm
 
+    RB = ms.MS_METHOD_RBGS
     variants = [("fp64", dict(precision=F64, temporal_block=1)),
                 ("fp64_tb2", dict(precision=F64, temporal_block=2)),
                 ("fp32_refined", dict(precision=F32R, temporal_block=1)),
-                ("fp32_refined_tb2", dict(precision=F32R, temporal_block=2))]
+                ("fp32_refined_tb2", dict(precision=F32R, temporal_block=2)),
+                ("fp64_rbgs", dict(precision=F64, method=RB)),
+                ("fp32_refined_rbgs", dict(precision=F32R, method=RB))]
     rows = {}
 
     def record(name, times, info, x):

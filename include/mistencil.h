@@ -140,8 +140,25 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
                      double* res_dev, void* work, size_t work_bytes,
                      void* stream);
 
+/* ---- fixed number of red-black Gauss-Seidel sweeps ----------------------
+ * The Section 4.1 benchmark is a Gauss-Seidel iteration of the same 7-point
+ * stencil; its in-place, lexicographic form is sequential, so this is the
+ * red-black ordering, which keeps every half-sweep data parallel. Cells with
+ * i + j + k even (interior coordinates, 0-based) are red. One sweep: every
+ * red cell takes (S - f) * fl(1/6) of the current field, then every black
+ * cell takes the same expression of the field with the red cells updated;
+ * the six neighbours of a cell always have the other colour. Arguments, the
+ * ping-pong buffers, res_dev (||r(u_k)||, k = 0..n, u_k the field after k
+ * sweeps), dtype, workspace (jacobi_sweeps_workspace_bytes) and errors are
+ * those of jacobi_sweeps; u_n lands in u if n is even, else in u_tmp. Each
+ * sweep is one pass over memory. Async. */
+int rbgs_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                const void* f, int64_t n, double* res_dev, void* work,
+                size_t work_bytes, void* stream);
+
 /* ---- convergence-controlled solve ----------------------------------------
- * Relative-residual Jacobi solve of L(u) = f with Dirichlet halo.
+ * Relative-residual Jacobi (or red-black Gauss-Seidel, method) solve of
+ * L(u) = f with Dirichlet halo.
  * res0 = ||r(u^0)||, u^0 = u with its interior zeroed (same halo, same f);
  * the answer is u_K with K the smallest k >= 0 such that
  * ||r(u_k)|| / res0 <= rel_tol (K = 0 if res0 = 0).
@@ -159,6 +176,9 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
  * temporal_block: sweeps fused per pass over memory: 0 or 1 = one,
  *   2 = two (as jacobi_sweeps_tb; same iterates, same K; the default).
  * use_graph: 1 = replay chunks as hipGraphs (default), 0 = plain launches.
+ * method: MS_METHOD_JACOBI (default) or MS_METHOD_RBGS, red-black
+ *   Gauss-Seidel sweeps as rbgs_sweeps (for the FP32 inner iteration too;
+ *   temporal_block is then ignored). K counts Gauss-Seidel sweeps.
  *
  * u: device, in: initial guess + Dirichlet halo; out: the answer u_K.
  * f: device, may be NULL. hist_host: host, may be NULL; receives
@@ -169,6 +189,8 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
  * or an error. */
 #define MS_SOLVE_F64 0
 #define MS_SOLVE_F32_REFINED 1
+#define MS_METHOD_JACOBI 0
+#define MS_METHOD_RBGS 1
 
 typedef struct {
   double rel_tol;
@@ -181,7 +203,7 @@ typedef struct {
   int32_t stall_window;
   int32_t temporal_block;
   int32_t use_graph;
-  int32_t reserved;
+  int32_t method;
 } ms_solve_opts;
 
 typedef struct {
@@ -249,7 +271,8 @@ void ms_tuning_clear(void);
  * MS_SOLVE_F32_REFINED with the refinement rules of jacobi_solve (same
  * per-cell arithmetic, same stopping rules; norms are summed per team, so an
  * iteration count may differ from jacobi_solve's by one only when a norm
- * sits within rounding of its threshold). Options used: rel_tol,
+ * sits within rounding of its threshold). method must be MS_METHOD_JACOBI
+ * (else MS_EUNSUPPORTED). Options used: rel_tol,
  * max_sweeps, precision, inner_eta, max_outer, max_inner, stall_window
  * (<= 1024). Instances must not overlap; n <= resident blocks of the device.
  * res: host array of n results. Blocks until done. Returns MS_OK,

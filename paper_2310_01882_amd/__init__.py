@@ -33,6 +33,8 @@ MS_F64 = 0
 MS_F32 = 1
 MS_SOLVE_F64 = 0
 MS_SOLVE_F32_REFINED = 1
+MS_METHOD_JACOBI = 0
+MS_METHOD_RBGS = 1
 
 
 class MsError(RuntimeError):
@@ -63,7 +65,7 @@ class SolveOpts(ctypes.Structure):
                 ("inner_eta", ctypes.c_double), ("max_outer", ctypes.c_int32),
                 ("max_inner", ctypes.c_int32), ("stall_window", ctypes.c_int32),
                 ("temporal_block", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("method", ctypes.c_int32)]
 
 
 class SolveResult(ctypes.Structure):
@@ -107,6 +109,7 @@ SIGNATURES = {
     "jacobi_sweeps_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
     "jacobi_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "jacobi_sweeps_tb": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _P, _P, _SZ, _P]),
+    "rbgs_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "ms_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "jacobi_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts)]),
     "jacobi_solve": (_I, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts), _P, _P, _P, _SZ,
@@ -323,6 +326,27 @@ def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None, tempora
     return u if passes % 2 == 0 else u_tmp
 
 
+def rbgs_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):
+    """Exactly ``n`` red-black Gauss-Seidel sweeps with ping-pong buffers;
+    returns the buffer holding u_n (``u`` if n is even, else ``u_tmp``).
+    ``res`` (float64 device tensor of n + 1 entries, optional) receives
+    ||r(u_k)||, k = 0..n."""
+    _field_check(u, "u")
+    _field_check(u_tmp, "u_tmp", u.dtype)
+    _same_layout(u, u_tmp, "u/u_tmp")
+    if f is not None:
+        _field_check(f, "f", u.dtype)
+        _same_layout(u, f, "u/f")
+    if res is not None and (res.dtype != torch.float64 or res.numel() < n + 1):
+        raise ValueError("res must be float64 with n + 1 entries")
+    g = grid_of(u)
+    if work is None:
+        work = jacobi_sweeps_workspace(u)
+    _check(lib.rbgs_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f), int(n),
+                           _ptr(res), _ptr(work), work.numel(), _stream(stream)))
+    return u if n % 2 == 0 else u_tmp
+
+
 @dataclass
 class SolveInfo:
     status: int
@@ -358,7 +382,7 @@ def jacobi_solve(u, f=None, work=None, want_hist=False, stream=None, **opts) -> 
     initial guess and Dirichlet halo on entry and the answer on return.
     Keyword options map onto ms_solve_opts (rel_tol, max_sweeps, precision,
     check_every, inner_eta, max_outer, max_inner, stall_window,
-    temporal_block, use_graph)."""
+    temporal_block, use_graph, method)."""
     _field_check(u, "u", torch.float64)
     if f is not None:
         _field_check(f, "f", torch.float64)

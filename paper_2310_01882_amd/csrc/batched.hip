@@ -628,6 +628,9 @@ int check_batch(int n, const ms_instance* inst, const ms_solve_opts* o) {
   if (!o) return set_error(MS_EINVAL, "jacobi_solve_batched: opts is NULL");
   if (o->precision != MS_SOLVE_F64 && o->precision != MS_SOLVE_F32_REFINED)
     return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: precision %d", o->precision);
+  if (o->method != MS_METHOD_JACOBI)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: Jacobi sweeps only (method %d)",
+                     o->method);
   if (!(o->rel_tol >= 0.0) || !std::isfinite(o->rel_tol))
     return set_error(MS_EINVAL, "jacobi_solve_batched: rel_tol must be finite and >= 0");
   if (o->stall_window < 0 || o->stall_window > kStallMax)

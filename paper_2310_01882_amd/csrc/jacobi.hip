@@ -474,6 +474,15 @@ __global__ void finalize_kernel(const double* partials, int nb, double* out, Ctl
 // Dirichlet halo keep their value, as a plain sweep never writes the halo.
 // Four LDS buffers per stage leave one barrier per level. Stage A adds the
 // residual of u_k on the tile, stage B the residual of u_{k+1}.
+//
+// RB: one red-black Gauss-Seidel sweep per launch instead. Red cells are
+// those with i + j + k even (interior coordinates). Stage A then updates only
+// the red cells of the ring region (black ones keep u_k), which is the first
+// half-sweep; stage B updates only the black cells of the tile from that
+// half-swept field (red ones keep it), which is the second. All six
+// neighbours of a cell have the other colour, so each half-sweep is the
+// Jacobi update restricted to one colour. Launch L reads u_L and writes
+// u_{L+1}; stage A adds the residual of u_L, and block 0 judges u_{L-1}.
 constexpr int kTbX = 64, kTbY = 8;
 constexpr int kTbAX = kTbX + 4, kTbAY = kTbY + 4;  // u_k region (68 x 12)
 constexpr int kTbBX = kTbX + 2, kTbBY = kTbY + 2;  // u_{k+1} region (66 x 10)
@@ -481,7 +490,7 @@ constexpr int kTbACells = kTbAX * kTbAY;           // 816 -> 4 per thread
 constexpr int kTbBCells = kTbBX * kTbBY;           // 660 -> 3 per thread
 constexpr int kTbOut = kTbX * kTbY;                // 512 -> 2 per thread
 
-template <typename T, bool HAS_F>
+template <typename T, bool HAS_F, bool RB>
 __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   __shared__ T A[4][kTbAY][kTbAX];
   __shared__ T B[4][kTbBY][kTbBX];
@@ -489,11 +498,11 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   __shared__ int s_done;
 
   const int64_t L = (a.ctl ? a.ctl->base : 0) + a.k_off;
-  const int64_t k0 = 2 * L;  // iterate read by this launch
-  // Block 0 finalises the two iterates of the previous launch, in order.
+  const int64_t k0 = RB ? L : 2 * L;  // iterate read by this launch
+  // Block 0 finalises the iterates of the previous launch, in order.
   if (blockIdx.x == 0 && L >= 1 && (a.hist || a.ctl)) {
 #pragma unroll
-    for (int d = 2; d >= 1; --d) {
+    for (int d = RB ? 1 : 2; d >= 1; --d) {
       if (!a.ctl || a.ctl->done == RUNNING) {
         const double t = sum_partials(a.partials + ((k0 - d) & 3) * (int64_t)kMaxBlocks,
                                       a.nblocks, red);
@@ -583,7 +592,7 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   constexpr int QB = (kTbBCells + kThreads - 1) / kThreads;
   constexpr int QO = kTbOut / kThreads;
   // Loop-invariant cell bookkeeping. Stage A: cells of the 66 x 10 region.
-  int arb[QB], acb[QB];
+  int arb[QB], acb[QB], apar[QB];  // apar: parity of i + j
   int64_t aoff[QB];  // clamped into the field (for the f loads)
   bool aown[QB], ain[QB], atile[QB];
 #pragma unroll
@@ -592,13 +601,14 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     aown[q] = c < kTbBCells;
     arb[q] = c / kTbBX;
     acb[q] = c % kTbBX;
+    apar[q] = (arb[q] + acb[q]) & 1;  // i0 and j0 are even
     const int i = i0 - 1 + acb[q], j = j0 - 1 + arb[q];
     ain[q] = aown[q] && i >= 0 && i < nx && j >= 0 && j < ny;
     atile[q] = arb[q] >= 1 && arb[q] <= kTbY && acb[q] >= 1 && acb[q] <= kTbX;
     aoff[q] = (int64_t)(clampy(j) + 1) * sy + (clampx(i) + 1);
   }
   // Stage B: cells of the 64 x 8 tile.
-  int brt[QO], bct[QO];
+  int brt[QO], bct[QO], bpar[QO];
   int64_t boff[QO];
   bool bin[QO];
 #pragma unroll
@@ -606,6 +616,7 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
     const int c = t + q * kThreads;
     brt[q] = c / kTbX;
     bct[q] = c % kTbX;
+    bpar[q] = (brt[q] + bct[q]) & 1;
     const int i = i0 + bct[q], j = j0 + brt[q];
     bin[q] = i < nx && j < ny;
     boff[q] = (int64_t)(clampy(j) + 1) * sy + (clampx(i) + 1);  // clamped
@@ -653,7 +664,7 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
           const T yp = A[bc][ra + 1][ca], ym = A[bc][ra - 1][ca];
           const T zp = A[bp][ra][ca], zm = A[bm][ra][ca];
           const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
-          v = HAS_F ? (s - fa[q]) * c6 : s * c6;
+          if (!RB || ((apar[q] + z) & 1) == 0) v = HAS_F ? (s - fa[q]) * c6 : s * c6;
           if (atile[q] && z >= z0 && z < z1) {
             const double res = cell_residual(xp, xm, yp, ym, zp, zm, uc, fa[q], HAS_F);
             acc_a += res * res;
@@ -676,10 +687,13 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
         const T yp = B[bc][rb + 1][cb], ym = B[bc][rb - 1][cb];
         const T zp = B[bp][rb][cb], zm = B[bm][rb][cb];
         const T s = ((((xp + xm) + yp) + ym) + zp) + zm;
-        const T v = HAS_F ? (s - fb[q]) * c6 : s * c6;
+        const bool upd = !RB || ((bpar[q] + zb) & 1) == 1;
+        const T v = upd ? (HAS_F ? (s - fb[q]) * c6 : s * c6) : uc;
         __builtin_nontemporal_store(v, dst + (int64_t)(zb + 1) * sz + boff[q]);
-        const double res = cell_residual(xp, xm, yp, ym, zp, zm, uc, fb[q], HAS_F);
-        acc_b += res * res;
+        if (!RB) {
+          const double res = cell_residual(xp, xm, yp, ym, zp, zm, uc, fb[q], HAS_F);
+          acc_b += res * res;
+        }
       }
     }
 #pragma unroll
@@ -693,10 +707,10 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   }
 
   const double ta = block_sum(acc_a, red);
-  const double tb = block_sum(acc_b, red);
+  const double tb = RB ? 0.0 : block_sum(acc_b, red);
   if (threadIdx.x == 0) {
     a.partials[(int64_t)(k0 & 3) * kMaxBlocks + blockIdx.x] = ta;
-    a.partials[(int64_t)((k0 + 1) & 3) * kMaxBlocks + blockIdx.x] = tb;
+    if (!RB) a.partials[(int64_t)((k0 + 1) & 3) * kMaxBlocks + blockIdx.x] = tb;
   }
 }
 
@@ -834,30 +848,46 @@ SweepGeom tb2_geom(const ms_grid& g, int dtype) {
 
 int tb2_blocks(const ms_grid& g, int dtype) { return tb2_geom(g, dtype).nblocks; }
 
+namespace {
+
+template <typename T, bool RB>
+void launch_tb2_typed(const ms_grid& g, const SweepGeom& geo, void* const bufs[3], int nbuf,
+                      const void* f, double* partials, double* hist, Ctl* ctl, int64_t k_off,
+                      hipStream_t s) {
+  auto a = make_args<T>(g, geo);
+  for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<T*>(bufs[q]);
+  a.f = static_cast<const T*>(f);
+  a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
+  const dim3 grid(geo.nblocks), block(kThreads);
+  if (f) hipLaunchKernelGGL((sweep_tb2_kernel<T, true, RB>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((sweep_tb2_kernel<T, false, RB>), grid, block, 0, s, a);
+}
+
+template <bool RB>
+int launch_tb2_any(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
+                   double* partials, double* hist, Ctl* ctl, int64_t k_off, hipStream_t s) {
+  const SweepGeom geo = tb2_geom(g, dtype);
+  if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
+    return set_error(MS_EUNSUPPORTED, "two-stage sweep geometry with %d blocks", geo.nblocks);
+  if (dtype == MS_F64)
+    launch_tb2_typed<double, RB>(g, geo, bufs, nbuf, f, partials, hist, ctl, k_off, s);
+  else
+    launch_tb2_typed<float, RB>(g, geo, bufs, nbuf, f, partials, hist, ctl, k_off, s);
+  MS_LAUNCH_CHECK();
+  return MS_OK;
+}
+
+}  // namespace
+
 int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
                      const void* f, double* partials, double* hist, Ctl* ctl, int64_t k_off,
                      hipStream_t s) {
-  const SweepGeom geo = tb2_geom(g, dtype);
-  if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
-    return set_error(MS_EUNSUPPORTED, "two-sweep geometry with %d blocks", geo.nblocks);
-  const dim3 grid(geo.nblocks), block(kThreads);
-  if (dtype == MS_F64) {
-    auto a = make_args<double>(g, geo);
-    for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<double*>(bufs[q]);
-    a.f = static_cast<const double*>(f);
-    a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
-    if (f) hipLaunchKernelGGL((sweep_tb2_kernel<double, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_tb2_kernel<double, false>), grid, block, 0, s, a);
-  } else {
-    auto a = make_args<float>(g, geo);
-    for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<float*>(bufs[q]);
-    a.f = static_cast<const float*>(f);
-    a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
-    if (f) hipLaunchKernelGGL((sweep_tb2_kernel<float, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((sweep_tb2_kernel<float, false>), grid, block, 0, s, a);
-  }
-  MS_LAUNCH_CHECK();
-  return MS_OK;
+  return launch_tb2_any<false>(g, dtype, bufs, nbuf, f, partials, hist, ctl, k_off, s);
+}
+
+int launch_rbgs(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
+                double* partials, double* hist, Ctl* ctl, int64_t k_off, hipStream_t s) {
+  return launch_tb2_any<true>(g, dtype, bufs, nbuf, f, partials, hist, ctl, k_off, s);
 }
 
 int launch_finalize(const double* partials, int slot, int nblocks, double* out_norm, Ctl* ctl,

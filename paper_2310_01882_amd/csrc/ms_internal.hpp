@@ -206,6 +206,12 @@ int launch_sweep(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
 int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
                      const void* f, double* partials, double* hist, Ctl* ctl,
                      int64_t k_off, hipStream_t s);
+// One red-black Gauss-Seidel sweep per launch on the two-sweep kernel's
+// geometry: launch index k = base + k_off reads u_k from bufs[k % nbuf],
+// writes u_{k+1} to bufs[(k + 1) % nbuf], adds the norm of u_k into
+// partials[k & 3] and judges k - 1 (as launch_sweep does).
+int launch_rbgs(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
+                double* partials, double* hist, Ctl* ctl, int64_t k_off, hipStream_t s);
 // Blocks of the two-sweep kernel (for finalising its last partials).
 int tb2_blocks(const ms_grid& g, int dtype);
 

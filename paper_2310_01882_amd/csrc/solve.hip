@@ -110,11 +110,13 @@ struct ChunkRunner {
   bool use_graph;
   hipStream_t s;
   int tb;  // sweeps per launch: 1, or 2 (temporal blocking)
+  bool rb;  // red-black Gauss-Seidel sweeps (one per launch)
 
   int enqueue_chunk() {
     for (int i = 0; i < m; ++i) {
-      int rc = tb == 2 ? launch_sweep_tb2(g, dtype, bufs, 3, f, partials, hist, ctl, i, s)
-                       : launch_sweep(g, dtype, bufs, 3, f, partials, hist, ctl, i, geo, s);
+      int rc = rb        ? launch_rbgs(g, dtype, bufs, 3, f, partials, hist, ctl, i, s)
+               : tb == 2 ? launch_sweep_tb2(g, dtype, bufs, 3, f, partials, hist, ctl, i, s)
+                         : launch_sweep(g, dtype, bufs, 3, f, partials, hist, ctl, i, geo, s);
       if (rc) return rc;
     }
     hipLaunchKernelGGL(ctl_advance_kernel, dim3(1), dim3(1), 0, s, ctl, (int64_t)m);
@@ -201,7 +203,10 @@ int locate_iterate(const ms_grid& g, int dtype, void* const bufs[3], const void*
   return MS_OK;
 }
 
-int tb_of(const ms_solve_opts& o) { return o.temporal_block == 2 ? 2 : 1; }
+int tb_of(const ms_solve_opts& o) {
+  return o.method == MS_METHOD_JACOBI && o.temporal_block == 2 ? 2 : 1;
+}
+bool rb_of(const ms_solve_opts& o) { return o.method == MS_METHOD_RBGS; }
 
 int auto_chunk(const ms_grid& g, int requested) {
   if (requested > 0) return requested;
@@ -259,6 +264,8 @@ int check_opts(const ms_solve_opts* o) {
   if (o->temporal_block < 0 || o->temporal_block > 2)
     return set_error(MS_EUNSUPPORTED, "jacobi_solve: temporal_block %d not available",
                      o->temporal_block);
+  if (o->method != MS_METHOD_JACOBI && o->method != MS_METHOD_RBGS)
+    return set_error(MS_EUNSUPPORTED, "jacobi_solve: unknown method %d", o->method);
   if (o->precision == MS_SOLVE_F32_REFINED) {
     if (!(o->inner_eta > 0.0 && o->inner_eta < 1.0))
       return set_error(MS_EINVAL, "jacobi_solve: inner_eta must be in (0, 1)");
@@ -378,6 +385,43 @@ extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tm
   return MS_OK;
 }
 
+extern "C" int rbgs_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
+                           int64_t n, double* res_dev, void* work, size_t work_bytes,
+                           void* stream) {
+  clear_error();
+  if (int rc = check_grid(g, "rbgs_sweeps")) return rc;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "rbgs_sweeps: dtype %d", dtype);
+  if (!u || !u_tmp) return set_error(MS_EINVAL, "rbgs_sweeps: u and u_tmp required");
+  if (n < 0) return set_error(MS_EINVAL, "rbgs_sweeps: n < 0");
+  const size_t bytes = (size_t)field_span(*g) * elem_size(dtype);
+  if (overlaps(u, bytes, u_tmp, bytes))
+    return set_error(MS_EINVAL, "rbgs_sweeps: u and u_tmp overlap");
+  if (f && (overlaps(f, bytes, u, bytes) || overlaps(f, bytes, u_tmp, bytes)))
+    return set_error(MS_EINVAL, "rbgs_sweeps: f overlaps a sweep buffer");
+  const size_t need = jacobi_sweeps_workspace_bytes(g);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "rbgs_sweeps: workspace needs %zu bytes", need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  double* partials = static_cast<double*>(work);
+  void* bufs[3] = {u, u_tmp, u};
+  for (int64_t k = 0; k < n; ++k)
+    if (int rc = launch_rbgs(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, k, s)) return rc;
+  if (res_dev) {
+    if (n >= 1)
+      if (int rc = launch_finalize(partials, (int)((n - 1) & 3), tb2_blocks(*g, dtype), nullptr,
+                                   nullptr, res_dev, n - 1, s))
+        return rc;
+    void* last = (n & 1) ? u_tmp : u;
+    const int slot = (int)(n & 3);  // partials[(n - 1) & 3] is final by now
+    if (int rc = launch_residual(*g, dtype, last, f, false, partials, slot, s)) return rc;
+    if (int rc = launch_finalize(partials, slot, residual_blocks(*g), nullptr, nullptr, res_dev,
+                                 n, s))
+      return rc;
+  }
+  return MS_OK;
+}
+
 extern "C" int jacobi_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
                              int64_t n, double* res_dev, void* work, size_t work_bytes,
                              void* stream) {
@@ -398,7 +442,7 @@ extern "C" void ms_solve_opts_default(ms_solve_opts* o) {
   o->stall_window = 256;
   o->temporal_block = 2;
   o->use_graph = 1;
-  o->reserved = 0;
+  o->method = MS_METHOD_JACOBI;
 }
 
 extern "C" size_t jacobi_workspace_bytes(const ms_grid* g, const ms_solve_opts* o) {
@@ -443,7 +487,7 @@ int solve_f64(const ms_grid& g, const ms_solve_opts& o, double* u, const double*
   hc.max_sweeps = o.max_sweeps;
   const int tb = tb_of(o);
   ChunkRunner run{g, MS_F64, {u, b1, b2}, f, partials, hist, ctl, geo,
-                  auto_chunk(g, o.check_every), o.use_graph != 0, s, tb};
+                  auto_chunk(g, o.check_every), o.use_graph != 0, s, tb, rb_of(o)};
   if (int rc = run.run(&hc)) return rc;
   const int64_t K = hc.K;
   void* ans = nullptr;
@@ -548,7 +592,7 @@ int solve_refined(const ms_grid& g, const ms_solve_opts& o, double* x, const dou
     hc.max_sweeps = cap;
     const int tb = tb_of(o);
     ChunkRunner run{h, MS_F32, {e[0], e[1], e[2]}, rhat, partials, hist, ctl, geo,
-                    auto_chunk(g, o.check_every), o.use_graph != 0, s, tb};
+                    auto_chunk(g, o.check_every), o.use_graph != 0, s, tb, rb_of(o)};
     if (int rc = run.run(&hc)) return rc;
     if (hc.done == NONFINITE) {
       status = set_error(MS_ENONFINITE, "jacobi_solve: inner residual not finite");

@@ -1,6 +1,6 @@
 """Small, fixed workloads for rocprofv3 runs (kernel traces and HBM counters).
 
-    python -m paper_2310_01882_amd.profile_run sweep   [--dtype f64|f32] [--sweeps N] [--tb 1|2]
+    python -m paper_2310_01882_amd.profile_run sweep   [--dtype f64|f32] [--sweeps N] [--tb 1|2] [--rb]
     python -m paper_2310_01882_amd.profile_run advect  [--passes N]
     python -m paper_2310_01882_amd.profile_run batched
     python -m paper_2310_01882_amd.profile_run cnn     [--steps N]
@@ -8,7 +8,8 @@
 
 `sweep` runs N sweeps of the 512^3 Poisson workload (8 Gaussian sources,
 seed 1, zero start) on aligned fields, with the launch geometry the
-benchmark uses (--tb 2: two sweeps per pass). `advect` runs N passes of the
+benchmark uses (--tb 2: two sweeps per pass; --rb: red-black Gauss-Seidel
+sweeps instead). `advect` runs N passes of the
 512 x 512 x 256 advection term. `batched` autotunes and then solves the
 benchmark's batch (64 instances, sizes log-uniform in [32, 256], seed 4,
 FP32-refined to 1e-8) once. `cnn` runs N training steps (forward, backward,
@@ -33,6 +34,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("what", choices=["sweep", "advect", "batched", "cnn", "copy"])
     ap.add_argument("--tb", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--rb", action="store_true")
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     ap.add_argument("--sweeps", type=int, default=10)
@@ -62,9 +64,13 @@ def main():
         u = ms.alloc_field(n, n, n, dt)
         tmp = ms.alloc_field(n, n, n, dt)
         res = torch.zeros(args.sweeps + 1, dtype=torch.float64, device="cuda")
-        ms.jacobi_sweeps(u, tmp, args.sweeps, f=f, res=res, temporal_block=args.tb)
+        if args.rb:
+            ms.rbgs_sweeps(u, tmp, args.sweeps, f=f, res=res)
+        else:
+            ms.jacobi_sweeps(u, tmp, args.sweeps, f=f, res=res, temporal_block=args.tb)
         torch.cuda.synchronize()
-        print(f"{args.sweeps} sweeps (temporal block {args.tb}) of {n}^3 ({args.dtype}) done; "
+        kind = "red-black Gauss-Seidel" if args.rb else f"temporal block {args.tb}"
+        print(f"{args.sweeps} sweeps ({kind}) of {n}^3 ({args.dtype}) done; "
               f"final residual {res[-1].item():.6e}", flush=True)
         return
     if args.what == "batched":
