@@ -113,6 +113,61 @@ int residual_norm(const ms_grid* g, int dtype, const void* u, const void* f,
                   double* norm_out, int out_on_device, void* work,
                   size_t work_bytes, void* stream);
 
+/* ---- runtime-compiled stencil programs ---------------------------------
+ * stencil.apply with an arbitrary arithmetic body (Section 2.2 and
+ * Listing 2: a region of arith operations on constant-offset accesses of
+ * input temps, writing the interior out-of-place; Section 3: the flow
+ * extracts such regions from Fortran loop nests). The region is given as
+ * text, parsed and compiled to a device kernel with hipRTC (gfx950) by
+ * ms_jit_compile, once; ms_jit_apply runs it on any grid.
+ *
+ * Language. Statements end with ';'; '#' starts a comment to end of line.
+ *   field a, b, ...;     input fields (at most 8), in argument order
+ *   param p, ...;        scalar parameters (at most 8), passed as double
+ *   profile t, ...;      per-level coefficients (at most 4): one value per
+ *                        interior level k (nz values), read as t at level k
+ *   let x = expr;        a named per-cell value (at most 256)
+ *   out o = expr;        an output field (1 to 4), in argument order
+ * expr: + - (left-associative) over terms; term: * / (left-associative)
+ * over unary; unary: '-' unary | primary; primary: a decimal number
+ * (digits [. digits] [e|E [+|-] digits]), a field access a[dx,dy,dz]
+ * with integer offsets in [-1, 1] (a bare field name is a[0,0,0]), a
+ * param, a profile, a let name, or '(' expr ')'. Names are unique across
+ * all declarations; outputs cannot be read.
+ * Arithmetic: every operation is evaluated in the program's dtype exactly
+ * in the order the text gives (no contraction, no reassociation, IEEE
+ * division, round to nearest); constants are rounded to double, then to
+ * the dtype; params are rounded from double to the dtype at launch.
+ *
+ * ms_jit_compile: program (host string, at most 64 KiB), dtype MS_F64 or
+ * MS_F32; *out receives a handle owned by the caller (ms_jit_free). Parse
+ * errors -> MS_EINVAL with "line L col C: ..." in ms_last_error; hipRTC
+ * failures -> MS_EHIP. Needs no GPU. Synchronous.
+ * ms_jit_apply: fields / profiles / outputs are arrays of device pointers
+ * (fields and outputs on grid g, profiles of nz values), params a host
+ * array; each count must equal the program's. Outputs are written on the
+ * interior only and must not overlap any input or each other (MS_EINVAL).
+ * Loads the code on the current device on first use. Async on `stream`.
+ * ms_jit_signature / ms_jit_name: declared counts and names (kind
+ * MS_JIT_FIELD, MS_JIT_PARAM, MS_JIT_PROFILE, MS_JIT_OUTPUT); ms_jit_name
+ * returns NULL out of range. ms_jit_source: the generated HIP source, valid
+ * until ms_jit_free. */
+typedef struct ms_jit_stencil ms_jit_stencil;
+#define MS_JIT_FIELD 0
+#define MS_JIT_PARAM 1
+#define MS_JIT_PROFILE 2
+#define MS_JIT_OUTPUT 3
+int ms_jit_compile(const char* program, int dtype, ms_jit_stencil** out);
+int ms_jit_apply(ms_jit_stencil* st, const ms_grid* g, const void* const* fields,
+                 int n_fields, const double* params, int n_params,
+                 const void* const* profiles, int n_profiles,
+                 void* const* outputs, int n_outputs, void* stream);
+int ms_jit_signature(const ms_jit_stencil* st, int* n_fields, int* n_params,
+                     int* n_profiles, int* n_outputs);
+const char* ms_jit_name(const ms_jit_stencil* st, int kind, int index);
+const char* ms_jit_source(const ms_jit_stencil* st);
+void ms_jit_free(ms_jit_stencil* st);
+
 /* ---- fixed number of Jacobi sweeps -------------------------------------
  * The 7-point Laplace/Poisson iteration of Section 4.1 as an out-of-place
  * (Jacobi) update, u'(p) = (S(p) - f(p)) * fl(1/6) (u'(p) = S(p) * fl(1/6)

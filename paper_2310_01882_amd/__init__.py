@@ -35,6 +35,7 @@ MS_SOLVE_F64 = 0
 MS_SOLVE_F32_REFINED = 1
 MS_METHOD_JACOBI = 0
 MS_METHOD_RBGS = 1
+MS_JIT_FIELD, MS_JIT_PARAM, MS_JIT_PROFILE, MS_JIT_OUTPUT = 0, 1, 2, 3
 
 
 class MsError(RuntimeError):
@@ -145,6 +146,14 @@ SIGNATURES = {
     "cnn_features": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _I, _P]),
     "cnn_guess": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
     "cnn_target": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
+    "ms_jit_compile": (_I, [ctypes.c_char_p, _I, ctypes.POINTER(_P)]),
+    "ms_jit_apply": (_I, [_P, ctypes.POINTER(Grid), ctypes.POINTER(_P), _I, ctypes.POINTER(_D),
+                          _I, ctypes.POINTER(_P), _I, ctypes.POINTER(_P), _I, _P]),
+    "ms_jit_signature": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I),
+                              ctypes.POINTER(_I)]),
+    "ms_jit_name": (ctypes.c_char_p, [_P, _I, _I]),
+    "ms_jit_source": (ctypes.c_char_p, [_P]),
+    "ms_jit_free": (None, [_P]),
 }
 
 
@@ -556,3 +565,63 @@ def batch_tuning_load(entries) -> None:
 
 def batch_tuning_clear() -> None:
     lib.ms_batch_tuning_clear()
+
+
+# ------------------------------------------------- runtime-compiled stencils
+
+class JitStencil:
+    """A stencil program compiled for the device (ms_jit_compile); the
+    language is described in include/mistencil.h. ``fields``, ``params``,
+    ``profiles`` and ``outputs`` list the declared names in argument order;
+    ``source`` is the generated HIP source."""
+
+    def __init__(self, program: str, dtype=torch.float64):
+        if dtype not in (torch.float64, torch.float32):
+            raise ValueError("dtype must be float64 or float32")
+        self.dtype = dtype
+        self._lib = lib
+        h = _P()
+        _check(lib.ms_jit_compile(program.encode(), MS_F64 if dtype == torch.float64 else MS_F32,
+                                  ctypes.byref(h)))
+        self._h = h
+        n = [_I() for _ in range(4)]
+        _check(lib.ms_jit_signature(h, *[ctypes.byref(x) for x in n]))
+        self.fields, self.params, self.profiles, self.outputs = (
+            [lib.ms_jit_name(h, kind, i).decode() for i in range(c.value)]
+            for kind, c in zip((MS_JIT_FIELD, MS_JIT_PARAM, MS_JIT_PROFILE, MS_JIT_OUTPUT), n))
+        self.source = lib.ms_jit_source(h).decode()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ms_jit_free(h)
+            self._h = None
+
+    def apply(self, fields, outputs, params=(), profiles=(), stream=None):
+        """Run the program: ``fields`` and ``outputs`` are device fields of
+        one layout (the program's dtype), ``params`` floats, ``profiles``
+        contiguous device vectors of nz values; each in declaration order."""
+        fields, outputs = list(fields), list(outputs)
+        if not outputs:
+            raise ValueError("no outputs")
+        ref = outputs[0]
+        for n, t in enumerate(fields):
+            _field_check(t, f"fields[{n}]", self.dtype)
+            _same_layout(ref, t, f"outputs[0]/fields[{n}]")
+        for n, t in enumerate(outputs):
+            _field_check(t, f"outputs[{n}]", self.dtype)
+            _same_layout(ref, t, f"outputs[0]/outputs[{n}]")
+        nz = ref.shape[0] - 2
+        for n, t in enumerate(profiles):
+            if (t.dtype != self.dtype or t.numel() != nz or not t.is_contiguous()
+                    or t.device.type != "cuda"):
+                raise ValueError(f"profiles[{n}] must be a contiguous device vector of nz values "
+                                 "in the program's dtype")
+        g = grid_of(ref)
+        fa = (_P * max(len(fields), 1))(*[t.data_ptr() for t in fields])
+        pa = (_D * max(len(params), 1))(*[float(x) for x in params])
+        qa = (_P * max(len(profiles), 1))(*[t.data_ptr() for t in profiles])
+        oa = (_P * len(outputs))(*[t.data_ptr() for t in outputs])
+        _check(lib.ms_jit_apply(self._h, ctypes.byref(g), fa, len(fields), pa, len(params), qa,
+                                len(profiles), oa, len(outputs), _stream(stream)))
+        return outputs

@@ -1,0 +1,637 @@
+// Runtime-compiled stencil programs: stencil.apply with an arbitrary
+// arithmetic body (Section 2.2 and Listing 2: a region of arith operations
+// on constant-offset accesses of input temps; Section 3: the flow discovers
+// such regions in Fortran loop nests and extracts them). A small text
+// language describes the region; it is parsed here, turned into a z-marching
+// HIP kernel and compiled for the device with hipRTC once per program.
+//
+// Language (grammar and rules are stated in mistencil.h):
+//   field u, f;  param c;  profile t;
+//   let s = ((((u[1,0,0] + u[-1,0,0]) + u[0,1,0]) + u[0,-1,0]) + u[0,0,1]) + u[0,0,-1];
+//   out v = (s - f) * c;
+//
+// Generated kernel: a block owns a 64 x 4 (x, y) tile and marches a
+// z-chunk; every distinct (field, dx, dy) column the body reads is a queue
+// of registers over its z offsets, so each column loads one new level per
+// step (prefetched one step ahead, from a level clamped into the halo so the
+// load is unconditional). Every operation of the body is emitted fully
+// parenthesised in source order and the program is compiled without
+// contraction, so each value is rounded as the text says.
+#include "ms_internal.hpp"
+
+#include <hip/hiprtc.h>
+
+#include <cctype>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+namespace ms {
+namespace {
+
+constexpr int kJitMaxFields = 8, kJitMaxOutputs = 4, kJitMaxParams = 8, kJitMaxProfiles = 4;
+constexpr int kJitMaxLets = 256, kJitMaxNodes = 1 << 16, kJitMaxDepth = 200;
+constexpr size_t kJitMaxSource = 1 << 16;
+
+struct Node {
+  enum Kind { NUM, FIELD, PARAM, PROFILE, LET, NEG, ADD, SUB, MUL, DIV } kind;
+  double num = 0.0;
+  int idx = 0;         // field / param / profile / let index
+  int dx = 0, dy = 0, dz = 0;
+  int a = -1, b = -1;  // operands
+};
+
+struct Program {
+  std::vector<std::string> fields, params, profiles;
+  std::vector<std::string> let_names, out_names;
+  std::vector<int> let_root, out_root;
+  std::vector<Node> nodes;
+};
+
+// ------------------------------------------------------------------ parser
+
+struct ParseError {
+  std::string msg;
+};
+
+class Parser {
+ public:
+  explicit Parser(const char* s) : s_(s) {}
+
+  Program run() {
+    Program p;
+    prog_ = &p;
+    skip();
+    while (s_[pos_]) {
+      const std::string kw = word();
+      if (kw == "field" || kw == "param" || kw == "profile") {
+        std::vector<std::string>& list =
+            kw == "field" ? p.fields : kw == "param" ? p.params : p.profiles;
+        do {
+          const std::string n = name();
+          declare(n);
+          list.push_back(n);
+        } while (accept(','));
+        const size_t cap = kw == "field" ? kJitMaxFields
+                           : kw == "param" ? kJitMaxParams
+                                           : kJitMaxProfiles;
+        if (list.size() > cap) fail("too many " + kw + " declarations");
+      } else if (kw == "let" || kw == "out") {
+        const std::string n = name();
+        expect('=');
+        depth_ = 0;
+        const int root = expr();
+        declare(n);
+        if (kw == "let") {
+          p.let_names.push_back(n);
+          p.let_root.push_back(root);
+          if (p.let_names.size() > (size_t)kJitMaxLets) fail("too many let statements");
+        } else {
+          p.out_names.push_back(n);
+          p.out_root.push_back(root);
+          if (p.out_names.size() > (size_t)kJitMaxOutputs) fail("too many outputs");
+        }
+      } else {
+        fail(kw.empty() ? "expected a statement" : "unknown statement '" + kw + "'");
+      }
+      expect(';');
+    }
+    if (p.out_names.empty()) fail("the program has no output");
+    return p;
+  }
+
+ private:
+  const char* s_;
+  size_t pos_ = 0;
+  int depth_ = 0;
+  Program* prog_ = nullptr;
+  std::set<std::string> names_;
+
+  [[noreturn]] void fail(const std::string& m) {
+    int line = 1, col = 1;
+    for (size_t i = 0; i < pos_ && s_[i]; ++i) {
+      if (s_[i] == '\n') {
+        ++line;
+        col = 1;
+      } else {
+        ++col;
+      }
+    }
+    throw ParseError{"line " + std::to_string(line) + " col " + std::to_string(col) + ": " + m};
+  }
+
+  void skip() {
+    for (;;) {
+      while (s_[pos_] && std::isspace((unsigned char)s_[pos_])) ++pos_;
+      if (s_[pos_] != '#') return;
+      while (s_[pos_] && s_[pos_] != '\n') ++pos_;
+    }
+  }
+  bool accept(char c) {
+    if (s_[pos_] != c) return false;
+    ++pos_;
+    skip();
+    return true;
+  }
+  void expect(char c) {
+    if (!accept(c)) fail(std::string("expected '") + c + "'");
+  }
+  std::string word() {
+    std::string w;
+    if (std::isalpha((unsigned char)s_[pos_]) || s_[pos_] == '_')
+      while (std::isalnum((unsigned char)s_[pos_]) || s_[pos_] == '_') w += s_[pos_++];
+    skip();
+    return w;
+  }
+  std::string name() {
+    const std::string n = word();
+    if (n.empty()) fail("expected a name");
+    return n;
+  }
+  void declare(const std::string& n) {
+    static const char* kReserved[] = {"field", "param", "profile", "let", "out"};
+    for (const char* r : kReserved)
+      if (n == r) fail("'" + n + "' is a reserved word");
+    if (!names_.insert(n).second) fail("'" + n + "' is already defined");
+  }
+  int add(const Node& n) {
+    if (prog_->nodes.size() >= (size_t)kJitMaxNodes) fail("program too large");
+    prog_->nodes.push_back(n);
+    return (int)prog_->nodes.size() - 1;
+  }
+  int binary(Node::Kind k, int a, int b) {
+    Node n;
+    n.kind = k;
+    n.a = a;
+    n.b = b;
+    return add(n);
+  }
+  int find(const std::vector<std::string>& v, const std::string& n) {
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] == n) return (int)i;
+    return -1;
+  }
+  int offset() {
+    const bool neg = accept('-');
+    if (!std::isdigit((unsigned char)s_[pos_])) fail("expected an integer offset");
+    int v = 0;
+    while (std::isdigit((unsigned char)s_[pos_])) {
+      v = v * 10 + (s_[pos_++] - '0');
+      if (v > 1000) fail("offset out of range");
+    }
+    skip();
+    v = neg ? -v : v;
+    if (v < -1 || v > 1) fail("offsets must lie in [-1, 1] (halo width 1)");
+    return v;
+  }
+
+  int expr() {
+    if (++depth_ > kJitMaxDepth) fail("expression nested too deeply");
+    int l = term();
+    for (;;) {
+      if (accept('+')) l = binary(Node::ADD, l, term());
+      else if (accept('-')) l = binary(Node::SUB, l, term());
+      else break;
+    }
+    --depth_;
+    return l;
+  }
+  int term() {
+    int l = unary();
+    for (;;) {
+      if (accept('*')) l = binary(Node::MUL, l, unary());
+      else if (accept('/')) l = binary(Node::DIV, l, unary());
+      else break;
+    }
+    return l;
+  }
+  int unary() {
+    if (accept('-')) {
+      if (++depth_ > kJitMaxDepth) fail("expression nested too deeply");
+      const int a = unary();
+      --depth_;
+      return binary(Node::NEG, a, -1);
+    }
+    return primary();
+  }
+  int primary() {
+    if (accept('(')) {
+      const int e = expr();
+      expect(')');
+      return e;
+    }
+    const char c = s_[pos_];
+    if (std::isdigit((unsigned char)c) || c == '.') {
+      const char* start = s_ + pos_;
+      // decimal literal: digits [. digits] [e|E [+|-] digits]
+      size_t p = pos_;
+      bool digits = false;
+      while (std::isdigit((unsigned char)s_[p])) ++p, digits = true;
+      if (s_[p] == '.') {
+        ++p;
+        while (std::isdigit((unsigned char)s_[p])) ++p, digits = true;
+      }
+      if (!digits) fail("malformed number");
+      if (s_[p] == 'e' || s_[p] == 'E') {
+        size_t q = p + 1;
+        if (s_[q] == '+' || s_[q] == '-') ++q;
+        if (!std::isdigit((unsigned char)s_[q])) fail("malformed exponent");
+        while (std::isdigit((unsigned char)s_[q])) ++q;
+        p = q;
+      }
+      if (std::isalpha((unsigned char)s_[p]) || s_[p] == '_') fail("malformed number");
+      const std::string text(start, s_ + p);
+      const double v = std::strtod(text.c_str(), nullptr);
+      if (!std::isfinite(v)) fail("constant out of range");
+      pos_ = p;
+      skip();
+      Node n;
+      n.kind = Node::NUM;
+      n.num = v;
+      return add(n);
+    }
+    const std::string id = word();
+    if (id.empty()) fail("expected a number, a name or '('");
+    Node n;
+    int k;
+    if ((k = find(prog_->fields, id)) >= 0) {
+      n.kind = Node::FIELD;
+      n.idx = k;
+      if (accept('[')) {
+        n.dx = offset();
+        expect(',');
+        n.dy = offset();
+        expect(',');
+        n.dz = offset();
+        expect(']');
+      }
+    } else if ((k = find(prog_->params, id)) >= 0) {
+      n.kind = Node::PARAM;
+      n.idx = k;
+    } else if ((k = find(prog_->profiles, id)) >= 0) {
+      n.kind = Node::PROFILE;
+      n.idx = k;
+    } else if ((k = find(prog_->let_names, id)) >= 0) {
+      n.kind = Node::LET;
+      n.idx = k;
+    } else {
+      fail("'" + id + "' is not defined (outputs cannot be read)");
+    }
+    if (n.kind != Node::FIELD && s_[pos_] == '[') fail("only fields take offsets");
+    return add(n);
+  }
+};
+
+// ----------------------------------------------------------------- codegen
+
+struct Column {
+  int field, dx, dy;
+  int dmin, dmax;  // z offsets read
+};
+
+std::string hex_literal(double v, int dtype) {
+  char buf[64];
+  if (dtype == MS_F64) {
+    std::snprintf(buf, sizeof buf, "%a", v);
+  } else {
+    const float f = (float)v;  // round to nearest, like a conversion at run time
+    std::snprintf(buf, sizeof buf, "%af", (double)f);
+  }
+  return buf;
+}
+
+struct Codegen {
+  const Program& p;
+  int dtype;
+  std::vector<Column> cols;
+  std::map<std::pair<int, std::pair<int, int>>, int> col_of;
+
+  int column(int f, int dx, int dy) {
+    auto key = std::make_pair(f, std::make_pair(dx, dy));
+    auto it = col_of.find(key);
+    if (it != col_of.end()) return it->second;
+    cols.push_back({f, dx, dy, 2, -2});
+    col_of[key] = (int)cols.size() - 1;
+    return (int)cols.size() - 1;
+  }
+
+  static std::string qname(int c, int d) {
+    return "q" + std::to_string(c) + (d < 0 ? "m" : "p") + std::to_string(d < 0 ? -d : d);
+  }
+
+  std::string emit(int id) {
+    const Node& n = p.nodes[id];
+    switch (n.kind) {
+      case Node::NUM: return "((T)" + hex_literal(n.num, dtype) + ")";
+      case Node::FIELD: {
+        const int c = col_of.at(std::make_pair(n.idx, std::make_pair(n.dx, n.dy)));
+        return qname(c, n.dz);
+      }
+      case Node::PARAM: return "prm" + std::to_string(n.idx);
+      case Node::PROFILE: return "pf" + std::to_string(n.idx);
+      case Node::LET: return "t" + std::to_string(n.idx);
+      case Node::NEG: return "(-" + emit(n.a) + ")";
+      case Node::ADD: return "(" + emit(n.a) + " + " + emit(n.b) + ")";
+      case Node::SUB: return "(" + emit(n.a) + " - " + emit(n.b) + ")";
+      case Node::MUL: return "(" + emit(n.a) + " * " + emit(n.b) + ")";
+      case Node::DIV: return "(" + emit(n.a) + " / " + emit(n.b) + ")";
+    }
+    return "";
+  }
+
+  std::string run() {
+    std::set<int> prm_used, prof_used;
+    for (const Node& n : p.nodes) {
+      if (n.kind == Node::FIELD) {
+        Column& c = cols[column(n.idx, n.dx, n.dy)];
+        c.dmin = std::min(c.dmin, n.dz);
+        c.dmax = std::max(c.dmax, n.dz);
+      } else if (n.kind == Node::PARAM) {
+        prm_used.insert(n.idx);
+      } else if (n.kind == Node::PROFILE) {
+        prof_used.insert(n.idx);
+      }
+    }
+    std::string o;
+    o += dtype == MS_F64 ? "typedef double T;\n" : "typedef float T;\n";
+    o += "struct JitArgs {\n"
+         "  const T* in[8];\n  T* out[4];\n  const T* prof[4];\n  T prm[8];\n"
+         "  long long sy, sz;\n  int nx, ny, nz, zc;\n  int tiles_x, tiles_y, nblocks, pad;\n"
+         "};\n";
+    o += "extern \"C\" __global__ __launch_bounds__(256) void ms_jit_kernel(JitArgs a) {\n"
+         "  const int b = blockIdx.x, nb = a.nblocks;\n"
+         "  const int xcd = b & 7, slot = b >> 3, qn = nb >> 3, rn = nb & 7;\n"
+         "  const int tile = xcd * qn + (xcd < rn ? xcd : rn) + slot;\n"
+         "  const int txi = tile % a.tiles_x, rest = tile / a.tiles_x;\n"
+         "  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;\n"
+         "  const int i = txi * 64 + (int)(threadIdx.x & 63);\n"
+         "  const int j = tyi * 4 + (int)(threadIdx.x >> 6);\n"
+         "  if (i >= a.nx || j >= a.ny) return;\n"
+         "  const int nz = a.nz, z0 = tzi * a.zc;\n"
+         "  const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;\n"
+         "  const long long sy = a.sy, sz = a.sz;\n"
+         "  const long long base = (long long)(j + 1) * sy + (i + 1);\n"
+         "  auto lev = [&](int l) { return (long long)((l < nz ? l : nz) + 1) * sz; };\n";
+    for (int k : prm_used) o += "  const T prm" + std::to_string(k) + " = a.prm[" + std::to_string(k) + "];\n";
+    for (size_t c = 0; c < cols.size(); ++c) {
+      const Column& q = cols[c];
+      const std::string cs = std::to_string(c);
+      o += "  const T* __restrict__ c" + cs + " = a.in[" + std::to_string(q.field) + "] + base + (" +
+           std::to_string(q.dy) + ") * sy + (" + std::to_string(q.dx) + ");\n";
+      for (int d = q.dmin; d <= q.dmax; ++d)
+        o += "  T " + qname((int)c, d) + " = c" + cs + "[lev(z0 + (" + std::to_string(d) + "))];\n";
+      o += "  T n" + cs + "a = c" + cs + "[lev(z0 + " + std::to_string(q.dmax + 1) + ")];\n";
+      o += "  T n" + cs + "b = c" + cs + "[lev(z0 + " + std::to_string(q.dmax + 2) + ")];\n";
+    }
+    o += "  for (int k = z0; k < z1; ++k) {\n";
+    for (int k : prof_used)
+      o += "    const T pf" + std::to_string(k) + " = a.prof[" + std::to_string(k) + "][k];\n";
+    for (size_t l = 0; l < p.let_root.size(); ++l)
+      o += "    const T t" + std::to_string(l) + " = " + emit(p.let_root[l]) + ";\n";
+    for (size_t r = 0; r < p.out_root.size(); ++r) {
+      const std::string rs = std::to_string(r);
+      o += "    const T o" + rs + " = " + emit(p.out_root[r]) + ";\n";
+      o += "    __builtin_nontemporal_store(o" + rs + ", a.out[" + rs +
+           "] + (long long)(k + 1) * sz + base);\n";
+    }
+    // rotate the column queues; the level two steps ahead is loaded now
+    for (size_t c = 0; c < cols.size(); ++c) {
+      const Column& q = cols[c];
+      const std::string cs = std::to_string(c);
+      for (int d = q.dmin; d < q.dmax; ++d)
+        o += "    " + qname((int)c, d) + " = " + qname((int)c, d + 1) + ";\n";
+      o += "    " + qname((int)c, q.dmax) + " = n" + cs + "a;\n";
+      o += "    n" + cs + "a = n" + cs + "b;\n";
+      o += "    n" + cs + "b = c" + cs + "[lev(k + " + std::to_string(q.dmax + 3) + ")];\n";
+    }
+    o += "  }\n}\n";
+    return o;
+  }
+};
+
+// Host mirror of the generated JitArgs (same member order and types).
+template <typename T>
+struct JitArgs {
+  const T* in[kJitMaxFields];
+  T* out[kJitMaxOutputs];
+  const T* prof[kJitMaxProfiles];
+  T prm[kJitMaxParams];
+  long long sy, sz;
+  int nx, ny, nz, zc;
+  int tiles_x, tiles_y, nblocks, pad;
+};
+
+// hipRTC options: the target, no contraction (each operation of the body is
+// rounded on its own), no packed FP32 instructions.
+int rtc_compile(const std::string& src, std::vector<char>* code) {
+  hiprtcProgram prog = nullptr;
+  if (hiprtcCreateProgram(&prog, src.c_str(), "ms_jit.hip", 0, nullptr, nullptr) !=
+      HIPRTC_SUCCESS)
+    return set_error(MS_EHIP, "ms_jit_compile: hiprtcCreateProgram failed");
+  const char* opts[] = {"--offload-arch=gfx950", "-O3", "-ffp-contract=off", "-Xclang",
+                        "-target-feature", "-Xclang", "-packed-fp32-ops"};
+  const hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof *opts), opts);
+  int rc = MS_OK;
+  if (r != HIPRTC_SUCCESS) {
+    size_t n = 0;
+    std::string log;
+    if (hiprtcGetProgramLogSize(prog, &n) == HIPRTC_SUCCESS && n > 1) {
+      log.resize(n);
+      (void)hiprtcGetProgramLog(prog, &log[0]);
+      if (log.size() > 600) log.resize(600);
+    }
+    rc = set_error(MS_EHIP, "ms_jit_compile: hipRTC: %s %s", hiprtcGetErrorString(r),
+                   log.c_str());
+  } else {
+    size_t n = 0;
+    if (hiprtcGetCodeSize(prog, &n) != HIPRTC_SUCCESS || n == 0) {
+      rc = set_error(MS_EHIP, "ms_jit_compile: no code object");
+    } else {
+      code->resize(n);
+      if (hiprtcGetCode(prog, code->data()) != HIPRTC_SUCCESS)
+        rc = set_error(MS_EHIP, "ms_jit_compile: hiprtcGetCode failed");
+    }
+  }
+  (void)hiprtcDestroyProgram(&prog);
+  return rc;
+}
+
+}  // namespace
+}  // namespace ms
+
+struct ms_jit_stencil {
+  ms::Program prog;
+  int dtype = MS_F64;
+  std::string source;
+  std::vector<char> code;
+  std::mutex mu;                                         // guards the module maps
+  std::map<int, std::pair<hipModule_t, hipFunction_t>> mods;  // per device
+};
+
+using namespace ms;
+
+extern "C" int ms_jit_compile(const char* program, int dtype, ms_jit_stencil** out) {
+  clear_error();
+  if (!program || !out) return set_error(MS_EINVAL, "ms_jit_compile: program and out required");
+  *out = nullptr;
+  if (dtype != MS_F64 && dtype != MS_F32)
+    return set_error(MS_EUNSUPPORTED, "ms_jit_compile: dtype %d", dtype);
+  if (std::strlen(program) > kJitMaxSource)
+    return set_error(MS_EINVAL, "ms_jit_compile: program longer than %zu bytes", kJitMaxSource);
+  try {
+    Program p = Parser(program).run();
+    std::string src = Codegen{p, dtype}.run();
+    std::vector<char> code;
+    if (int rc = rtc_compile(src, &code)) return rc;
+    auto* st = new ms_jit_stencil;
+    st->prog = std::move(p);
+    st->dtype = dtype;
+    st->source = std::move(src);
+    st->code = std::move(code);
+    *out = st;
+    return MS_OK;
+  } catch (const ParseError& e) {
+    return set_error(MS_EINVAL, "ms_jit_compile: %s", e.msg.c_str());
+  } catch (const std::exception& e) {
+    return set_error(MS_EINVAL, "ms_jit_compile: %s", e.what());
+  }
+}
+
+extern "C" void ms_jit_free(ms_jit_stencil* st) {
+  if (!st) return;
+  int cur = -1;
+  const bool have = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : st->mods) {
+    if (hipSetDevice(kv.first) == hipSuccess) (void)hipModuleUnload(kv.second.first);
+  }
+  if (have) (void)hipSetDevice(cur);
+  delete st;
+}
+
+extern "C" const char* ms_jit_source(const ms_jit_stencil* st) {
+  return st ? st->source.c_str() : nullptr;
+}
+
+extern "C" int ms_jit_signature(const ms_jit_stencil* st, int* n_fields, int* n_params,
+                                int* n_profiles, int* n_outputs) {
+  clear_error();
+  if (!st) return set_error(MS_EINVAL, "ms_jit_signature: NULL program");
+  if (n_fields) *n_fields = (int)st->prog.fields.size();
+  if (n_params) *n_params = (int)st->prog.params.size();
+  if (n_profiles) *n_profiles = (int)st->prog.profiles.size();
+  if (n_outputs) *n_outputs = (int)st->prog.out_names.size();
+  return MS_OK;
+}
+
+extern "C" const char* ms_jit_name(const ms_jit_stencil* st, int kind, int index) {
+  if (!st || index < 0) return nullptr;
+  const std::vector<std::string>* v = kind == MS_JIT_FIELD     ? &st->prog.fields
+                                      : kind == MS_JIT_PARAM   ? &st->prog.params
+                                      : kind == MS_JIT_PROFILE ? &st->prog.profiles
+                                      : kind == MS_JIT_OUTPUT  ? &st->prog.out_names
+                                                               : nullptr;
+  if (!v || (size_t)index >= v->size()) return nullptr;
+  return (*v)[index].c_str();
+}
+
+namespace {
+
+int jit_function(ms_jit_stencil* st, hipFunction_t* fn) {
+  int dev = 0;
+  MS_HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(st->mu);
+  auto it = st->mods.find(dev);
+  if (it == st->mods.end()) {
+    hipModule_t m = nullptr;
+    MS_HIP_TRY(hipModuleLoadData(&m, st->code.data()));
+    hipFunction_t f = nullptr;
+    const hipError_t e = hipModuleGetFunction(&f, m, "ms_jit_kernel");
+    if (e != hipSuccess) {
+      (void)hipModuleUnload(m);
+      return set_error(MS_EHIP, "ms_jit_apply: kernel not found: %s", hipGetErrorString(e));
+    }
+    it = st->mods.emplace(dev, std::make_pair(m, f)).first;
+  }
+  *fn = it->second.second;
+  return MS_OK;
+}
+
+template <typename T>
+int jit_launch(ms_jit_stencil* st, const ms_grid& g, const void* const* fields,
+               const double* params, const void* const* profiles, void* const* outputs,
+               hipStream_t s) {
+  const Program& p = st->prog;
+  JitArgs<T> a{};
+  for (size_t q = 0; q < p.fields.size(); ++q) a.in[q] = static_cast<const T*>(fields[q]);
+  for (size_t q = 0; q < p.out_names.size(); ++q) a.out[q] = static_cast<T*>(outputs[q]);
+  for (size_t q = 0; q < p.profiles.size(); ++q) a.prof[q] = static_cast<const T*>(profiles[q]);
+  for (size_t q = 0; q < p.params.size(); ++q) a.prm[q] = (T)params[q];
+  a.sy = g.sy;
+  a.sz = g.sz;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.nz = g.nz;
+  a.tiles_x = (g.nx + 63) / 64;
+  a.tiles_y = (g.ny + 3) / 4;
+  // About 4096 blocks (16 per CU), marches of at least 8 levels.
+  const int64_t t2 = (int64_t)a.tiles_x * a.tiles_y;
+  int64_t chunks = (4096 + t2 - 1) / t2;
+  const int64_t max_chunks = (g.nz + 7) / 8;
+  if (chunks > max_chunks) chunks = max_chunks;
+  if (chunks < 1) chunks = 1;
+  a.zc = (int)((g.nz + chunks - 1) / chunks);
+  chunks = (g.nz + a.zc - 1) / a.zc;
+  const int64_t nb = t2 * chunks;
+  if (nb > 0x7fffffff) return set_error(MS_EUNSUPPORTED, "ms_jit_apply: grid too large");
+  a.nblocks = (int)nb;
+  hipFunction_t fn = nullptr;
+  if (int rc = jit_function(st, &fn)) return rc;
+  void* kargs[] = {&a};
+  MS_HIP_TRY(hipModuleLaunchKernel(fn, (unsigned)nb, 1, 1, 256, 1, 1, 0, s, kargs, nullptr));
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" int ms_jit_apply(ms_jit_stencil* st, const ms_grid* g, const void* const* fields,
+                            int n_fields, const double* params, int n_params,
+                            const void* const* profiles, int n_profiles, void* const* outputs,
+                            int n_outputs, void* stream) {
+  clear_error();
+  if (!st) return set_error(MS_EINVAL, "ms_jit_apply: NULL program");
+  if (int rc = check_grid(g, "ms_jit_apply")) return rc;
+  const Program& p = st->prog;
+  if (n_fields != (int)p.fields.size() || n_params != (int)p.params.size() ||
+      n_profiles != (int)p.profiles.size() || n_outputs != (int)p.out_names.size())
+    return set_error(MS_EINVAL,
+                     "ms_jit_apply: the program takes %zu fields, %zu params, %zu profiles, "
+                     "%zu outputs",
+                     p.fields.size(), p.params.size(), p.profiles.size(), p.out_names.size());
+  if ((n_fields && !fields) || (n_params && !params) || (n_profiles && !profiles) || !outputs)
+    return set_error(MS_EINVAL, "ms_jit_apply: missing argument array");
+  for (int q = 0; q < n_fields; ++q)
+    if (!fields[q]) return set_error(MS_EINVAL, "ms_jit_apply: field %d is NULL", q);
+  for (int q = 0; q < n_profiles; ++q)
+    if (!profiles[q]) return set_error(MS_EINVAL, "ms_jit_apply: profile %d is NULL", q);
+  const size_t esz = st->dtype == MS_F64 ? 8 : 4;
+  const size_t fbytes = (size_t)field_span(*g) * esz, pbytes = (size_t)g->nz * esz;
+  for (int r = 0; r < n_outputs; ++r) {
+    if (!outputs[r]) return set_error(MS_EINVAL, "ms_jit_apply: output %d is NULL", r);
+    for (int q = 0; q < n_fields; ++q)
+      if (overlaps(outputs[r], fbytes, fields[q], fbytes))
+        return set_error(MS_EINVAL, "ms_jit_apply: output %d overlaps field %d", r, q);
+    for (int q = 0; q < n_profiles; ++q)
+      if (overlaps(outputs[r], fbytes, profiles[q], pbytes))
+        return set_error(MS_EINVAL, "ms_jit_apply: output %d overlaps profile %d", r, q);
+    for (int q = 0; q < r; ++q)
+      if (overlaps(outputs[r], fbytes, outputs[q], fbytes))
+        return set_error(MS_EINVAL, "ms_jit_apply: outputs %d and %d overlap", q, r);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (st->dtype == MS_F64) return jit_launch<double>(st, *g, fields, params, profiles, outputs, s);
+  return jit_launch<float>(st, *g, fields, params, profiles, outputs, s);
+}
