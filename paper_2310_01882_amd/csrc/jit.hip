@@ -343,8 +343,10 @@ struct Codegen {
     return "";
   }
 
+  std::set<int> prof_used;
+
   std::string run() {
-    std::set<int> prm_used, prof_used;
+    std::set<int> prm_used;
     for (const Node& n : p.nodes) {
       if (n.kind == Node::FIELD) {
         Column& c = cols[column(n.idx, n.dx, n.dy)];
@@ -387,28 +389,42 @@ struct Codegen {
       o += "  T n" + cs + "a = c" + cs + "[lev(z0 + " + std::to_string(q.dmax + 1) + ")];\n";
       o += "  T n" + cs + "b = c" + cs + "[lev(z0 + " + std::to_string(q.dmax + 2) + ")];\n";
     }
-    o += "  for (int k = z0; k < z1; ++k) {\n";
-    for (int k : prof_used)
-      o += "    const T pf" + std::to_string(k) + " = a.prof[" + std::to_string(k) + "][k];\n";
+    // Two steps per trip, so the two prefetch registers of a column swap
+    // roles instead of being copied: a copy of a register whose load is
+    // still in flight would wait for that load.
+    o += "  for (int k = z0; k < z1; k += 2) {\n";
+    o += step("k", 'a', "    ");
+    o += "    if (k + 1 >= z1) break;\n";
+    o += "    {\n      const int k1 = k + 1;\n";
+    o += step("k1", 'b', "      ");
+    o += "    }\n";
+    o += "  }\n}\n";
+    return o;
+  }
+
+  // One z step at level `k`: profiles, lets, outputs and their stores, then
+  // the queue rotation; prefetch register `ph` takes the level two steps on.
+  std::string step(const std::string& k, char ph, const std::string& in) {
+    std::string o;
+    for (int q = 0; q < (int)p.profiles.size(); ++q)
+      if (prof_used.count(q))
+        o += in + "const T pf" + std::to_string(q) + " = a.prof[" + std::to_string(q) + "][" + k + "];\n";
     for (size_t l = 0; l < p.let_root.size(); ++l)
-      o += "    const T t" + std::to_string(l) + " = " + emit(p.let_root[l]) + ";\n";
+      o += in + "const T t" + std::to_string(l) + " = " + emit(p.let_root[l]) + ";\n";
     for (size_t r = 0; r < p.out_root.size(); ++r) {
       const std::string rs = std::to_string(r);
-      o += "    const T o" + rs + " = " + emit(p.out_root[r]) + ";\n";
-      o += "    __builtin_nontemporal_store(o" + rs + ", a.out[" + rs +
-           "] + (long long)(k + 1) * sz + base);\n";
+      o += in + "const T o" + rs + " = " + emit(p.out_root[r]) + ";\n";
+      o += in + "__builtin_nontemporal_store(o" + rs + ", a.out[" + rs + "] + (long long)(" + k +
+           " + 1) * sz + base);\n";
     }
-    // rotate the column queues; the level two steps ahead is loaded now
     for (size_t c = 0; c < cols.size(); ++c) {
       const Column& q = cols[c];
-      const std::string cs = std::to_string(c);
+      const std::string cs = std::to_string(c), reg = "n" + cs + ph;
       for (int d = q.dmin; d < q.dmax; ++d)
-        o += "    " + qname((int)c, d) + " = " + qname((int)c, d + 1) + ";\n";
-      o += "    " + qname((int)c, q.dmax) + " = n" + cs + "a;\n";
-      o += "    n" + cs + "a = n" + cs + "b;\n";
-      o += "    n" + cs + "b = c" + cs + "[lev(k + " + std::to_string(q.dmax + 3) + ")];\n";
+        o += in + "" + qname((int)c, d) + " = " + qname((int)c, d + 1) + ";\n";
+      o += in + "" + qname((int)c, q.dmax) + " = " + reg + ";\n";
+      o += in + "" + reg + " = c" + cs + "[lev(" + k + " + " + std::to_string(q.dmax + 3) + ")];\n";
     }
-    o += "  }\n}\n";
     return o;
   }
 };
@@ -577,9 +593,12 @@ int jit_launch(ms_jit_stencil* st, const ms_grid& g, const void* const* fields,
   a.nz = g.nz;
   a.tiles_x = (g.nx + 63) / 64;
   a.tiles_y = (g.ny + 3) / 4;
-  // About 4096 blocks (16 per CU), marches of at least 8 levels.
+  // About 4096 blocks (16 per CU), marches of at least 8 levels;
+  // MS_JIT_BLOCKS overrides the target for tuning.
+  const char* ev = getenv("MS_JIT_BLOCKS");
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 4096;
   const int64_t t2 = (int64_t)a.tiles_x * a.tiles_y;
-  int64_t chunks = (4096 + t2 - 1) / t2;
+  int64_t chunks = (want + t2 - 1) / t2;
   const int64_t max_chunks = (g.nz + 7) / 8;
   if (chunks > max_chunks) chunks = max_chunks;
   if (chunks < 1) chunks = 1;

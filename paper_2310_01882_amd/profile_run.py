@@ -4,6 +4,7 @@
     python -m paper_2310_01882_amd.profile_run advect  [--passes N]
     python -m paper_2310_01882_amd.profile_run batched
     python -m paper_2310_01882_amd.profile_run cnn     [--steps N]
+    python -m paper_2310_01882_amd.profile_run jit     [--program jacobi|advection] [--passes N]
     python -m paper_2310_01882_amd.profile_run copy    [--mib M]
 
 `sweep` runs N sweeps of the 512^3 Poisson workload (8 Gaussian sources,
@@ -13,7 +14,9 @@ sweeps instead). `advect` runs N passes of the
 512 x 512 x 256 advection term. `batched` autotunes and then solves the
 benchmark's batch (64 instances, sizes log-uniform in [32, 256], seed 4,
 FP32-refined to 1e-8) once. `cnn` runs N training steps (forward, backward,
-Adam) of the warm-start network on a 128^3 instance. `copy` is the
+Adam) of the warm-start network on a 128^3 instance. `jit` compiles the
+Jacobi (or advection) program of the stencil-program language and runs it N
+times on the sweep (or advection) input. `copy` is the
 calibration kernel of known size: one device-to-device tensor copy of M MiB
 (reads M MiB, writes M MiB), used to scale the FETCH_SIZE / WRITE_SIZE
 counters.
@@ -32,7 +35,7 @@ if ROOT not in sys.path:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["sweep", "advect", "batched", "cnn", "copy"])
+    ap.add_argument("what", choices=["sweep", "advect", "batched", "cnn", "copy", "jit"])
     ap.add_argument("--tb", type=int, default=1, choices=[1, 2])
     ap.add_argument("--rb", action="store_true")
     ap.add_argument("--steps", type=int, default=5)
@@ -40,6 +43,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=10)
     ap.add_argument("--passes", type=int, default=5)
     ap.add_argument("--mib", type=int, default=1024)
+    ap.add_argument("--program", default="jacobi", choices=["jacobi", "advection"])
     ap.add_argument("--n", type=int, default=512)
     args = ap.parse_args()
 
@@ -94,6 +98,29 @@ def main():
             net.train_step(u, f, target)
         torch.cuda.synchronize()
         print(f"{args.steps} warm-start training steps at {n}^3 done", flush=True)
+        return
+    if args.what == "jit":
+        from paper_2310_01882_amd.programs import ADVECTION, JACOBI
+        if args.program == "jacobi":
+            n = args.n
+            f = ms.field_from(synth.gaussian_sources(n, n, n, 8, 1))
+            u = ms.alloc_field(n, n, n)
+            o = ms.alloc_field(n, n, n)
+            jac = ms.JitStencil(JACOBI)
+            for _ in range(args.passes):
+                jac.apply([u, f], [o])
+            torch.cuda.synchronize()
+            print(f"{args.passes} compiled Jacobi passes at {n}^3 done", flush=True)
+            return
+        nx, ny, nz = 512, 512, 256
+        u, v, w = (ms.field_from(a) for a in synth.velocity_fields(nx, ny, nz, 2))
+        t1, t2 = (torch.from_numpy(a).cuda() for a in synth.tzc_arrays(nz, 3))
+        outs = [ms.alloc_field(nx, ny, nz) for _ in range(3)]
+        adv = ms.JitStencil(ADVECTION)
+        for _ in range(args.passes):
+            adv.apply([u, v, w], outs, [0.25, 0.25], [t1, t2])
+        torch.cuda.synchronize()
+        print(f"{args.passes} compiled advection passes done", flush=True)
         return
     nx, ny, nz = 512, 512, 256
     u, v, w = (ms.field_from(a) for a in synth.velocity_fields(nx, ny, nz, 2))

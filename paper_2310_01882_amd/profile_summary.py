@@ -31,6 +31,7 @@ SOURCES = {
     "advect": ["advect.hip"],
     "batched": ["batched.hip", "ms_internal.hpp"],
     "conv": ["cnn.hip"],
+    "jit": ["jit.hip", "programs.py"],
 }
 
 
@@ -38,7 +39,10 @@ def source_hash(key: str) -> str:
     names = SOURCES[next((k for k in SOURCES if key.startswith(k)), "jacobi7")]
     h = hashlib.sha256()
     for n in names:
-        with open(os.path.join(HERE, "csrc", n), "rb") as fh:
+        path = os.path.join(HERE, "csrc", n)
+        if not os.path.exists(path):
+            path = os.path.join(HERE, n)
+        with open(path, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
