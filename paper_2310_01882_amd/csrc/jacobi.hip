@@ -714,6 +714,187 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
   }
 }
 
+// ------------------------------- two-stage pass, one column per lane
+
+// The same two stages (two Jacobi sweeps, or one red-black Gauss-Seidel
+// sweep) with the work laid out so that almost every neighbour is a
+// register. A block of kTwWaves waves covers a staging region of 64 columns
+// (one per lane) x kTwWaves * kTwRows rows; a lane keeps its column's rows in
+// registers across three z levels. x neighbours come from the adjacent lane
+// (DPP moves), y neighbours from the thread's own rows, z neighbours from
+// its level queue; only the rows just above and below a wave's group cross
+// waves, through LDS (two rows per wave and level, one barrier per level).
+// Stage A (u_k -> h) covers columns 1..62 and rows 1..R-2 of the region,
+// stage B (h -> output) columns 2..61 and rows 2..R-3 (the 60-wide output
+// tile), one level behind stage A. f is loaded once per cell and kept for
+// stage B. The per-cell arithmetic is the single sweep's, so the results
+// are bit-identical to the other kernels.
+constexpr int kTwWaves = 8, kTwRows = 3;  // 121 VGPRs (FP64): four waves per SIMD
+constexpr int kTwThreads = 64 * kTwWaves;
+constexpr int kTwRegionY = kTwWaves * kTwRows;  // 32 rows
+constexpr int kTwTileX = 60, kTwTileY = kTwRegionY - 4;
+
+template <typename T, bool HAS_F, bool RB>
+__global__ __launch_bounds__(kTwThreads) __attribute__((amdgpu_waves_per_eu(4))) void sweep_tbw_kernel(SweepK<T> a) {
+  __shared__ T xu[2][kTwWaves][2][64];  // u_k rows 0 and R-1 of every wave group
+  __shared__ T xh[2][kTwWaves][2][64];  // h rows 0 and R-1
+  __shared__ double red[kTwWaves];
+  __shared__ int s_done;
+
+  const int64_t L = (a.ctl ? a.ctl->base : 0) + a.k_off;
+  const int64_t k0 = RB ? L : 2 * L;  // iterate read by this launch
+  if (blockIdx.x == 0 && L >= 1 && (a.hist || a.ctl)) {
+#pragma unroll
+    for (int d = RB ? 1 : 2; d >= 1; --d) {
+      if (!a.ctl || a.ctl->done == RUNNING) {
+        const double t = sum_partials(a.partials + ((k0 - d) & 3) * (int64_t)kMaxBlocks,
+                                      a.nblocks, red);
+        if (threadIdx.x == 0) judge(a.ctl, a.hist, k0 - d, sqrt(t));
+        __syncthreads();
+      }
+    }
+  }
+  if (a.ctl) {
+    if (threadIdx.x == 0) s_done = a.ctl->done;
+    __syncthreads();
+    if (s_done != RUNNING) return;
+  }
+
+  const int tile = xcd_tile(blockIdx.x, a.nblocks);
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int tzi = rest / a.tiles_y;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int z0 = tzi * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
+  const int64_t sy = a.sy, sz = a.sz;
+  const T* __restrict__ src = a.buf[L % a.nbuf];
+  T* __restrict__ dst = a.buf[(L + 1) % a.nbuf];
+  const T* __restrict__ f = a.f;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = txi * kTwTileX - 2 + lane;            // this lane's column
+  const int jr0 = tyi * kTwTileY - 2 + w * kTwRows;   // its first row
+  const int wup = min(w + 1, kTwWaves - 1), wdn = max(w - 1, 0);
+  const int ic = min(max(i, -1), nx);
+  const bool colA = lane >= 1 && lane <= 62, colB = lane >= 2 && lane <= 61;
+  const bool xin = i >= 0 && i < nx;
+  int64_t off[kTwRows];
+  bool inA[kTwRows], outB[kTwRows];
+#pragma unroll
+  for (int s = 0; s < kTwRows; ++s) {
+    const int j = jr0 + s, row = w * kTwRows + s;
+    off[s] = (int64_t)(min(max(j, -1), ny) + 1) * sy + (ic + 1);
+    const bool yin = j >= 0 && j < ny;
+    inA[s] = colA && row >= 1 && row <= kTwRegionY - 2 && xin && yin;
+    outB[s] = colB && row >= 2 && row <= kTwRegionY - 3 && xin && yin;
+  }
+  auto plane = [&](int z) { return (int64_t)(min(max(z, -1), nz) + 1) * sz; };
+  auto load_u = [&](T (&r)[kTwRows], int z) {
+    const int64_t p = plane(z);
+#pragma unroll
+    for (int s = 0; s < kTwRows; ++s) r[s] = src[p + off[s]];
+  };
+  auto load_f = [&](T (&r)[kTwRows], int z) {
+    const int64_t p = plane(z);
+#pragma unroll
+    for (int s = 0; s < kTwRows; ++s) r[s] = HAS_F ? f[p + off[s]] : T(0);
+  };
+  // colour parity of (i + j) for row 0 (RB): red cells have i + j + z even
+  const int par0 = (i + jr0) & 1;
+
+  T um[kTwRows], uc[kTwRows], up[kTwRows];  // u_k at z-1, z, z+1
+  T hm2[kTwRows], hm1[kTwRows];             // h at z-2, z-1
+  T fa[kTwRows], fb[kTwRows];               // f at z (stage A), z-1 (stage B)
+  T pu0[kTwRows], pu1[kTwRows], pf0[kTwRows], pf1[kTwRows];
+  load_u(um, z0 - 2);
+  load_u(uc, z0 - 1);
+  load_u(up, z0);
+  load_u(pu0, z0 + 1);
+  load_u(pu1, z0 + 2);
+  load_f(fa, z0 - 1);
+  load_f(pf0, z0);
+  load_f(pf1, z0 + 1);
+#pragma unroll
+  for (int s = 0; s < kTwRows; ++s) {
+    hm2[s] = T(0);
+    hm1[s] = T(0);
+    fb[s] = T(0);
+  }
+
+  double acc_a = 0.0, acc_b = 0.0;
+  const T c6 = C6<T>::v();
+  // One level: stage A at z (u_k -> h(z)), stage B at z - 1 (h -> output).
+  // pu / pf hold u_k(z+2) / f(z+1) on entry and take u_k(z+4) / f(z+3).
+  auto step = [&](int z, int b, T (&pu)[kTwRows], T (&pf)[kTwRows]) {
+    // publish the group's edge rows of u_k(z) and h(z-1)
+    xu[b][w][0][lane] = uc[0];
+    xu[b][w][1][lane] = uc[kTwRows - 1];
+    xh[b][w][0][lane] = hm1[0];
+    xh[b][w][1][lane] = hm1[kTwRows - 1];
+    __syncthreads();
+    const bool zA = z >= 0 && z < nz, zres = z >= z0 && z < z1;
+    T hn[kTwRows];
+#pragma unroll
+    for (int s = 0; s < kTwRows; ++s) {
+      const T xp = lane_from_right(uc[s], uc[s]), xm = lane_from_left(uc[s], uc[s]);
+      const T yp = s < kTwRows - 1 ? uc[s + 1] : xu[b][wup][0][lane];
+      const T ym = s > 0 ? uc[s - 1] : xu[b][wdn][1][lane];
+      const T sum = ((((xp + xm) + yp) + ym) + up[s]) + um[s];
+      const bool upd = !RB || ((par0 + s + z) & 1) == 0;
+      hn[s] = inA[s] && zA && upd ? (HAS_F ? (sum - fa[s]) * c6 : sum * c6) : uc[s];
+      if (outB[s] && zres) {
+        const double r = cell_residual(xp, xm, yp, ym, up[s], um[s], uc[s], fa[s], HAS_F);
+        acc_a += r * r;
+      }
+    }
+    const int zb = z - 1;
+    if (zb >= z0 && zb < z1) {
+      const int64_t pb = (int64_t)(zb + 1) * sz;
+#pragma unroll
+      for (int s = 0; s < kTwRows; ++s) {
+        const T xp = lane_from_right(hm1[s], hm1[s]), xm = lane_from_left(hm1[s], hm1[s]);
+        const T yp = s < kTwRows - 1 ? hm1[s + 1] : xh[b][wup][0][lane];
+        const T ym = s > 0 ? hm1[s - 1] : xh[b][wdn][1][lane];
+        const T sum = ((((xp + xm) + yp) + ym) + hn[s]) + hm2[s];
+        const bool upd = !RB || ((par0 + s + zb) & 1) == 1;
+        const T v = upd ? (HAS_F ? (sum - fb[s]) * c6 : sum * c6) : hm1[s];
+        if (outB[s]) {
+          __builtin_nontemporal_store(v, dst + pb + off[s]);
+          if (!RB) {
+            const double r = cell_residual(xp, xm, yp, ym, hn[s], hm2[s], hm1[s], fb[s], HAS_F);
+            acc_b += r * r;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < kTwRows; ++s) {
+      um[s] = uc[s];
+      uc[s] = up[s];
+      up[s] = pu[s];
+      hm2[s] = hm1[s];
+      hm1[s] = hn[s];
+      fb[s] = fa[s];
+      fa[s] = pf[s];
+    }
+    load_u(pu, z + 4);
+    load_f(pf, z + 3);
+  };
+  for (int z = z0 - 1; z <= z1; z += 2) {
+    step(z, 0, pu0, pf0);
+    if (z + 1 > z1) break;
+    step(z + 1, 1, pu1, pf1);
+  }
+
+  const double ta = block_sum(acc_a, red);
+  const double tb = RB ? 0.0 : block_sum(acc_b, red);
+  if (threadIdx.x == 0) {
+    a.partials[(int64_t)(k0 & 3) * kMaxBlocks + blockIdx.x] = ta;
+    if (!RB) a.partials[(int64_t)((k0 + 1) & 3) * kMaxBlocks + blockIdx.x] = tb;
+  }
+}
+
 template <typename T, bool HAS_F, bool WRITE, bool ZERO_INT>
 int launch_lds(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
   const dim3 grid(geo.nblocks), block(kThreads);
@@ -819,20 +1000,35 @@ int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
 
 int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 
+// Variants of the two-stage pass: kTbLds (LDS-staged 64 x 8 tiles) and
+// kTbColumns (one column per lane). Measured: FP64 within 1% of each other
+// at 512^3 and the LDS tiles 15% faster at 128^3 (less padding: 64 x 8
+// tiles against 60 x 20); FP32 16-20% faster with columns at both sizes.
+// Default: LDS tiles for FP64, columns for FP32; MS_TB_VARIANT=0 or 2
+// forces one.
+constexpr int kTbLds = 0, kTbColumns = 2;
+
 SweepGeom tb2_geom(const ms_grid& g, int dtype) {
   SweepGeom s{};
-  s.variant = kVariantLds;
+  const char* ev_var = getenv("MS_TB_VARIANT");
+  s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : kTbColumns)
+                     : (dtype == MS_F64 ? kTbLds : kTbColumns);
   s.vec = 1;
   s.wx = 1;
   s.rows = 2;
-  s.tiles_x = (g.nx + kTbX - 1) / kTbX;
-  s.tiles_y = (g.ny + kTbY - 1) / kTbY;
+  const bool cols = s.variant == kTbColumns;
+  s.tiles_x = cols ? (g.nx + kTwTileX - 1) / kTwTileX : (g.nx + kTbX - 1) / kTbX;
+  s.tiles_y = cols ? (g.ny + kTwTileY - 1) / kTwTileY : (g.ny + kTbY - 1) / kTbY;
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
-  // Block targets measured at 512^3 (three FP64 / four FP32 blocks are
-  // resident per CU): 2048 for FP64, 1024 for FP32; marches of at least 8
-  // levels. MS_TB_BLOCKS overrides the target for tuning.
+  // Block targets measured at 512^3. LDS tiles: 2048 (FP64) / 1024 (FP32)
+  // blocks of 256 threads, three or four resident per CU. Columns: 4096
+  // blocks of 512 threads (two resident per CU; 256 to 4096 were within 3%
+  // for FP64, 4096 best for FP32). Marches of at least 8 levels.
+  // MS_TB_BLOCKS overrides the target for tuning.
   const char* ev = getenv("MS_TB_BLOCKS");
-  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : (dtype == MS_F64 ? 2048 : 1024);
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev)
+                       : cols              ? 4096
+                                           : (dtype == MS_F64 ? 2048 : 1024);
   int64_t chunks = (want + tiles2d - 1) / tiles2d;
   int zc = (int)((g.nz + chunks - 1) / chunks);
   if (zc < 8) zc = 8;
@@ -858,9 +1054,14 @@ void launch_tb2_typed(const ms_grid& g, const SweepGeom& geo, void* const bufs[3
   for (int q = 0; q < 3; ++q) a.buf[q] = static_cast<T*>(bufs[q]);
   a.f = static_cast<const T*>(f);
   a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
-  const dim3 grid(geo.nblocks), block(kThreads);
-  if (f) hipLaunchKernelGGL((sweep_tb2_kernel<T, true, RB>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((sweep_tb2_kernel<T, false, RB>), grid, block, 0, s, a);
+  const dim3 grid(geo.nblocks);
+  if (geo.variant == kTbColumns) {
+    if (f) hipLaunchKernelGGL((sweep_tbw_kernel<T, true, RB>), grid, dim3(kTwThreads), 0, s, a);
+    else hipLaunchKernelGGL((sweep_tbw_kernel<T, false, RB>), grid, dim3(kTwThreads), 0, s, a);
+  } else {
+    if (f) hipLaunchKernelGGL((sweep_tb2_kernel<T, true, RB>), grid, dim3(kThreads), 0, s, a);
+    else hipLaunchKernelGGL((sweep_tb2_kernel<T, false, RB>), grid, dim3(kThreads), 0, s, a);
+  }
 }
 
 template <bool RB>

@@ -188,13 +188,18 @@ def test_every_tile_geometry_is_bit_exact(geom, dtype, monkeypatch):
         np.testing.assert_allclose(host(res)[:3], hist, rtol=NORM_RTOL)
 
 
+TB_VARIANTS = {"columns": "2", "lds": "0"}
+
+
+@pytest.mark.parametrize("variant", list(TB_VARIANTS))
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("dims", [(64, 8, 9), (130, 37, 11), (5, 3, 2), (1, 1, 1), (65, 17, 40),
-                                  (200, 9, 3)])
-def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype):
-    """Two sweeps fused per pass: the same fields and norms as the oracle's
-    plain sweeps, for even and odd sweep counts."""
-    note(f"case: tb2 {dims} {dtype.__name__}")
+                                  (200, 9, 3), (61, 21, 10), (121, 41, 17)])
+def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype, variant, monkeypatch):
+    """Two sweeps fused per pass, in both kernel layouts: the same fields and
+    norms as the oracle's plain sweeps, for even and odd sweep counts."""
+    monkeypatch.setenv("MS_TB_VARIANT", TB_VARIANTS[variant])
+    note(f"case: tb2 {variant} {dims} {dtype.__name__}")
     u, f = _problem(*dims, seed=3 * dims[0] + dims[2])
     u, f = u.astype(dtype), f.astype(dtype)
     for n in (1, 2, 3, 4, 7):
@@ -215,8 +220,10 @@ def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype):
         np.testing.assert_allclose(host(res), hist, rtol=NORM_RTOL)
 
 
-def test_temporal_blocking_at_benchmark_size():
-    note("case: tb2 512^3 x 4 sweeps vs plain")
+@pytest.mark.parametrize("variant", list(TB_VARIANTS))
+def test_temporal_blocking_at_benchmark_size(variant, monkeypatch):
+    monkeypatch.setenv("MS_TB_VARIANT", TB_VARIANTS[variant])
+    note(f"case: tb2 {variant} 512^3 x 4 sweeps vs plain")
     n = 512
     f = ms.field_from(synth.gaussian_sources(n, n, n, 8, 1))
     outs = []

@@ -39,11 +39,16 @@ def _run(u, f, n, dtype=np.float64, pad=(0, 0)):
     return host(out), host(res)
 
 
+TB_VARIANTS = {"columns": "2", "lds": "0"}
+
+
+@pytest.mark.parametrize("variant", list(TB_VARIANTS))
 @pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 4), (64, 8, 8), (65, 17, 9), (130, 9, 20),
-                                  (63, 15, 7), (200, 3, 70), (3, 2, 41)])
+                                  (63, 15, 7), (200, 3, 70), (3, 2, 41), (61, 21, 10)])
 @pytest.mark.parametrize("with_f", [True, False])
-def test_sweeps_bit_exact_on_ragged_grids(dims, with_f):
-    note(f"case: rbgs sweeps {dims} f={with_f}")
+def test_sweeps_bit_exact_on_ragged_grids(dims, with_f, variant, monkeypatch):
+    monkeypatch.setenv("MS_TB_VARIANT", TB_VARIANTS[variant])
+    note(f"case: rbgs sweeps {variant} {dims} f={with_f}")
     u, f = _problem(*dims, seed=sum(dims) + 3, with_f=with_f)
     for n in (0, 1, 2, 5):
         got, res = _run(u, f, n)
