@@ -10,13 +10,17 @@
 //   let s = ((((u[1,0,0] + u[-1,0,0]) + u[0,1,0]) + u[0,-1,0]) + u[0,0,1]) + u[0,0,-1];
 //   out v = (s - f) * c;
 //
-// Generated kernel: a block owns a 64 x 4 (x, y) tile and marches a
-// z-chunk; every distinct (field, dx, dy) column the body reads is a queue
-// of registers over its z offsets, so each column loads one new level per
-// step (prefetched one step ahead, from a level clamped into the halo so the
-// load is unconditional). Every operation of the body is emitted fully
-// parenthesised in source order and the program is compiled without
-// contraction, so each value is rounded as the text says.
+// Generated kernels (one module, two entry points): a block owns a
+// 64V x 4 (x, y) tile and marches a z-chunk. The vector kernel (V = 2 FP64
+// / 4 FP32 cells per lane, whole tiles of fields aligned to V cells) keeps
+// one register queue per (field, dy) row over its z offsets and takes x
+// neighbours from the adjacent lanes (DPP); the scalar kernel (V = 1, the
+// remaining columns or unaligned fields) keeps one queue per (field, dx, dy)
+// column. Each queue loads one new level per step, two steps ahead, from a
+// level clamped into the halo so the load is unconditional. Every operation
+// of the body is emitted fully parenthesised in source order and the
+// program is compiled without contraction, so each value is rounded as the
+// text says.
 #include "ms_internal.hpp"
 
 #include <hip/hiprtc.h>
@@ -345,6 +349,7 @@ struct Codegen {
 
   std::set<int> prof_used;
 
+  // The scalar kernel: one x cell per lane, columns x0 .. nx-1.
   std::string run() {
     std::set<int> prm_used;
     for (const Node& n : p.nodes) {
@@ -359,18 +364,13 @@ struct Codegen {
       }
     }
     std::string o;
-    o += dtype == MS_F64 ? "typedef double T;\n" : "typedef float T;\n";
-    o += "struct JitArgs {\n"
-         "  const T* in[8];\n  T* out[4];\n  const T* prof[4];\n  T prm[8];\n"
-         "  long long sy, sz;\n  int nx, ny, nz, zc;\n  int tiles_x, tiles_y, nblocks, pad;\n"
-         "};\n";
-    o += "extern \"C\" __global__ __launch_bounds__(256) void ms_jit_kernel(JitArgs a) {\n"
+    o += "extern \"C\" __global__ __launch_bounds__(256) void ms_jit_kernel_s(JitArgs a) {\n"
          "  const int b = blockIdx.x, nb = a.nblocks;\n"
          "  const int xcd = b & 7, slot = b >> 3, qn = nb >> 3, rn = nb & 7;\n"
          "  const int tile = xcd * qn + (xcd < rn ? xcd : rn) + slot;\n"
          "  const int txi = tile % a.tiles_x, rest = tile / a.tiles_x;\n"
          "  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;\n"
-         "  const int i = txi * 64 + (int)(threadIdx.x & 63);\n"
+         "  const int i = a.x0 + txi * 64 + (int)(threadIdx.x & 63);\n"
          "  const int j = tyi * 4 + (int)(threadIdx.x >> 6);\n"
          "  if (i >= a.nx || j >= a.ny) return;\n"
          "  const int nz = a.nz, z0 = tzi * a.zc;\n"
@@ -429,6 +429,205 @@ struct Codegen {
   }
 };
 
+// The vector kernel: V consecutive x cells per lane (one 16-byte load per
+// row and level), whole 64V-column tiles only. Accesses with dx = -1 / +1
+// take the neighbour lane's last / first element through a DPP move; lanes
+// 0 and 63 take the cell beyond the wave from one extra load per row and
+// level (every other lane loads its own first cell there, a cache hit).
+struct VecCodegen {
+  const Program& p;
+  int dtype, V;
+  struct Group {
+    int field, dy, dmin, dmax;
+    bool left, right;
+  };
+  std::vector<Group> groups;
+  std::map<std::pair<int, int>, int> group_of;
+  std::set<int> prm_used, prof_used;
+
+  static std::string gname(int g, int d) {
+    return "g" + std::to_string(g) + (d < 0 ? "m" : "p") + std::to_string(d < 0 ? -d : d);
+  }
+  static std::string ename(int g, int d) { return "e" + gname(g, d).substr(1); }
+
+  std::string emit(int id, int v) {
+    const Node& n = p.nodes[id];
+    const std::string vs = std::to_string(v);
+    switch (n.kind) {
+      case Node::NUM: return "((T)" + hex_literal(n.num, dtype) + ")";
+      case Node::FIELD: {
+        const int g = group_of.at(std::make_pair(n.idx, n.dy));
+        const std::string q = gname(g, n.dz);
+        if (n.dx == 0) return q + "[" + vs + "]";
+        if (n.dx < 0) return v > 0 ? q + "[" + std::to_string(v - 1) + "]" : "L" + q.substr(1);
+        return v < V - 1 ? q + "[" + std::to_string(v + 1) + "]" : "R" + q.substr(1);
+      }
+      case Node::PARAM: return "prm" + std::to_string(n.idx);
+      case Node::PROFILE: return "pf" + std::to_string(n.idx);
+      case Node::LET: return "t" + std::to_string(n.idx) + "_" + vs;
+      case Node::NEG: return "(-" + emit(n.a, v) + ")";
+      case Node::ADD: return "(" + emit(n.a, v) + " + " + emit(n.b, v) + ")";
+      case Node::SUB: return "(" + emit(n.a, v) + " - " + emit(n.b, v) + ")";
+      case Node::MUL: return "(" + emit(n.a, v) + " * " + emit(n.b, v) + ")";
+      case Node::DIV: return "(" + emit(n.a, v) + " / " + emit(n.b, v) + ")";
+    }
+    return "";
+  }
+
+  std::string step(const std::string& k, char ph, const std::string& in) {
+    std::string o;
+    for (int q : prof_used)
+      o += in + "const T pf" + std::to_string(q) + " = a.prof[" + std::to_string(q) + "][" + k + "];\n";
+    // neighbour-lane values for the x offsets
+    std::set<std::pair<int, int>> lused, rused;
+    for (const Node& n : p.nodes)
+      if (n.kind == Node::FIELD && n.dx != 0) {
+        const int g = group_of.at(std::make_pair(n.idx, n.dy));
+        (n.dx < 0 ? lused : rused).insert(std::make_pair(g, n.dz));
+      }
+    for (auto gd : lused)
+      o += in + "const T L" + gname(gd.first, gd.second).substr(1) + " = ms_from_left(" +
+           ename(gd.first, gd.second) + ", " + gname(gd.first, gd.second) + "[" +
+           std::to_string(V - 1) + "]);\n";
+    for (auto gd : rused)
+      o += in + "const T R" + gname(gd.first, gd.second).substr(1) + " = ms_from_right(" +
+           ename(gd.first, gd.second) + ", " + gname(gd.first, gd.second) + "[0]);\n";
+    for (size_t l = 0; l < p.let_root.size(); ++l)
+      for (int v = 0; v < V; ++v)
+        o += in + "const T t" + std::to_string(l) + "_" + std::to_string(v) + " = " +
+             emit(p.let_root[l], v) + ";\n";
+    for (size_t r = 0; r < p.out_root.size(); ++r) {
+      const std::string rs = std::to_string(r);
+      o += in + "{\n" + in + "  TV ov;\n";
+      for (int v = 0; v < V; ++v)
+        o += in + "  ov[" + std::to_string(v) + "] = " + emit(p.out_root[r], v) + ";\n";
+      o += in + "  __builtin_nontemporal_store(ov, (TV*)(a.out[" + rs + "] + (long long)(" + k +
+           " + 1) * sz + base));\n" + in + "}\n";
+    }
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const Group& q = groups[g];
+      const std::string gs = std::to_string(g), reg = std::string(1, ph);
+      const bool edge = q.left || q.right;
+      for (int d = q.dmin; d < q.dmax; ++d) {
+        o += in + gname((int)g, d) + " = " + gname((int)g, d + 1) + ";\n";
+        if (edge) o += in + ename((int)g, d) + " = " + ename((int)g, d + 1) + ";\n";
+      }
+      o += in + gname((int)g, q.dmax) + " = n" + gs + reg + ";\n";
+      o += in + "n" + gs + reg + " = *(const TV*)(c" + gs + " + lev(" + k + " + " +
+           std::to_string(q.dmax + 3) + "));\n";
+      if (edge) {
+        o += in + ename((int)g, q.dmax) + " = m" + gs + reg + ";\n";
+        o += in + "m" + gs + reg + " = c" + gs + "[lev(" + k + " + " + std::to_string(q.dmax + 3) +
+             ") + eoff];\n";
+      }
+    }
+    return o;
+  }
+
+  std::string run() {
+    for (const Node& n : p.nodes) {
+      if (n.kind == Node::FIELD) {
+        auto key = std::make_pair(n.idx, n.dy);
+        if (!group_of.count(key)) {
+          group_of[key] = (int)groups.size();
+          groups.push_back({n.idx, n.dy, 2, -2, false, false});
+        }
+        Group& g = groups[group_of[key]];
+        g.dmin = std::min(g.dmin, n.dz);
+        g.dmax = std::max(g.dmax, n.dz);
+        if (n.dx < 0) g.left = true;
+        if (n.dx > 0) g.right = true;
+      } else if (n.kind == Node::PARAM) {
+        prm_used.insert(n.idx);
+      } else if (n.kind == Node::PROFILE) {
+        prof_used.insert(n.idx);
+      }
+    }
+    const std::string Vs = std::to_string(V);
+    std::string o = "typedef T TV __attribute__((ext_vector_type(" + Vs + ")));\n";
+    o += "extern \"C\" __global__ __launch_bounds__(256) void ms_jit_kernel_v(JitArgs a) {\n"
+         "  const int b = blockIdx.x, nb = a.nblocks;\n"
+         "  const int xcd = b & 7, slot = b >> 3, qn = nb >> 3, rn = nb & 7;\n"
+         "  const int tile = xcd * qn + (xcd < rn ? xcd : rn) + slot;\n"
+         "  const int txi = tile % a.tiles_x, rest = tile / a.tiles_x;\n"
+         "  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;\n"
+         "  const int lane = (int)(threadIdx.x & 63);\n"
+         "  const int i = txi * " + std::to_string(64 * V) + " + " + Vs + " * lane;\n"
+         "  const int j = tyi * 4 + (int)(threadIdx.x >> 6);\n"
+         "  if (j >= a.ny) return;  // whole waves only: the DPP moves stay within a wave\n"
+         "  const int eoff = lane == 0 ? -1 : (lane == 63 ? " + Vs + " : 0);\n"
+         "  const int nz = a.nz, z0 = tzi * a.zc;\n"
+         "  const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;\n"
+         "  const long long sy = a.sy, sz = a.sz;\n"
+         "  const long long base = (long long)(j + 1) * sy + (i + 1);\n"
+         "  auto lev = [&](int l) { return (long long)((l < nz ? l : nz) + 1) * sz; };\n";
+    for (int k : prm_used) o += "  const T prm" + std::to_string(k) + " = a.prm[" + std::to_string(k) + "];\n";
+    for (size_t g = 0; g < groups.size(); ++g) {
+      const Group& q = groups[g];
+      const std::string gs = std::to_string(g);
+      const bool edge = q.left || q.right;
+      o += "  const T* __restrict__ c" + gs + " = a.in[" + std::to_string(q.field) + "] + base + (" +
+           std::to_string(q.dy) + ") * sy;\n";
+      for (int d = q.dmin; d <= q.dmax; ++d) {
+        o += "  TV " + gname((int)g, d) + " = *(const TV*)(c" + gs + " + lev(z0 + (" +
+             std::to_string(d) + ")));\n";
+        if (edge)
+          o += "  T " + ename((int)g, d) + " = c" + gs + "[lev(z0 + (" + std::to_string(d) +
+               ")) + eoff];\n";
+      }
+      for (int t = 0; t < 2; ++t) {
+        const std::string reg = t ? "b" : "a", lv = std::to_string(q.dmax + 1 + t);
+        o += "  TV n" + gs + reg + " = *(const TV*)(c" + gs + " + lev(z0 + " + lv + "));\n";
+        if (edge) o += "  T m" + gs + reg + " = c" + gs + "[lev(z0 + " + lv + ") + eoff];\n";
+      }
+    }
+    o += "  for (int k = z0; k < z1; k += 2) {\n";
+    o += step("k", 'a', "    ");
+    o += "    if (k + 1 >= z1) break;\n";
+    o += "    {\n      const int k1 = k + 1;\n";
+    o += step("k1", 'b', "      ");
+    o += "    }\n  }\n}\n";
+    return o;
+  }
+};
+
+// The generated source: shared declarations, the scalar kernel and the
+// vector kernel (2 FP64 / 4 FP32 cells per lane).
+std::string generate(const Program& p, int dtype) {
+  std::string o = dtype == MS_F64 ? "typedef double T;\n" : "typedef float T;\n";
+  o += "struct JitArgs {\n"
+       "  const T* in[8];\n  T* out[4];\n  const T* prof[4];\n  T prm[8];\n"
+       "  long long sy, sz;\n  int nx, ny, nz, zc;\n  int tiles_x, tiles_y, nblocks, x0;\n"
+       "};\n";
+  // lane l receives lane l-1's value (lane 0 keeps `old`), or lane l+1's
+  // (lane 63 keeps `old`): DPP wave_shr:1 / wave_shl:1 on each 32-bit half
+  const char* dpp = dtype == MS_F64 ?
+      "__device__ __forceinline__ T ms_dpp(T old, T v, int ctl_shr) {\n"
+      "  const long long o = __builtin_bit_cast(long long, old), s = __builtin_bit_cast(long long, v);\n"
+      "  int lo, hi;\n"
+      "  if (ctl_shr) {\n"
+      "    lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x138, 0xf, 0xf, false);\n"
+      "    hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x138, 0xf, 0xf, false);\n"
+      "  } else {\n"
+      "    lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);\n"
+      "    hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x130, 0xf, 0xf, false);\n"
+      "  }\n"
+      "  return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned int)lo);\n"
+      "}\n" :
+      "__device__ __forceinline__ T ms_dpp(T old, T v, int ctl_shr) {\n"
+      "  const int o = __builtin_bit_cast(int, old), s = __builtin_bit_cast(int, v);\n"
+      "  const int r = ctl_shr ? __builtin_amdgcn_update_dpp(o, s, 0x138, 0xf, 0xf, false)\n"
+      "                        : __builtin_amdgcn_update_dpp(o, s, 0x130, 0xf, 0xf, false);\n"
+      "  return __builtin_bit_cast(T, r);\n"
+      "}\n";
+  o += dpp;
+  o += "__device__ __forceinline__ T ms_from_left(T old, T v) { return ms_dpp(old, v, 1); }\n"
+       "__device__ __forceinline__ T ms_from_right(T old, T v) { return ms_dpp(old, v, 0); }\n";
+  o += Codegen{p, dtype}.run();
+  o += VecCodegen{p, dtype, dtype == MS_F64 ? 2 : 4}.run();
+  return o;
+}
+
 // Host mirror of the generated JitArgs (same member order and types).
 template <typename T>
 struct JitArgs {
@@ -438,7 +637,7 @@ struct JitArgs {
   T prm[kJitMaxParams];
   long long sy, sz;
   int nx, ny, nz, zc;
-  int tiles_x, tiles_y, nblocks, pad;
+  int tiles_x, tiles_y, nblocks, x0;
 };
 
 // hipRTC options: the target, no contraction (each operation of the body is
@@ -479,13 +678,22 @@ int rtc_compile(const std::string& src, std::vector<char>* code) {
 }  // namespace
 }  // namespace ms
 
+namespace ms {
+namespace {
+struct JitModule {
+  hipModule_t module;
+  hipFunction_t scalar, vector;
+};
+}  // namespace
+}  // namespace ms
+
 struct ms_jit_stencil {
   ms::Program prog;
   int dtype = MS_F64;
   std::string source;
   std::vector<char> code;
-  std::mutex mu;                                         // guards the module maps
-  std::map<int, std::pair<hipModule_t, hipFunction_t>> mods;  // per device
+  std::mutex mu;                         // guards `mods`
+  std::map<int, ms::JitModule> mods;     // per device
 };
 
 using namespace ms;
@@ -500,7 +708,7 @@ extern "C" int ms_jit_compile(const char* program, int dtype, ms_jit_stencil** o
     return set_error(MS_EINVAL, "ms_jit_compile: program longer than %zu bytes", kJitMaxSource);
   try {
     Program p = Parser(program).run();
-    std::string src = Codegen{p, dtype}.run();
+    std::string src = generate(p, dtype);
     std::vector<char> code;
     if (int rc = rtc_compile(src, &code)) return rc;
     auto* st = new ms_jit_stencil;
@@ -522,7 +730,7 @@ extern "C" void ms_jit_free(ms_jit_stencil* st) {
   int cur = -1;
   const bool have = hipGetDevice(&cur) == hipSuccess;
   for (auto& kv : st->mods) {
-    if (hipSetDevice(kv.first) == hipSuccess) (void)hipModuleUnload(kv.second.first);
+    if (hipSetDevice(kv.first) == hipSuccess) (void)hipModuleUnload(kv.second.module);
   }
   if (have) (void)hipSetDevice(cur);
   delete st;
@@ -556,23 +764,46 @@ extern "C" const char* ms_jit_name(const ms_jit_stencil* st, int kind, int index
 
 namespace {
 
-int jit_function(ms_jit_stencil* st, hipFunction_t* fn) {
+// The module's two kernels on the current device (loaded on first use).
+int jit_functions(ms_jit_stencil* st, hipFunction_t* scalar, hipFunction_t* vector) {
   int dev = 0;
   MS_HIP_TRY(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(st->mu);
   auto it = st->mods.find(dev);
   if (it == st->mods.end()) {
-    hipModule_t m = nullptr;
-    MS_HIP_TRY(hipModuleLoadData(&m, st->code.data()));
-    hipFunction_t f = nullptr;
-    const hipError_t e = hipModuleGetFunction(&f, m, "ms_jit_kernel");
+    JitModule jm{};
+    MS_HIP_TRY(hipModuleLoadData(&jm.module, st->code.data()));
+    hipError_t e = hipModuleGetFunction(&jm.scalar, jm.module, "ms_jit_kernel_s");
+    if (e == hipSuccess) e = hipModuleGetFunction(&jm.vector, jm.module, "ms_jit_kernel_v");
     if (e != hipSuccess) {
-      (void)hipModuleUnload(m);
+      (void)hipModuleUnload(jm.module);
       return set_error(MS_EHIP, "ms_jit_apply: kernel not found: %s", hipGetErrorString(e));
     }
-    it = st->mods.emplace(dev, std::make_pair(m, f)).first;
+    it = st->mods.emplace(dev, jm).first;
   }
-  *fn = it->second.second;
+  *scalar = it->second.scalar;
+  *vector = it->second.vector;
+  return MS_OK;
+}
+
+// z split so that one launch has about `target` blocks (MS_JIT_BLOCKS
+// overrides), marches of at least 8 levels. Measured at 512^3: the vector
+// kernel is fastest near 512 blocks (two per CU, long marches), the scalar
+// one near 4096.
+template <typename T>
+int jit_geometry(JitArgs<T>& a, int nz, int64_t target) {
+  const char* ev = getenv("MS_JIT_BLOCKS");
+  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : target;
+  const int64_t t2 = (int64_t)a.tiles_x * a.tiles_y;
+  int64_t chunks = (want + t2 - 1) / t2;
+  const int64_t max_chunks = (nz + 7) / 8;
+  if (chunks > max_chunks) chunks = max_chunks;
+  if (chunks < 1) chunks = 1;
+  a.zc = (int)((nz + chunks - 1) / chunks);
+  chunks = (nz + a.zc - 1) / a.zc;
+  const int64_t nb = t2 * chunks;
+  if (nb > 0x7fffffff) return set_error(MS_EUNSUPPORTED, "ms_jit_apply: grid too large");
+  a.nblocks = (int)nb;
   return MS_OK;
 }
 
@@ -582,8 +813,15 @@ int jit_launch(ms_jit_stencil* st, const ms_grid& g, const void* const* fields,
                hipStream_t s) {
   const Program& p = st->prog;
   JitArgs<T> a{};
-  for (size_t q = 0; q < p.fields.size(); ++q) a.in[q] = static_cast<const T*>(fields[q]);
-  for (size_t q = 0; q < p.out_names.size(); ++q) a.out[q] = static_cast<T*>(outputs[q]);
+  std::vector<const void*> ptrs;
+  for (size_t q = 0; q < p.fields.size(); ++q) {
+    a.in[q] = static_cast<const T*>(fields[q]);
+    ptrs.push_back(fields[q]);
+  }
+  for (size_t q = 0; q < p.out_names.size(); ++q) {
+    a.out[q] = static_cast<T*>(outputs[q]);
+    ptrs.push_back(outputs[q]);
+  }
   for (size_t q = 0; q < p.profiles.size(); ++q) a.prof[q] = static_cast<const T*>(profiles[q]);
   for (size_t q = 0; q < p.params.size(); ++q) a.prm[q] = (T)params[q];
   a.sy = g.sy;
@@ -591,26 +829,31 @@ int jit_launch(ms_jit_stencil* st, const ms_grid& g, const void* const* fields,
   a.nx = g.nx;
   a.ny = g.ny;
   a.nz = g.nz;
-  a.tiles_x = (g.nx + 63) / 64;
   a.tiles_y = (g.ny + 3) / 4;
-  // About 4096 blocks (16 per CU), marches of at least 8 levels;
-  // MS_JIT_BLOCKS overrides the target for tuning.
-  const char* ev = getenv("MS_JIT_BLOCKS");
-  const int64_t want = ev && atoi(ev) > 0 ? atoi(ev) : 4096;
-  const int64_t t2 = (int64_t)a.tiles_x * a.tiles_y;
-  int64_t chunks = (want + t2 - 1) / t2;
-  const int64_t max_chunks = (g.nz + 7) / 8;
-  if (chunks > max_chunks) chunks = max_chunks;
-  if (chunks < 1) chunks = 1;
-  a.zc = (int)((g.nz + chunks - 1) / chunks);
-  chunks = (g.nz + a.zc - 1) / a.zc;
-  const int64_t nb = t2 * chunks;
-  if (nb > 0x7fffffff) return set_error(MS_EUNSUPPORTED, "ms_jit_apply: grid too large");
-  a.nblocks = (int)nb;
-  hipFunction_t fn = nullptr;
-  if (int rc = jit_function(st, &fn)) return rc;
+  hipFunction_t fs = nullptr, fv = nullptr;
+  if (int rc = jit_functions(st, &fs, &fv)) return rc;
+  // Whole 64V-column tiles go to the vector kernel when every field is
+  // aligned to V cells; the remaining columns to the scalar kernel.
+  const int vmax = 16 / (int)sizeof(T);
+  const int vec = vec_alignment(g, sizeof(T) == 8 ? MS_F64 : MS_F32, ptrs.data(),
+                                (int)ptrs.size());
+  const char* ev = getenv("MS_JIT_SCALAR");
+  const int full = vec == vmax && !(ev && atoi(ev) > 0) ? g.nx / (64 * vmax) : 0;
   void* kargs[] = {&a};
-  MS_HIP_TRY(hipModuleLaunchKernel(fn, (unsigned)nb, 1, 1, 256, 1, 1, 0, s, kargs, nullptr));
+  if (full > 0) {
+    a.tiles_x = full;
+    a.x0 = 0;
+    if (int rc = jit_geometry(a, g.nz, 512)) return rc;
+    MS_HIP_TRY(hipModuleLaunchKernel(fv, (unsigned)a.nblocks, 1, 1, 256, 1, 1, 0, s, kargs,
+                                     nullptr));
+  }
+  a.x0 = full * 64 * vmax;
+  if (a.x0 < g.nx) {
+    a.tiles_x = (g.nx - a.x0 + 63) / 64;
+    if (int rc = jit_geometry(a, g.nz, 4096)) return rc;
+    MS_HIP_TRY(hipModuleLaunchKernel(fs, (unsigned)a.nblocks, 1, 1, 256, 1, 1, 0, s, kargs,
+                                     nullptr));
+  }
   return MS_OK;
 }
 

@@ -18,9 +18,17 @@ def test_jacobi_program_compiles_with_its_signature():
     j = ms.JitStencil(JACOBI)
     assert (j.fields, j.params, j.profiles, j.outputs) == (["u", "f"], [], [], ["v"])
     src = j.source
-    assert "typedef double T;" in src and "ms_jit_kernel" in src
-    # six (field, dx, dy) columns: u at x+-1, y+-1, the centre column, and f
-    assert len(re.findall(r"const T\* __restrict__ c\d+ =", src)) == 6
+    assert "typedef double T;" in src
+    scalar = src[src.index("ms_jit_kernel_s"):src.index("ms_jit_kernel_v")]
+    vector = src[src.index("ms_jit_kernel_v"):]
+    # scalar kernel: six (field, dx, dy) columns: u at x+-1, y+-1, the
+    # centre column, and f
+    assert len(re.findall(r"const T\* __restrict__ c\d+ =", scalar)) == 6
+    # vector kernel: four (field, dy) rows (u at y-1, y, y+1, and f); x
+    # neighbours by DPP, with one edge load only for the row that needs them
+    assert len(re.findall(r"const T\* __restrict__ c\d+ =", vector)) == 4
+    assert vector.count("ms_from_left(") == 2 and vector.count("ms_from_right(") == 2
+    assert "ext_vector_type(2)" in src
     # the constant is the double nearest 1/6, as a hex literal
     assert "0x1.5555555555555p-3" in src
 
@@ -28,6 +36,7 @@ def test_jacobi_program_compiles_with_its_signature():
 def test_float32_program_and_the_advection_program_compile():
     j = ms.JitStencil(JACOBI, dtype=torch.float32)
     assert "typedef float T;" in j.source and "0x1.555556p-3f" in j.source
+    assert "ext_vector_type(4)" in j.source
     a = ms.JitStencil(advection())
     assert a.fields == ["u", "v", "w"] and a.params == ["tcx", "tcy"]
     assert a.profiles == ["tzc1", "tzc2"] and a.outputs == ["su", "sv", "sw"]
