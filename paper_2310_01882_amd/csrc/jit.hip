@@ -40,6 +40,7 @@ namespace {
 constexpr int kJitMaxFields = 8, kJitMaxOutputs = 4, kJitMaxParams = 8, kJitMaxProfiles = 4;
 constexpr int kJitMaxLets = 256, kJitMaxNodes = 1 << 16, kJitMaxDepth = 200;
 constexpr size_t kJitMaxSource = 1 << 16;
+constexpr int kJitVecRows = 2;  // rows per lane in the vector kernel
 
 struct Node {
   enum Kind { NUM, FIELD, PARAM, PROFILE, LET, NEG, ADD, SUB, MUL, DIV } kind;
@@ -429,47 +430,50 @@ struct Codegen {
   }
 };
 
-// The vector kernel: V consecutive x cells per lane (one 16-byte load per
-// row and level), whole 64V-column tiles only. Accesses with dx = -1 / +1
-// take the neighbour lane's last / first element through a DPP move; lanes
-// 0 and 63 take the cell beyond the wave from one extra load per row and
-// level (every other lane loads its own first cell there, a cache hit).
+// The vector kernel: V consecutive x cells of R rows per lane (one 16-byte
+// load per row and level), whole 64V-column tiles only. A row the body
+// reads at several y offsets is loaded once for the lane's R rows. Accesses
+// with dx = -1 / +1 take the neighbour lane's last / first element through
+// a DPP move; lanes 0 and 63 take the cell beyond the wave from one extra
+// load per row and level (every other lane loads its own first cell there,
+// a cache hit).
 struct VecCodegen {
   const Program& p;
-  int dtype, V;
+  int dtype, V, R;
   struct Group {
-    int field, dy, dmin, dmax;
-    bool left, right;
+    int field, row, dmin, dmax;  // row: offset from the lane's first row
+    bool edge;
   };
   std::vector<Group> groups;
   std::map<std::pair<int, int>, int> group_of;
   std::set<int> prm_used, prof_used;
+  std::set<std::pair<int, int>> lused, rused;  // (group, dz) read at dx -1 / +1
 
   static std::string gname(int g, int d) {
     return "g" + std::to_string(g) + (d < 0 ? "m" : "p") + std::to_string(d < 0 ? -d : d);
   }
   static std::string ename(int g, int d) { return "e" + gname(g, d).substr(1); }
 
-  std::string emit(int id, int v) {
+  std::string emit(int id, int v, int r) {
     const Node& n = p.nodes[id];
-    const std::string vs = std::to_string(v);
     switch (n.kind) {
       case Node::NUM: return "((T)" + hex_literal(n.num, dtype) + ")";
       case Node::FIELD: {
-        const int g = group_of.at(std::make_pair(n.idx, n.dy));
+        const int g = group_of.at(std::make_pair(n.idx, r + n.dy));
         const std::string q = gname(g, n.dz);
-        if (n.dx == 0) return q + "[" + vs + "]";
+        if (n.dx == 0) return q + "[" + std::to_string(v) + "]";
         if (n.dx < 0) return v > 0 ? q + "[" + std::to_string(v - 1) + "]" : "L" + q.substr(1);
         return v < V - 1 ? q + "[" + std::to_string(v + 1) + "]" : "R" + q.substr(1);
       }
       case Node::PARAM: return "prm" + std::to_string(n.idx);
       case Node::PROFILE: return "pf" + std::to_string(n.idx);
-      case Node::LET: return "t" + std::to_string(n.idx) + "_" + vs;
-      case Node::NEG: return "(-" + emit(n.a, v) + ")";
-      case Node::ADD: return "(" + emit(n.a, v) + " + " + emit(n.b, v) + ")";
-      case Node::SUB: return "(" + emit(n.a, v) + " - " + emit(n.b, v) + ")";
-      case Node::MUL: return "(" + emit(n.a, v) + " * " + emit(n.b, v) + ")";
-      case Node::DIV: return "(" + emit(n.a, v) + " / " + emit(n.b, v) + ")";
+      case Node::LET:
+        return "t" + std::to_string(n.idx) + "_" + std::to_string(r) + "_" + std::to_string(v);
+      case Node::NEG: return "(-" + emit(n.a, v, r) + ")";
+      case Node::ADD: return "(" + emit(n.a, v, r) + " + " + emit(n.b, v, r) + ")";
+      case Node::SUB: return "(" + emit(n.a, v, r) + " - " + emit(n.b, v, r) + ")";
+      case Node::MUL: return "(" + emit(n.a, v, r) + " * " + emit(n.b, v, r) + ")";
+      case Node::DIV: return "(" + emit(n.a, v, r) + " / " + emit(n.b, v, r) + ")";
     }
     return "";
   }
@@ -478,13 +482,6 @@ struct VecCodegen {
     std::string o;
     for (int q : prof_used)
       o += in + "const T pf" + std::to_string(q) + " = a.prof[" + std::to_string(q) + "][" + k + "];\n";
-    // neighbour-lane values for the x offsets
-    std::set<std::pair<int, int>> lused, rused;
-    for (const Node& n : p.nodes)
-      if (n.kind == Node::FIELD && n.dx != 0) {
-        const int g = group_of.at(std::make_pair(n.idx, n.dy));
-        (n.dx < 0 ? lused : rused).insert(std::make_pair(g, n.dz));
-      }
     for (auto gd : lused)
       o += in + "const T L" + gname(gd.first, gd.second).substr(1) + " = ms_from_left(" +
            ename(gd.first, gd.second) + ", " + gname(gd.first, gd.second) + "[" +
@@ -492,30 +489,33 @@ struct VecCodegen {
     for (auto gd : rused)
       o += in + "const T R" + gname(gd.first, gd.second).substr(1) + " = ms_from_right(" +
            ename(gd.first, gd.second) + ", " + gname(gd.first, gd.second) + "[0]);\n";
-    for (size_t l = 0; l < p.let_root.size(); ++l)
-      for (int v = 0; v < V; ++v)
-        o += in + "const T t" + std::to_string(l) + "_" + std::to_string(v) + " = " +
-             emit(p.let_root[l], v) + ";\n";
-    for (size_t r = 0; r < p.out_root.size(); ++r) {
-      const std::string rs = std::to_string(r);
-      o += in + "{\n" + in + "  TV ov;\n";
-      for (int v = 0; v < V; ++v)
-        o += in + "  ov[" + std::to_string(v) + "] = " + emit(p.out_root[r], v) + ";\n";
-      o += in + "  __builtin_nontemporal_store(ov, (TV*)(a.out[" + rs + "] + (long long)(" + k +
-           " + 1) * sz + base));\n" + in + "}\n";
+    for (int r = 0; r < R; ++r) {
+      for (size_t l = 0; l < p.let_root.size(); ++l)
+        for (int v = 0; v < V; ++v)
+          o += in + "const T t" + std::to_string(l) + "_" + std::to_string(r) + "_" +
+               std::to_string(v) + " = " + emit(p.let_root[l], v, r) + ";\n";
+      o += in + "if (j + " + std::to_string(r) + " < a.ny) {\n";
+      for (size_t q = 0; q < p.out_root.size(); ++q) {
+        o += in + "  {\n" + in + "    TV ov;\n";
+        for (int v = 0; v < V; ++v)
+          o += in + "    ov[" + std::to_string(v) + "] = " + emit(p.out_root[q], v, r) + ";\n";
+        o += in + "    __builtin_nontemporal_store(ov, (TV*)(a.out[" + std::to_string(q) +
+             "] + (long long)(" + k + " + 1) * sz + base + " + std::to_string(r) + " * sy));\n" +
+             in + "  }\n";
+      }
+      o += in + "}\n";
     }
     for (size_t g = 0; g < groups.size(); ++g) {
       const Group& q = groups[g];
       const std::string gs = std::to_string(g), reg = std::string(1, ph);
-      const bool edge = q.left || q.right;
       for (int d = q.dmin; d < q.dmax; ++d) {
         o += in + gname((int)g, d) + " = " + gname((int)g, d + 1) + ";\n";
-        if (edge) o += in + ename((int)g, d) + " = " + ename((int)g, d + 1) + ";\n";
+        if (q.edge) o += in + ename((int)g, d) + " = " + ename((int)g, d + 1) + ";\n";
       }
       o += in + gname((int)g, q.dmax) + " = n" + gs + reg + ";\n";
       o += in + "n" + gs + reg + " = *(const TV*)(c" + gs + " + lev(" + k + " + " +
            std::to_string(q.dmax + 3) + "));\n";
-      if (edge) {
+      if (q.edge) {
         o += in + ename((int)g, q.dmax) + " = m" + gs + reg + ";\n";
         o += in + "m" + gs + reg + " = c" + gs + "[lev(" + k + " + " + std::to_string(q.dmax + 3) +
              ") + eoff];\n";
@@ -527,23 +527,28 @@ struct VecCodegen {
   std::string run() {
     for (const Node& n : p.nodes) {
       if (n.kind == Node::FIELD) {
-        auto key = std::make_pair(n.idx, n.dy);
-        if (!group_of.count(key)) {
-          group_of[key] = (int)groups.size();
-          groups.push_back({n.idx, n.dy, 2, -2, false, false});
+        for (int r = 0; r < R; ++r) {
+          auto key = std::make_pair(n.idx, r + n.dy);
+          if (!group_of.count(key)) {
+            group_of[key] = (int)groups.size();
+            groups.push_back({n.idx, r + n.dy, 2, -2, false});
+          }
+          const int gi = group_of[key];
+          Group& g = groups[gi];
+          g.dmin = std::min(g.dmin, n.dz);
+          g.dmax = std::max(g.dmax, n.dz);
+          if (n.dx != 0) {
+            g.edge = true;
+            (n.dx < 0 ? lused : rused).insert(std::make_pair(gi, n.dz));
+          }
         }
-        Group& g = groups[group_of[key]];
-        g.dmin = std::min(g.dmin, n.dz);
-        g.dmax = std::max(g.dmax, n.dz);
-        if (n.dx < 0) g.left = true;
-        if (n.dx > 0) g.right = true;
       } else if (n.kind == Node::PARAM) {
         prm_used.insert(n.idx);
       } else if (n.kind == Node::PROFILE) {
         prof_used.insert(n.idx);
       }
     }
-    const std::string Vs = std::to_string(V);
+    const std::string Vs = std::to_string(V), Rs = std::to_string(R);
     std::string o = "typedef T TV __attribute__((ext_vector_type(" + Vs + ")));\n";
     o += "extern \"C\" __global__ __launch_bounds__(256) void ms_jit_kernel_v(JitArgs a) {\n"
          "  const int b = blockIdx.x, nb = a.nblocks;\n"
@@ -553,32 +558,34 @@ struct VecCodegen {
          "  const int tyi = rest % a.tiles_y, tzi = rest / a.tiles_y;\n"
          "  const int lane = (int)(threadIdx.x & 63);\n"
          "  const int i = txi * " + std::to_string(64 * V) + " + " + Vs + " * lane;\n"
-         "  const int j = tyi * 4 + (int)(threadIdx.x >> 6);\n"
+         "  const int j = tyi * " + std::to_string(4 * R) + " + " + Rs + " * (int)(threadIdx.x >> 6);\n"
          "  if (j >= a.ny) return;  // whole waves only: the DPP moves stay within a wave\n"
          "  const int eoff = lane == 0 ? -1 : (lane == 63 ? " + Vs + " : 0);\n"
-         "  const int nz = a.nz, z0 = tzi * a.zc;\n"
+         "  const int nz = a.nz, ny = a.ny, z0 = tzi * a.zc;\n"
          "  const int z1 = z0 + a.zc < nz ? z0 + a.zc : nz;\n"
          "  const long long sy = a.sy, sz = a.sz;\n"
          "  const long long base = (long long)(j + 1) * sy + (i + 1);\n"
-         "  auto lev = [&](int l) { return (long long)((l < nz ? l : nz) + 1) * sz; };\n";
+         "  auto lev = [&](int l) { return (long long)((l < nz ? l : nz) + 1) * sz; };\n"
+         "  // a row's offset from row j, clamped into the halo (rows past ny\n"
+         "  // feed no stored cell)\n"
+         "  auto rowoff = [&](int d) { return (long long)((j + d < ny ? j + d : ny) - j) * sy; };\n";
     for (int k : prm_used) o += "  const T prm" + std::to_string(k) + " = a.prm[" + std::to_string(k) + "];\n";
     for (size_t g = 0; g < groups.size(); ++g) {
       const Group& q = groups[g];
       const std::string gs = std::to_string(g);
-      const bool edge = q.left || q.right;
-      o += "  const T* __restrict__ c" + gs + " = a.in[" + std::to_string(q.field) + "] + base + (" +
-           std::to_string(q.dy) + ") * sy;\n";
+      o += "  const T* __restrict__ c" + gs + " = a.in[" + std::to_string(q.field) +
+           "] + base + rowoff(" + std::to_string(q.row) + ");\n";
       for (int d = q.dmin; d <= q.dmax; ++d) {
         o += "  TV " + gname((int)g, d) + " = *(const TV*)(c" + gs + " + lev(z0 + (" +
              std::to_string(d) + ")));\n";
-        if (edge)
+        if (q.edge)
           o += "  T " + ename((int)g, d) + " = c" + gs + "[lev(z0 + (" + std::to_string(d) +
                ")) + eoff];\n";
       }
       for (int t = 0; t < 2; ++t) {
         const std::string reg = t ? "b" : "a", lv = std::to_string(q.dmax + 1 + t);
         o += "  TV n" + gs + reg + " = *(const TV*)(c" + gs + " + lev(z0 + " + lv + "));\n";
-        if (edge) o += "  T m" + gs + reg + " = c" + gs + "[lev(z0 + " + lv + ") + eoff];\n";
+        if (q.edge) o += "  T m" + gs + reg + " = c" + gs + "[lev(z0 + " + lv + ") + eoff];\n";
       }
     }
     o += "  for (int k = z0; k < z1; k += 2) {\n";
@@ -624,7 +631,7 @@ std::string generate(const Program& p, int dtype) {
   o += "__device__ __forceinline__ T ms_from_left(T old, T v) { return ms_dpp(old, v, 1); }\n"
        "__device__ __forceinline__ T ms_from_right(T old, T v) { return ms_dpp(old, v, 0); }\n";
   o += Codegen{p, dtype}.run();
-  o += VecCodegen{p, dtype, dtype == MS_F64 ? 2 : 4}.run();
+  o += VecCodegen{p, dtype, dtype == MS_F64 ? 2 : 4, kJitVecRows}.run();
   return o;
 }
 
@@ -788,7 +795,7 @@ int jit_functions(ms_jit_stencil* st, hipFunction_t* scalar, hipFunction_t* vect
 
 // z split so that one launch has about `target` blocks (MS_JIT_BLOCKS
 // overrides), marches of at least 8 levels. Measured at 512^3: the vector
-// kernel is fastest near 512 blocks (two per CU, long marches), the scalar
+// kernel is fastest near 256 blocks (one per CU, long marches), the scalar
 // one near 4096.
 template <typename T>
 int jit_geometry(JitArgs<T>& a, int nz, int64_t target) {
@@ -842,14 +849,16 @@ int jit_launch(ms_jit_stencil* st, const ms_grid& g, const void* const* fields,
   void* kargs[] = {&a};
   if (full > 0) {
     a.tiles_x = full;
+    a.tiles_y = (g.ny + 4 * kJitVecRows - 1) / (4 * kJitVecRows);
     a.x0 = 0;
-    if (int rc = jit_geometry(a, g.nz, 512)) return rc;
+    if (int rc = jit_geometry(a, g.nz, 256)) return rc;
     MS_HIP_TRY(hipModuleLaunchKernel(fv, (unsigned)a.nblocks, 1, 1, 256, 1, 1, 0, s, kargs,
                                      nullptr));
   }
   a.x0 = full * 64 * vmax;
   if (a.x0 < g.nx) {
     a.tiles_x = (g.nx - a.x0 + 63) / 64;
+    a.tiles_y = (g.ny + 3) / 4;
     if (int rc = jit_geometry(a, g.nz, 4096)) return rc;
     MS_HIP_TRY(hipModuleLaunchKernel(fs, (unsigned)a.nblocks, 1, 1, 256, 1, 1, 0, s, kargs,
                                      nullptr));

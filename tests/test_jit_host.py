@@ -24,10 +24,11 @@ def test_jacobi_program_compiles_with_its_signature():
     # scalar kernel: six (field, dx, dy) columns: u at x+-1, y+-1, the
     # centre column, and f
     assert len(re.findall(r"const T\* __restrict__ c\d+ =", scalar)) == 6
-    # vector kernel: four (field, dy) rows (u at y-1, y, y+1, and f); x
-    # neighbours by DPP, with one edge load only for the row that needs them
-    assert len(re.findall(r"const T\* __restrict__ c\d+ =", vector)) == 4
-    assert vector.count("ms_from_left(") == 2 and vector.count("ms_from_right(") == 2
+    # vector kernel, two rows per lane: six rows (u at rows -1, 0, 1, 2 and
+    # f at rows 0, 1); x neighbours by DPP for u's two own rows, in each of
+    # the two unrolled steps
+    assert len(re.findall(r"const T\* __restrict__ c\d+ =", vector)) == 6
+    assert vector.count("ms_from_left(") == 4 and vector.count("ms_from_right(") == 4
     assert "ext_vector_type(2)" in src
     # the constant is the double nearest 1/6, as a hex literal
     assert "0x1.5555555555555p-3" in src
