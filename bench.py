@@ -409,7 +409,7 @@ def bench_jit(args):
                    "rhs": "8 Gaussian sources (seed 1)", "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic_for(f"jit_jacobi_f64_{n}"), "kernel": "ms_jit_kernel",
+                     "traffic": traffic_for(f"jit_jacobi_f64_{n}"), "kernel": "ms_jit_kernel_v",
                      "bytes_per_launch_algorithmic": 24 * cells,
                      "avg_launch_us": round(launch_s * 1e6, 3)},
         "compile_seconds": {"jacobi": round(t_jac, 3), "advection": round(t_adv, 3)},
