@@ -319,8 +319,10 @@ void ms_tuning_clear(void);
  * solved in ONE persistent kernel launch (captured in a hipGraph). The
  * device's resident blocks are split into teams, one per instance, so that
  * the longest estimated finish time is as short as possible (estimate:
- * cells x Jacobi sweeps to rel_tol from the spectral radius, split over the
- * team, plus a per-sweep barrier cost for teams of more than one block); a
+ * cells x Jacobi sweeps to rel_tol, from the spectral radius and the
+ * reference residual's component along the slowest mode (one device pass
+ * before planning; see jacobi_batched_plan), split over the team, plus a
+ * per-sweep barrier cost for teams of more than one block); a
  * team runs its instance's whole solve with team barriers and never waits
  * for another team. precision: MS_SOLVE_F64 or
  * MS_SOLVE_F32_REFINED with the refinement rules of jacobi_solve (same
@@ -344,9 +346,39 @@ size_t jacobi_batched_workspace_bytes(int n, const ms_instance* inst,
 int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
                          void* work, size_t work_bytes, ms_solve_result* res,
                          void* stream);
-/* The team sizes (n ints) and the grid size the batched solve would use. */
+/* The team sizes (n ints), the grid size and the per-instance sweep
+ * estimates (n doubles) the batched solve would use; any output may be NULL.
+ * The estimates come from one device pass over the instances (the same
+ * probe the solve runs): ||r(u^0)|| and the component c1 of r(u^0) along
+ * the slowest Jacobi mode give about ln(tol ||r(u^0)|| / c1) / ln(rho)
+ * sweeps, kept within [1/10, 1] of ln(tol) / ln(rho). They depend on f and
+ * the halo of x, not on its interior. work: device, at least
+ * jacobi_batched_plan_workspace_bytes(n) bytes. Synchronises `stream`. */
+size_t jacobi_batched_plan_workspace_bytes(int n);
 int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
-                        int* team_sizes, int* grid_blocks);
+                        int* team_sizes, int* grid_blocks, double* est_sweeps,
+                        void* work, size_t work_bytes, void* stream);
+
+/* ---- batched solves on concurrent streams -----------------------------------
+ * The same batch as jacobi_solve_batched, run instead by `workers` (1..64)
+ * host threads, each with its own HIP stream (created and destroyed by the
+ * call, default priority) and its own slice of the workspace. The threads
+ * take the instances in order of estimated work (cells x the planner's
+ * sweep estimate, largest first) and solve each exactly as jacobi_solve
+ * does with `o` (any precision, temporal_block and method), so instances
+ * overlap on the device and every result equals jacobi_solve's (fields bit
+ * for bit). res[i] as jacobi_solve's result. work: device, at least
+ * jacobi_batched_streams_workspace_bytes(n, inst, o, workers) bytes (the
+ * probe area plus workers x the largest single-instance workspace).
+ * Synchronises `stream` before it starts (its one device pass runs there)
+ * and blocks until every instance is done. Returns MS_OK, MS_NOT_CONVERGED
+ * or MS_ENONFINITE (worst over instances), or the first other error with
+ * its instance. Instances' x must not overlap. */
+size_t jacobi_batched_streams_workspace_bytes(int n, const ms_instance* inst,
+                                              const ms_solve_opts* o, int workers);
+int jacobi_solve_batched_streams(int n, const ms_instance* inst, const ms_solve_opts* o,
+                                 int workers, void* work, size_t work_bytes,
+                                 ms_solve_result* res, void* stream);
 
 /* ---- autotuning of the batched tile shapes ----------------------------------
  * A team walks its instance in tiles of tx x-cells (one row of tx lanes;

@@ -120,8 +120,14 @@ SIGNATURES = {
                                              ctypes.POINTER(SolveOpts)]),
     "jacobi_solve_batched": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts), _P,
                                   _SZ, ctypes.POINTER(SolveResult), _P]),
+    "jacobi_batched_plan_workspace_bytes": (_SZ, [_I]),
+    "jacobi_batched_streams_workspace_bytes": (_SZ, [_I, ctypes.POINTER(Instance),
+                                                     ctypes.POINTER(SolveOpts), _I]),
+    "jacobi_solve_batched_streams": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
+                                          _I, _P, _SZ, ctypes.POINTER(SolveResult), _P]),
     "jacobi_batched_plan": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
-                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(_D), _P, _SZ, _P]),
     "ms_autotune_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I, _P, _SZ,
                                 ctypes.POINTER(Tuning), _P]),
     "ms_sweep_shape": (_I, [ctypes.POINTER(Grid), _I, ctypes.POINTER(ctypes.c_void_p), _I,
@@ -445,13 +451,40 @@ def _instances(xs, fs):
     return arr
 
 
-def batched_plan(xs, fs, **opts):
-    """(team sizes, grid blocks) the batched solve would use."""
+def jacobi_solve_batched_streams(xs, fs, workers=4, work=None, stream=None, **opts):
+    """Solve every instance as jacobi_solve would, on ``workers`` concurrent
+    streams (largest estimated work first). Returns a SolveInfo per
+    instance; raises MsError on errors other than non-convergence."""
+    arr = _instances(xs, fs)
+    o = solve_opts(**opts)
+    if work is None:
+        nbytes = lib.jacobi_batched_streams_workspace_bytes(len(xs), arr, ctypes.byref(o),
+                                                            int(workers))
+        if nbytes == 0:
+            raise MsError(MS_EINVAL, last_error())
+        work = _workspace(nbytes, xs[0].device)
+    res = (SolveResult * len(xs))()
+    rc = lib.jacobi_solve_batched_streams(len(xs), arr, ctypes.byref(o), int(workers), _ptr(work),
+                                          work.numel(), res, _stream(stream))
+    _check(rc, allow=(MS_OK, MS_NOT_CONVERGED))
+    return [SolveInfo(r.status, r.sweeps, r.outer_iters, r.res0, r.res_final, r.rel_final, [],
+                      r.seconds) for r in res]
+
+
+def batched_plan(xs, fs, stream=None, with_estimates=False, **opts):
+    """(team sizes, grid blocks) the batched solve would use, and with
+    ``with_estimates`` the per-instance sweep estimates it plans with (from
+    one device pass over the instances)."""
     arr = _instances(xs, fs)
     o = solve_opts(**opts)
     teams = (ctypes.c_int * len(xs))()
+    est = (_D * len(xs))()
     g = ctypes.c_int(0)
-    _check(lib.jacobi_batched_plan(len(xs), arr, ctypes.byref(o), teams, ctypes.byref(g)))
+    work = _workspace(lib.jacobi_batched_plan_workspace_bytes(len(xs)), xs[0].device)
+    _check(lib.jacobi_batched_plan(len(xs), arr, ctypes.byref(o), teams, ctypes.byref(g), est,
+                                   _ptr(work), work.numel(), _stream(stream)))
+    if with_estimates:
+        return list(teams), g.value, list(est)
     return list(teams), g.value
 
 

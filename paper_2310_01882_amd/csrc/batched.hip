@@ -4,7 +4,8 @@
 // The grid holds G blocks, no more than can be resident at once. Blocks are
 // split into teams, one per instance, balancing the instances' estimated
 // finish times (cells x Jacobi sweeps to the tolerance, from the spectral
-// radius, over the team size, plus a barrier cost per sweep), and placed
+// radius and a device probe of the reference residual's slowest-mode
+// component, over the team size, plus a barrier cost per sweep), and placed
 // XCD by XCD so that a team shares an L2 where it can. A team
 // runs its instance's whole solve -- FP64 Jacobi, or FP32-storage Jacobi
 // inside FP64 iterative refinement -- with team barriers (a counter and a
@@ -31,10 +32,14 @@
 #include "ms_internal.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <numeric>
+#include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -480,14 +485,112 @@ struct Plan {
   size_t bytes = 0;
 };
 
-// Estimated Jacobi sweeps to the tolerance: the decay of the slowest mode,
-// whose factor per sweep is the spectral radius (mean of cos(pi/(n+1))).
-double est_sweeps(const ms_grid& g, double tol) {
+// Estimated Jacobi sweeps to the tolerance. The slowest mode
+// phi_1 = prod_axes sin(pi (i+1) / (n+1)) decays by the spectral radius rho
+// (the mean of cos(pi / (n+1))) per sweep, and the residual is dominated by
+// it long before the tolerance; so if c1 is the component of the reference
+// residual r(u^0) along phi_1 (<r(u^0), phi_1> / ||phi_1||) and res0 its
+// norm, about ln(tol res0 / c1) / ln(rho) sweeps are needed from u^0 (a
+// better start needs fewer: the estimate does not depend on the interior of
+// x, so a plan, and the tile shapes tuned for it, stay the same whatever x
+// holds). Without the probe this is ln(tol) / ln(rho), an upper bound; the
+// estimate is kept within [upper / 10, upper].
+double est_sweeps(const ms_grid& g, double tol, double res0, double c1) {
   const double pi = 3.14159265358979323846;
   const double rho =
       (std::cos(pi / (g.nx + 1)) + std::cos(pi / (g.ny + 1)) + std::cos(pi / (g.nz + 1))) / 3.0;
-  const double k = std::log(std::max(tol, 1e-300)) / std::log(std::min(rho, 1.0 - 1e-16));
-  return std::max(k, 1.0);
+  const double lr = std::log(std::min(rho, 1.0 - 1e-16));
+  const double upper = std::max(std::log(std::max(tol, 1e-300)) / lr, 1.0);
+  if (!(res0 > 0.0)) return 1.0;  // already converged at k = 0
+  if (!(c1 > 0.0) || !std::isfinite(c1)) return upper;
+  const double k = std::log(std::max(tol * res0 / c1, 1e-300)) / lr;
+  return std::min(upper, std::max(k, std::max(upper / 10.0, 1.0)));
+}
+
+// Planning probe input and output, one block per instance.
+struct ProbeIn {
+  int nx, ny, nz, pad;
+  int64_t sy, sz;
+  const double* x;
+  const double* f;
+};
+constexpr int kProbeTab = 4096;  // sin tables in LDS when nx + ny + nz fits
+
+// out[3 i] = ||r(u^0)||^2 (u^0: x with its interior zeroed), out[3 i + 1] =
+// <r(u^0), phi_1>, out[3 i + 2] = ||phi_1||^2, each summed in a fixed order.
+__global__ __launch_bounds__(kBatchThreads) void batch_probe_kernel(const ProbeIn* in,
+                                                                    double* out) {
+  __shared__ double tab[kProbeTab];
+  __shared__ double red[kBatchWaves];
+  const ProbeIn q = in[blockIdx.x];
+  const double pi = 3.14159265358979323846;
+  const bool tabbed = q.nx + q.ny + q.nz <= kProbeTab;
+  if (tabbed) {
+    for (int t = threadIdx.x; t < q.nx + q.ny + q.nz; t += blockDim.x) {
+      const int n = t < q.nx ? q.nx : t < q.nx + q.ny ? q.ny : q.nz;
+      const int idx = t < q.nx ? t : t < q.nx + q.ny ? t - q.nx : t - q.nx - q.ny;
+      tab[t] = sin(pi * (idx + 1) / (n + 1));
+    }
+  }
+  __syncthreads();
+  double a0 = 0.0, ac = 0.0, ap = 0.0;
+  const int64_t cells = (int64_t)q.nx * q.ny * q.nz;
+  for (int64_t c = threadIdx.x; c < cells; c += blockDim.x) {
+    const int i = (int)(c % q.nx);
+    const int64_t rest = c / q.nx;
+    const int j = (int)(rest % q.ny), k = (int)(rest / q.ny);
+    const int64_t p = (int64_t)(k + 1) * q.sz + (int64_t)(j + 1) * q.sy + (i + 1);
+    const double xp = q.x[p + 1], xm = q.x[p - 1], yp = q.x[p + q.sy], ym = q.x[p - q.sy];
+    const double zp = q.x[p + q.sz], zm = q.x[p - q.sz];
+    const double fv = q.f ? q.f[p] : 0.0;
+    // neighbours of the zero-interior start: halo cells only
+    const double s0 = (i == q.nx - 1 ? xp : 0.0) + (i == 0 ? xm : 0.0) +
+                      (j == q.ny - 1 ? yp : 0.0) + (j == 0 ? ym : 0.0) +
+                      (k == q.nz - 1 ? zp : 0.0) + (k == 0 ? zm : 0.0);
+    const double r0 = fv - s0;
+    const double phi =
+        tabbed ? tab[i] * tab[q.nx + j] * tab[q.nx + q.ny + k]
+               : sin(pi * (i + 1) / (q.nx + 1)) * sin(pi * (j + 1) / (q.ny + 1)) *
+                     sin(pi * (k + 1) / (q.nz + 1));
+    a0 += r0 * r0;
+    ac += r0 * phi;
+    ap += phi * phi;
+  }
+  const double t0 = block_sum(a0, red), tc = block_sum(ac, red), tp = block_sum(ap, red);
+  if (threadIdx.x == 0) {
+    out[3 * blockIdx.x] = t0;
+    out[3 * blockIdx.x + 1] = tc;
+    out[3 * blockIdx.x + 2] = tp;
+  }
+}
+
+// Bytes of the probe area at the head of a batched workspace.
+size_t probe_bytes(int n) {
+  return align_up(sizeof(ProbeIn) * n, 256) + align_up(3 * sizeof(double) * n, 256);
+}
+
+// Sweep estimates of every instance from one probe launch (synchronous).
+int batch_estimates(int n, const ms_instance* inst, double tol, char* area, hipStream_t s,
+                    std::vector<double>& est) {
+  std::vector<ProbeIn> h(n);
+  for (int i = 0; i < n; ++i) {
+    const ms_grid& g = inst[i].grid;
+    h[i] = ProbeIn{g.nx, g.ny, g.nz, 0, g.sy, g.sz, inst[i].x, inst[i].f};
+  }
+  ProbeIn* din = reinterpret_cast<ProbeIn*>(area);
+  double* dout = reinterpret_cast<double*>(area + align_up(sizeof(ProbeIn) * n, 256));
+  MS_HIP_TRY(hipMemcpyAsync(din, h.data(), sizeof(ProbeIn) * n, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(batch_probe_kernel, dim3(n), dim3(kBatchThreads), 0, s, din, dout);
+  MS_LAUNCH_CHECK();
+  std::vector<double> r(3 * (size_t)n);
+  MS_HIP_TRY(hipMemcpyAsync(r.data(), dout, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s));
+  MS_HIP_TRY(hipStreamSynchronize(s));
+  est.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const double c1 = r[3 * i + 2] > 0.0 ? std::fabs(r[3 * i + 1]) / std::sqrt(r[3 * i + 2]) : 0.0;
+    est[i] = est_sweeps(inst[i].grid, tol, std::sqrt(r[3 * i]), c1);
+  }
+  return MS_OK;
 }
 
 // Estimated solve time on a team of t blocks, in units of one block's time
@@ -542,17 +645,21 @@ ShapeRec lookup_shape(int prec, const ms_grid& g, int team) {
   return it->second;
 }
 
+// Largest team plan_teams gives an instance on a device of G blocks (sizes
+// the per-team tables, so a workspace does not depend on the plan).
+int team_cap(const ms_grid& g, int G) { return std::min(G, tiles_of(g) * kShapeZS[3]); }
+
 // Splits up to G blocks into teams, one block at a time to the instance
 // whose estimated finish time (est_time) is the longest and would shrink
 // with one more block -- greedy makespan balancing; every team has at least
 // one block and at most one per default tile split into the most z chunks.
 // Then lays the teams out XCD by XCD.
-void plan_teams(int n, const ms_instance* inst, double tol, int G, Plan& P) {
-  std::vector<double> cells(n), sweeps(n);
+void plan_teams(int n, const ms_instance* inst, const std::vector<double>& sweeps, int G,
+                Plan& P) {
+  std::vector<double> cells(n);
   for (int i = 0; i < n; ++i) {
     const ms_grid& g = inst[i].grid;
     cells[i] = (double)g.nx * g.ny * g.nz;
-    sweeps[i] = est_sweeps(g, tol);
   }
   P.team.assign(n, 1);
   int used = n;
@@ -616,6 +723,15 @@ size_t inst_bytes(const ms_grid& g, int mode, int team) {
   return t;
 }
 
+// Workspace of a batched solve on G blocks: the probe area, the instance
+// table, the block map and every instance's buffers with its largest team.
+size_t batch_bytes(int n, const ms_instance* inst, int mode, int G) {
+  size_t t = probe_bytes(n) + align_up(sizeof(Inst) * n, 256) +
+             align_up(sizeof(int) * 2 * (size_t)G, 256) + 256;
+  for (int i = 0; i < n; ++i) t += inst_bytes(inst[i].grid, mode, team_cap(inst[i].grid, G));
+  return t;
+}
+
 }  // namespace
 }  // namespace ms
 
@@ -660,11 +776,7 @@ extern "C" size_t jacobi_batched_workspace_bytes(int n, const ms_instance* inst,
   if (check_batch(n, inst, o)) return 0;
   const int G = resident_blocks();
   if (G <= 0) return 0;
-  Plan P;
-  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
-  size_t t = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
-  for (int i = 0; i < n; ++i) t += inst_bytes(inst[i].grid, o->precision, P.team[i]);
-  return t;
+  return batch_bytes(n, inst, o->precision, std::max(G, n));
 }
 
 extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
@@ -678,14 +790,16 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   if (G < n)
     return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: %d instances need %d resident "
                      "blocks, the device holds %d", n, n, G);
-  Plan P;
-  plan_teams(n, inst, o->rel_tol, G, P);
-  size_t need = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
-  for (int i = 0; i < n; ++i) need += inst_bytes(inst[i].grid, o->precision, P.team[i]);
+  const size_t need = batch_bytes(n, inst, o->precision, G);
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "jacobi_solve_batched: workspace needs %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws{static_cast<char*>(work), work_bytes};
+  std::vector<double> est;
+  if (int rc = batch_estimates(n, inst, o->rel_tol, ws.take<char>(probe_bytes(n)), s, est))
+    return rc;
+  Plan P;
+  plan_teams(n, inst, est, G, P);
   Inst* dinst = ws.take<Inst>(n);
   int* dmap = ws.take<int>(2 * (size_t)P.G);
   int* derr = ws.take<int>(64);
@@ -702,7 +816,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
     q.team = P.team[i];
     const ShapeRec sh = lookup_shape(o->precision, g, q.team);
     set_shape(q, sh.tx, sh.zs);
-    q.part = ws.take<double>(2 * (size_t)q.team);
+    q.part = ws.take<double>(2 * (size_t)team_cap(g, G));
     q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
     const size_t span = (size_t)field_span(g);
     if (o->precision == MS_SOLVE_F64) {
@@ -786,16 +900,146 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   return MS_OK;
 }
 
+extern "C" size_t jacobi_batched_plan_workspace_bytes(int n) {
+  return n < 1 ? 0 : probe_bytes(n);
+}
+
 extern "C" int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
-                                   int* team_sizes, int* grid_blocks) {
+                                   int* team_sizes, int* grid_blocks, double* est_sweeps,
+                                   void* work, size_t work_bytes, void* stream) {
   clear_error();
   if (int rc = check_batch(n, inst, o)) return rc;
   const int G = resident_blocks();
   if (G <= 0) return set_error(MS_EHIP, "jacobi_batched_plan: occupancy query failed");
+  if (!work || work_bytes < probe_bytes(n))
+    return set_error(MS_EWORKSPACE, "jacobi_batched_plan: workspace needs %zu bytes",
+                     probe_bytes(n));
+  std::vector<double> est;
+  if (int rc = batch_estimates(n, inst, o->rel_tol, static_cast<char*>(work),
+                               static_cast<hipStream_t>(stream), est))
+    return rc;
   Plan P;
-  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
+  plan_teams(n, inst, est, std::max(G, n), P);
   if (team_sizes) std::copy(P.team.begin(), P.team.end(), team_sizes);
   if (grid_blocks) *grid_blocks = P.G;
+  if (est_sweeps) std::copy(est.begin(), est.end(), est_sweeps);
+  return MS_OK;
+}
+
+// ------------------------------------------- batched solves on streams
+
+// The other way to run a batch: host worker threads, each with its own HIP
+// stream and workspace slice, take the instances in order of estimated work
+// (cells x estimated sweeps, longest first) and run each one as jacobi_solve
+// does (graph-replayed chunks, two sweeps per pass or red-black
+// Gauss-Seidel, FP64 or FP32-refined). Instances overlap on the device, so
+// small ones fill what large ones leave idle.
+
+namespace {
+
+size_t stream_slice_bytes(int n, const ms_instance* inst, const ms_solve_opts* o) {
+  size_t m = 0;
+  for (int i = 0; i < n; ++i)
+    m = std::max(m, align_up(jacobi_workspace_bytes(&inst[i].grid, o), 256));
+  return m;
+}
+
+int check_streams(int n, const ms_instance* inst, const ms_solve_opts* o, int workers) {
+  if (n < 1 || !inst) return set_error(MS_EINVAL, "jacobi_solve_batched_streams: no instances");
+  if (!o) return set_error(MS_EINVAL, "jacobi_solve_batched_streams: opts is NULL");
+  if (workers < 1 || workers > 64)
+    return set_error(MS_EINVAL, "jacobi_solve_batched_streams: workers must be in [1, 64]");
+  for (int i = 0; i < n; ++i) {
+    if (int rc = check_grid(&inst[i].grid, "jacobi_solve_batched_streams")) return rc;
+    if (!inst[i].x)
+      return set_error(MS_EINVAL, "jacobi_solve_batched_streams: instance %d has no x", i);
+    if (jacobi_workspace_bytes(&inst[i].grid, o) == 0) return MS_EINVAL;  // opts rejected
+  }
+  for (int i = 0; i < n; ++i) {
+    const size_t bi = (size_t)field_span(inst[i].grid) * 8;
+    for (int j = 0; j < i; ++j) {
+      const size_t bj = (size_t)field_span(inst[j].grid) * 8;
+      if (overlaps(inst[i].x, bi, inst[j].x, bj))
+        return set_error(MS_EINVAL, "jacobi_solve_batched_streams: instances %d and %d overlap",
+                         j, i);
+    }
+  }
+  return MS_OK;
+}
+
+}  // namespace
+
+extern "C" size_t jacobi_batched_streams_workspace_bytes(int n, const ms_instance* inst,
+                                                         const ms_solve_opts* o, int workers) {
+  if (check_streams(n, inst, o, workers)) return 0;
+  return probe_bytes(n) + (size_t)workers * stream_slice_bytes(n, inst, o);
+}
+
+extern "C" int jacobi_solve_batched_streams(int n, const ms_instance* inst,
+                                            const ms_solve_opts* o, int workers, void* work,
+                                            size_t work_bytes, ms_solve_result* res,
+                                            void* stream) {
+  clear_error();
+  if (int rc = check_streams(n, inst, o, workers)) return rc;
+  if (!res) return set_error(MS_EINVAL, "jacobi_solve_batched_streams: res is NULL");
+  const size_t slice = stream_slice_bytes(n, inst, o);
+  const size_t need = probe_bytes(n) + (size_t)workers * slice;
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "jacobi_solve_batched_streams: workspace needs %zu bytes",
+                     need);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(work);
+  std::vector<double> est;
+  if (int rc = batch_estimates(n, inst, o->rel_tol, base, s, est)) return rc;
+  std::vector<int> order(n);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    const ms_grid &ga = inst[a].grid, &gb = inst[b].grid;
+    return (double)ga.nx * ga.ny * ga.nz * est[a] > (double)gb.nx * gb.ny * gb.nz * est[b];
+  });
+  int dev = 0;
+  MS_HIP_TRY(hipGetDevice(&dev));
+  std::atomic<int> next{0};
+  std::vector<int> rcs(n, MS_OK);
+  std::vector<std::string> msgs(n);
+  std::vector<int> setup_rc(workers, MS_OK);
+  auto worker = [&](int w) {
+    hipStream_t ws = nullptr;
+    if (hipSetDevice(dev) != hipSuccess ||
+        hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) {
+      setup_rc[w] = MS_EHIP;
+      return;
+    }
+    char* mine = base + probe_bytes(n) + (size_t)w * slice;
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      const int i = order[k];
+      res[i] = ms_solve_result{};
+      rcs[i] = jacobi_solve(&inst[i].grid, o, inst[i].x, inst[i].f, mine, slice, nullptr,
+                            &res[i], ws);
+      if (rcs[i] != MS_OK) msgs[i] = ms_last_error();
+    }
+    (void)hipStreamDestroy(ws);
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(workers);
+  for (int w = 0; w < workers; ++w) pool.emplace_back(worker, w);
+  for (auto& t : pool) t.join();
+  for (int w = 0; w < workers; ++w)
+    if (setup_rc[w]) return set_error(MS_EHIP, "jacobi_solve_batched_streams: stream setup failed");
+  int worst = MS_OK;
+  for (int i = 0; i < n; ++i) {
+    const int rc = rcs[i];
+    if (rc != MS_OK && rc != MS_NOT_CONVERGED && rc != MS_ENONFINITE)
+      return set_error(rc, "jacobi_solve_batched_streams: instance %d: %s", i, msgs[i].c_str());
+    if (rc == MS_ENONFINITE) worst = MS_ENONFINITE;
+    else if (rc == MS_NOT_CONVERGED && worst == MS_OK) worst = MS_NOT_CONVERGED;
+  }
+  if (worst == MS_ENONFINITE)
+    return set_error(worst, "jacobi_solve_batched_streams: non-finite norm");
+  if (worst == MS_NOT_CONVERGED)
+    return set_error(worst, "jacobi_solve_batched_streams: an instance did not converge");
   return MS_OK;
 }
 
@@ -808,6 +1052,13 @@ size_t tune_inst_bytes(const ms_grid& g, int team) {
   return align_up(2 * (size_t)team * sizeof(double), 256) + 256 + 2 * align_up(span * 8, 256);
 }
 
+size_t tune_bytes(int n, const ms_instance* inst, int G) {
+  size_t t = probe_bytes(n) + align_up(sizeof(Inst) * n, 256) +
+             align_up(sizeof(int) * 2 * (size_t)G, 256) + 256;
+  for (int i = 0; i < n; ++i) t += tune_inst_bytes(inst[i].grid, team_cap(inst[i].grid, G));
+  return t;
+}
+
 }  // namespace
 
 extern "C" size_t jacobi_batched_autotune_workspace_bytes(int n, const ms_instance* inst,
@@ -815,11 +1066,7 @@ extern "C" size_t jacobi_batched_autotune_workspace_bytes(int n, const ms_instan
   if (check_batch(n, inst, o)) return 0;
   const int G = resident_blocks();
   if (G <= 0) return 0;
-  Plan P;
-  plan_teams(n, inst, o->rel_tol, std::max(G, n), P);
-  size_t t = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
-  for (int i = 0; i < n; ++i) t += tune_inst_bytes(inst[i].grid, P.team[i]);
-  return t;
+  return tune_bytes(n, inst, std::max(G, n));
 }
 
 extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_solve_opts* o,
@@ -836,17 +1083,19 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
   if (G < n)
     return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: %d instances need %d resident "
                      "blocks, the device holds %d", n, n, G);
-  Plan P;
-  plan_teams(n, inst, o->rel_tol, G, P);
-  if (P.G > Gt)
-    return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: the timing kernel holds only %d "
-                     "resident blocks, the plan has %d", Gt, P.G);
-  size_t need = align_up(sizeof(Inst) * n, 256) + align_up(sizeof(int) * 2 * P.G, 256) + 256;
-  for (int i = 0; i < n; ++i) need += tune_inst_bytes(inst[i].grid, P.team[i]);
+  const size_t need = tune_bytes(n, inst, G);
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "jacobi_batched_autotune: workspace needs %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws{static_cast<char*>(work), work_bytes};
+  std::vector<double> est;
+  if (int rc = batch_estimates(n, inst, o->rel_tol, ws.take<char>(probe_bytes(n)), s, est))
+    return rc;
+  Plan P;
+  plan_teams(n, inst, est, G, P);
+  if (P.G > Gt)
+    return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: the timing kernel holds only %d "
+                     "resident blocks, the plan has %d", Gt, P.G);
   Inst* dinst = ws.take<Inst>(n);
   int* dmap = ws.take<int>(2 * (size_t)P.G);
   int* derr = ws.take<int>(64);
@@ -860,7 +1109,7 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
     q.f = inst[i].f;  // read only (FP64 trials)
     q.team0 = P.first[i];
     q.team = P.team[i];
-    q.part = ws.take<double>(2 * (size_t)q.team);
+    q.part = ws.take<double>(2 * (size_t)team_cap(g, G));
     q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
     const size_t span = (size_t)field_span(g);
     double* A = ws.take<double>(span);

@@ -2,6 +2,7 @@
 against single-instance solves."""
 
 import numpy as np
+import torch
 import pytest
 
 import oracle
@@ -173,3 +174,81 @@ def test_full_batch_of_64_uneven_instances_after_autotuning():
         s = ms.jacobi_solve(single, dev(f), **opts)
         assert (s.sweeps, s.outer_iters) == (infos[i].sweeps, infos[i].outer_iters)
         assert np.array_equal(host(single), host(xs[i]))
+
+
+def test_plan_estimates_follow_the_slowest_mode_component():
+    """The planner's sweep estimate is ln(tol ||r(u^0)|| / c1) / ln(rho), c1
+    the starting residual's component along the slowest mode, kept within
+    [1/10, 1] of ln(tol) / ln(rho), with r the residual of the zero-interior
+    start: recomputed here from the oracle's residual, for an eigenmode
+    right-hand side (c1 = ||r||: the bound), a Gaussian one with a random
+    halo, a nonzero interior (ignored) and a problem already solved."""
+    import math
+    note("case: batched plan estimates")
+    tol = 1e-8
+    dims = [(20, 16, 12), (33, 17, 9), (24, 24, 24), (10, 9, 8)]
+    probs = []
+    phi = synth.eigenmode(*dims[0])
+    f0 = np.zeros_like(phi)
+    f0[1:-1, 1:-1, 1:-1] = phi[1:-1, 1:-1, 1:-1]
+    probs.append((synth.zeros(*dims[0]), f0))
+    probs.append((synth.dirichlet_uniform(*dims[1], 3), synth.gaussian_sources(*dims[1], 4, 4)))
+    u2 = synth.zeros(*dims[2])
+    u2[1:-1, 1:-1, 1:-1] = synth.rng(5).standard_normal((24, 24, 24)) * 1e-3
+    probs.append((u2, synth.gaussian_sources(*dims[2], 6, 6)))
+    probs.append((synth.zeros(*dims[3]), np.zeros_like(synth.zeros(*dims[3]))))
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    _, _, est = ms.batched_plan(xs, fs, with_estimates=True,
+                                precision=ms.MS_SOLVE_F32_REFINED, rel_tol=tol)
+    for (u, f), (nx, ny, nz), e in zip(probs, dims, est):
+        rho = sum(math.cos(math.pi / (n + 1)) for n in (nx, ny, nz)) / 3.0
+        upper = max(math.log(tol) / math.log(rho), 1.0)
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        if res0 == 0.0:
+            assert e == 1.0
+            continue
+        p1 = synth.eigenmode(nx, ny, nz)[1:-1, 1:-1, 1:-1]
+        r = oracle.residual(oracle.zero_interior(u), f)
+        c1 = abs(float((r * p1).sum())) / float(np.linalg.norm(p1))
+        want = min(upper, max(math.log(tol * res0 / c1) / math.log(rho), upper / 10, 1.0))
+        assert e == pytest.approx(want, rel=1e-9), (nx, ny, nz)
+    assert est[0] == pytest.approx(
+        math.log(tol) / math.log(sum(math.cos(math.pi / (n + 1)) for n in dims[0]) / 3.0),
+        rel=1e-9)
+
+
+@pytest.mark.parametrize("workers", [1, 3])
+@pytest.mark.parametrize("kw", [dict(precision=ms.MS_SOLVE_F32_REFINED),
+                                dict(precision=ms.MS_SOLVE_F64),
+                                dict(precision=ms.MS_SOLVE_F64, method=ms.MS_METHOD_RBGS)],
+                         ids=["f32r", "f64", "f64-rbgs"])
+def test_stream_batch_equals_single_solves(workers, kw):
+    """Instances solved on concurrent streams give what jacobi_solve gives
+    one at a time: the same fields bit for bit and the same counts."""
+    note(f"case: stream batch workers={workers} {kw}")
+    dims = [(40, 30, 20), (9, 7, 5), (64, 33, 17), (20, 20, 20), (5, 60, 9), (33, 9, 41)]
+    probs = _instances(dims, 700, halo=True)
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    infos = ms.jacobi_solve_batched_streams(xs, fs, workers=workers, rel_tol=1e-8, **kw)
+    for (u, f), x, info in zip(probs, xs, infos):
+        y = dev(u)
+        ref = ms.jacobi_solve(y, dev(f), rel_tol=1e-8, **kw)
+        assert (info.sweeps, info.outer_iters, info.status) == (ref.sweeps, ref.outer_iters,
+                                                                 ref.status)
+        assert torch.equal(x, y)
+
+
+def test_stream_batch_reports_a_nonfinite_instance_and_solves_the_rest():
+    dims = [(12, 10, 8), (16, 9, 7), (8, 8, 8)]
+    probs = _instances(dims, 800)
+    probs[1][1][3, 4, 5] = np.nan
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    with pytest.raises(ms.MsError) as e:
+        ms.jacobi_solve_batched_streams(xs, fs, workers=2, rel_tol=1e-8)
+    assert e.value.code == ms.MS_ENONFINITE
+    for (u, f), x in zip([probs[0], probs[2]], [xs[0], xs[2]]):
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        assert oracle.residual_norm(host(x), f) <= 1e-8 * res0 * (1 + 1e-9)
