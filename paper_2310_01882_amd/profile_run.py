@@ -2,7 +2,7 @@
 
     python -m paper_2310_01882_amd.profile_run sweep   [--dtype f64|f32] [--sweeps N] [--tb 1|2] [--rb]
     python -m paper_2310_01882_amd.profile_run advect  [--passes N]
-    python -m paper_2310_01882_amd.profile_run batched
+    python -m paper_2310_01882_amd.profile_run batched [--streams W]
     python -m paper_2310_01882_amd.profile_run cnn     [--steps N]
     python -m paper_2310_01882_amd.profile_run jit     [--program jacobi|advection] [--passes N]
     python -m paper_2310_01882_amd.profile_run copy    [--mib M]
@@ -13,7 +13,8 @@ benchmark uses (--tb 2: two sweeps per pass; --rb: red-black Gauss-Seidel
 sweeps instead). `advect` runs N passes of the
 512 x 512 x 256 advection term. `batched` autotunes and then solves the
 benchmark's batch (64 instances, sizes log-uniform in [32, 256], seed 4,
-FP32-refined to 1e-8) once. `cnn` runs N training steps (forward, backward,
+FP32-refined to 1e-8) once (--streams W: on W concurrent streams instead,
+without the autotuning). `cnn` runs N training steps (forward, backward,
 Adam) of the warm-start network on a 128^3 instance. `jit` compiles the
 Jacobi (or advection) program of the stencil-program language and runs it N
 times on the sweep (or advection) input. `copy` is the
@@ -44,6 +45,7 @@ def main():
     ap.add_argument("--passes", type=int, default=5)
     ap.add_argument("--mib", type=int, default=1024)
     ap.add_argument("--program", default="jacobi", choices=["jacobi", "advection"])
+    ap.add_argument("--streams", type=int, default=0)
     ap.add_argument("--n", type=int, default=512)
     args = ap.parse_args()
 
@@ -82,6 +84,11 @@ def main():
         xs = [ms.field_from(synth.zeros(*d)) for d in dims]
         fs = [ms.field_from(synth.gaussian_sources(*d, 8, 1000 + i)) for i, d in enumerate(dims)]
         opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, max_outer=40)
+        if args.streams > 0:
+            infos = ms.jacobi_solve_batched_streams(xs, fs, workers=args.streams, **opts)
+            print(f"batched solve on {args.streams} streams done: "
+                  f"{sum(i.sweeps for i in infos)} inner sweeps", flush=True)
+            return
         ms.batched_autotune(xs, fs, sweeps_per_trial=20, **opts)
         print("batched autotune done", flush=True)
         infos = ms.jacobi_solve_batched(xs, fs, **opts)
