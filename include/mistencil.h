@@ -195,6 +195,30 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
                      double* res_dev, void* work, size_t work_bytes,
                      void* stream);
 
+/* ---- Jacobi sweeps on a field held in host memory -------------------------
+ * Exactly n >= 0 sweeps of jacobi_sweeps on a field that stays in host
+ * memory (Section 4.3's data management taken to fields larger than the
+ * device holds): u, u_tmp and f (f may be NULL) are HOST pointers with the
+ * layout of grid g (page-locked memory, as from hipHostMalloc, lets copies
+ * overlap the sweeps); both u and u_tmp carry the Dirichlet halo. The field
+ * is cut into z slabs of slab_planes interior planes; each pass uploads a
+ * slab with sweeps_per_pass (T) extra planes on either side, runs T sweeps
+ * on the device and downloads the slab's own planes, so every value is
+ * bit-identical to jacobi_sweeps. Passes alternate between u and u_tmp: the
+ * result lands in u if ceil(n / min(T, nz)) is even, else in u_tmp. Two internal
+ * streams (default priority) overlap one slab's copies with another's
+ * sweeps. No residual norms. work: device, at least
+ * jacobi_sweeps_streamed_workspace_bytes(g, dtype, T, slab_planes) bytes
+ * (two sets of three slab buffers of slab_planes + 2T + 2 planes). Blocks
+ * until done (synchronises `stream` first). T in [1, 4096], slab_planes
+ * >= 1. */
+size_t jacobi_sweeps_streamed_workspace_bytes(const ms_grid* g, int dtype,
+                                              int sweeps_per_pass, int slab_planes);
+int jacobi_sweeps_streamed(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                           const void* f, int64_t n, int sweeps_per_pass,
+                           int slab_planes, void* work, size_t work_bytes,
+                           void* stream);
+
 /* ---- fixed number of red-black Gauss-Seidel sweeps ----------------------
  * The Section 4.1 benchmark is a Gauss-Seidel iteration of the same 7-point
  * stencil; its in-place, lexicographic form is sequential, so this is the

@@ -111,6 +111,9 @@ SIGNATURES = {
     "jacobi_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "jacobi_sweeps_tb": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _P, _P, _SZ, _P]),
     "rbgs_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
+    "jacobi_sweeps_streamed_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), _I, _I, _I]),
+    "jacobi_sweeps_streamed": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _I, _P, _SZ,
+                                    _P]),
     "ms_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "jacobi_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts)]),
     "jacobi_solve": (_I, [ctypes.POINTER(Grid), ctypes.POINTER(SolveOpts), _P, _P, _P, _SZ,
@@ -360,6 +363,32 @@ def rbgs_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):
     _check(lib.rbgs_sweeps(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp), _ptr(f), int(n),
                            _ptr(res), _ptr(work), work.numel(), _stream(stream)))
     return u if n % 2 == 0 else u_tmp
+
+
+def jacobi_sweeps_streamed(u, u_tmp, n, f=None, sweeps_per_pass=16, slab_planes=64,
+                           work=None, stream=None):
+    """Exactly ``n`` Jacobi sweeps of a field held in host memory (``u``,
+    ``u_tmp``, ``f``: CPU tensors of one layout, pinned for overlap), in z
+    slabs of ``slab_planes`` planes with ``sweeps_per_pass`` sweeps per trip
+    through the device; returns the tensor holding u_n."""
+    for name, t in (("u", u), ("u_tmp", u_tmp)) + ((("f", f),) if f is not None else ()):
+        if t.device.type != "cpu" or t.dim() != 3 or t.stride(2) != 1:
+            raise ValueError(f"{name} must be a 3-D host tensor with unit x stride")
+        if t.dtype != u.dtype or t.shape != u.shape or t.stride() != u.stride():
+            raise ValueError(f"{name} must share u's dtype, shape and strides")
+    g = grid_of(u)
+    code = MS_F64 if u.dtype == torch.float64 else MS_F32
+    if work is None:
+        nbytes = lib.jacobi_sweeps_streamed_workspace_bytes(ctypes.byref(g), code,
+                                                            int(sweeps_per_pass), int(slab_planes))
+        if nbytes == 0:
+            raise MsError(MS_EINVAL, last_error())
+        work = _workspace(nbytes, torch.device("cuda"))
+    _check(lib.jacobi_sweeps_streamed(ctypes.byref(g), code, _ptr(u), _ptr(u_tmp), _ptr(f), int(n),
+                                      int(sweeps_per_pass), int(slab_planes), _ptr(work),
+                                      work.numel(), _stream(stream)))
+    passes = -(-int(n) // min(int(sweeps_per_pass), u.shape[0] - 2)) if n > 0 else 0
+    return u if passes % 2 == 0 else u_tmp
 
 
 @dataclass
