@@ -193,3 +193,59 @@ def test_sweep_shape_query_follows_the_tuning_table_and_alignment():
     m = shape(aligned[:3] + [aligned[3] + 4])
     assert m.vec_ok == 1 and m.us_per_sweep == 0.0
     ms.tuning_clear()
+
+
+def test_red_black_and_solve_method_validation():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    assert ms.lib.rbgs_sweeps(ctypes.byref(g), 7, FAKE, FAKE2, None, 1, None, FAKE, 1 << 20,
+                              None) == ms.MS_EUNSUPPORTED
+    assert ms.lib.rbgs_sweeps(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, -1, None, FAKE,
+                              1 << 20, None) == ms.MS_EINVAL
+    assert ms.lib.rbgs_sweeps(ctypes.byref(g), ms.MS_F64, FAKE, FAKE, None, 1, None, FAKE,
+                              1 << 20, None) == ms.MS_EINVAL  # u and u_tmp overlap
+    o = ms.solve_opts(method=5)
+    assert ms.lib.jacobi_workspace_bytes(ctypes.byref(g), ctypes.byref(o)) == 0
+    assert "method" in ms.last_error()
+    assert ms.lib.jacobi_workspace_bytes(ctypes.byref(g),
+                                         ctypes.byref(ms.solve_opts(method=ms.MS_METHOD_RBGS))) > 0
+
+
+def test_streamed_sweeps_validation():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    ws = ms.lib.jacobi_sweeps_streamed_workspace_bytes
+    assert ws(ctypes.byref(g), ms.MS_F64, 0, 4) == 0  # sweeps_per_pass < 1
+    assert ws(ctypes.byref(g), ms.MS_F64, 2, 0) == 0  # slab_planes < 1
+    need = ws(ctypes.byref(g), ms.MS_F64, 2, 2)
+    # two sets of three slab buffers of S + 2T + 2 planes, plus partial tables
+    assert need >= 2 * 3 * (2 + 4 + 2) * g.sz * 8
+    assert ws(ctypes.byref(g), ms.MS_F32, 2, 2) < need
+    call = ms.lib.jacobi_sweeps_streamed
+    assert call(ctypes.byref(g), ms.MS_F64, FAKE, FAKE, None, 3, 2, 2, FAKE, need,
+                None) == ms.MS_EINVAL  # u and u_tmp overlap
+    assert call(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, 3, 2, 2, FAKE, need - 1,
+                None) == ms.MS_EWORKSPACE
+    assert call(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, -1, 2, 2, FAKE, need,
+                None) == ms.MS_EINVAL
+
+
+def test_stream_batch_validation():
+    import paper_2310_01882_amd as ms
+    arr = (ms.Instance * 2)()
+    for n in range(2):
+        arr[n].grid = _grid(ms)
+        arr[n].x = 0x100000 * (n + 1)
+    o = ms.solve_opts()
+    ws = ms.lib.jacobi_batched_streams_workspace_bytes
+    assert ws(2, arr, ctypes.byref(o), 0) == 0  # workers < 1
+    one = ms.lib.jacobi_workspace_bytes(ctypes.byref(arr[0].grid), ctypes.byref(o))
+    assert ws(2, arr, ctypes.byref(o), 4) >= 4 * one
+    res = (ms.SolveResult * 2)()
+    assert ms.lib.jacobi_solve_batched_streams(2, arr, ctypes.byref(o), 65, FAKE, 1 << 30, res,
+                                               None) == ms.MS_EINVAL
+    arr[1].x = arr[0].x  # overlapping instances
+    assert ms.lib.jacobi_solve_batched_streams(2, arr, ctypes.byref(o), 2, FAKE, 1 << 30, res,
+                                               None) == ms.MS_EINVAL
+    assert ms.lib.jacobi_batched_plan_workspace_bytes(2) > 0
+    assert ms.lib.jacobi_batched_plan_workspace_bytes(0) == 0
