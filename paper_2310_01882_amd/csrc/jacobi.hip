@@ -20,6 +20,11 @@
 //   V = 2 (FP64) makes each row access one 1 KiB dwordx4 wave load.
 // * LDS-tiled: a block stages the current plane of a 64 x 4R tile plus its
 //   ring in LDS (double-buffered, one barrier per plane).
+//
+// Two-stage passes (further down) apply two sweeps per pass over memory, or
+// one red-black Gauss-Seidel sweep (red half, then black half), in two
+// layouts: LDS-staged 64 x 8 tiles (sweep_tb2_kernel) and one column per
+// lane (sweep_tbw_kernel).
 #include "ms_internal.hpp"
 
 // Bit-exact parity with the oracle needs every operation rounded on its own.
