@@ -167,3 +167,33 @@ def test_vector_kernel_on_aligned_fields_with_ragged_tails(dtype, dims, which, m
     torch.cuda.synchronize()
     for a, b in zip(outs, outs2):
         assert torch.equal(a[1:-1, 1:-1, 1:-1], b[1:-1, 1:-1, 1:-1])
+
+
+@pytest.mark.parametrize("text,params,nprof", [
+    ("param c; out o = c * 2;", [1.5], 0),
+    ("profile t; out o = t - 1;", [], 1),
+    ("field a; out o = a[0,0,1] - a[0,0,-1];", [], 0),
+    ("field a, b; param p; out o = p; out q = b[1,1,1] / (2 + a * a);", [0.25], 0),
+])
+@pytest.mark.parametrize("aligned", [True, False])
+def test_programs_without_some_kinds_of_inputs(text, params, nprof, aligned):
+    """Programs with no fields, only a profile, z offsets only, or an output
+    that reads nothing: both kernels (aligned fields take the vector one)."""
+    note(f"case: jit {text!r} aligned={aligned}")
+    dims = (300, 5, 7)
+    prog = sl.parse(text)
+    arrays = [_field(*dims, 60 + n) for n in range(len(prog["fields"]))]
+    prof = [np.linspace(0.5, 2.0, dims[2])] * nprof
+    j = ms.JitStencil(text)
+    if aligned:
+        ins = [ms.field_from(a) for a in arrays]
+        outs = [ms.alloc_field(*dims) for _ in j.outputs]
+    else:
+        ins = [dev(a) for a in arrays]
+        outs = [empty_like_layout(dev(synth.zeros(*dims))) for _ in j.outputs]
+    profs = [torch.from_numpy(np.ascontiguousarray(p)).cuda() for p in prof]
+    j.apply(ins, outs, params, profs)
+    torch.cuda.synchronize()
+    want = sl.run(text, arrays, params, prof, interior_shape=dims[::-1])
+    for o, w_ in zip(outs, want):
+        assert np.array_equal(host(o)[1:-1, 1:-1, 1:-1], w_)
