@@ -490,7 +490,8 @@ int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, const void* w,
 int conv3d_bf16_dgrad(int X, int Y, int Z, int cin, const void* dout, const void* wd,
                       const void* mask, void* din, void* stream);
 /* dw[t][co][ci] = sum_v dpre[v][co] in[v + d_t][ci], db[co] = sum_v dpre[v][co]
- * (FP32, deterministic two-pass reduction through `work`). */
+ * over interior voxels v (FP32, deterministic two-pass reduction through
+ * `work`). The halo of dpre is not read; that of `in` must be zero. */
 size_t conv3d_bf16_wgrad_workspace_bytes(int cin);
 int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, const void* dpre,
                       float* dw, float* db, void* work, size_t work_bytes, void* stream);

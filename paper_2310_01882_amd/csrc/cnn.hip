@@ -18,9 +18,10 @@
 //  * dgrad:    A = output gradient at voxel - tap offset, B = W[tap][ci][co];
 //    epilogue multiplies by the ReLU mask of the layer input (post > 0).
 //  * wgrad:    dW[tap][co][ci] = sum over voxels of dPre[v][co] in[v+d][ci];
-//    M = co, N = ci, K = 16 voxels per step, operands transposed through
-//    LDS; each wave owns up to 7 taps; per-block partials are summed by a
-//    second kernel in a fixed order (deterministic).
+//    M = co, N = ci (or, for 8 input channels, N = (dx, ci)), K = voxels
+//    in steps of 16, operands staged and transposed through LDS, block tasks
+//    of 32 voxels x 4 rows; per-block partials are summed by a second kernel
+//    in a fixed order (deterministic).
 #include "ms_internal.hpp"
 
 #include <hip/hip_bf16.h>
@@ -414,6 +415,323 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgK a) {
   if (w == 0 && h == 0) out[kTaps * kCo * CIN + m] = dbacc;
 }
 
+// ---------------------------------------------- row-blocked 32-channel wgrad
+//
+// Weight gradient of a layer with 32 input channels. A block task is 32
+// voxels along x on kWgRows consecutive rows y0.. of one z level: K = 128
+// voxels, eight MFMA K-steps of 16. The block stages the task's dPre rows and
+// the input rows they reach (3 dz x (kWgRows + 2) rows of 34 voxels, from
+// x0 - 1) in LDS; the next task's chunks are loaded into registers while the
+// current task computes, so one barrier pair serves 7 x 8 MFMAs per wave.
+// Taps are split so that a wave owns whole (dy, dz) rows of three dx taps:
+// wave w takes rows 2w and 2w + 1 (taps 6w .. 6w + 5) and, for w < 3, tap
+// 24 + w of row 8. For a row, lane (ci, h) reads the 10 input voxels
+// 16kk + 8h + j (j = 0..9) of its channel once and forms the operands of
+// dx = -1, 0, 1 from the windows j = e + dx + 1. A = dPre[16kk + 8h + e][co]
+// is read once per K-step and shared by the wave's taps; wave 3 (six taps)
+// also multiplies it by a ones column, which sums dPre for the bias.
+//
+// LDS voxel slots are 64 bytes with 64 bytes of padding after every 8
+// voxels: the two lane halves read voxels 8 apart, 576 bytes, i.e. disjoint
+// bank ranges. dPre values of voxels past X or rows past Y are stored as
+// zero (their loads are clamped into the interior), so the dPre halo is never
+// read; input loads are clamped into the input's zero halo.
+constexpr int kWgRows = 4;
+constexpr int kWgVox = 32;
+constexpr int kWgInVox = kWgVox + 2;
+__host__ __device__ constexpr int wg_slot(int x) { return 32 * x + 32 * (x >> 3); }
+constexpr int kWgDpRow = wg_slot(kWgVox - 1) + 32;    // bf16 elements per dPre row
+constexpr int kWgInRow = wg_slot(kWgInVox - 1) + 32;  // per input row
+constexpr int kWgInRows = 3 * (kWgRows + 2);
+constexpr int kWgDpChunks = kWgRows * kWgVox * 4;         // 16-byte chunks per task
+constexpr int kWgInChunks = kWgInRows * kWgInVox * 4;
+constexpr int kWgChunks = kWgDpChunks + kWgInChunks;
+constexpr int kWgPerThread = (kWgChunks + 255) / 256;
+static_assert(kWgDpChunks % 256 == 0, "dPre chunks fill whole load rounds");
+constexpr int kWgBlocks = 512;
+
+// Tasks of a block: blocks are dispatched round-robin over the XCDs (8, each
+// with its own L2), so XCD k = b % 8 gets the contiguous task range
+// [k ntask / 8, (k + 1) ntask / 8), walked by its blocks in stride. The
+// blocks of one XCD then work on neighbouring rows and planes at the same
+// time and share their halo rows in that XCD's L2.
+struct TaskWalk {
+  int first, step, end;
+};
+__device__ __forceinline__ TaskWalk xcd_tasks(int ntask) {
+  const int G = min(8, (int)gridDim.x);
+  const int k = blockIdx.x % G, slot = blockIdx.x / G;
+  const int nk = ((int)gridDim.x - k + G - 1) / G;  // blocks of group k
+  return {(int)((int64_t)k * ntask / G) + slot, nk, (int)((int64_t)(k + 1) * ntask / G)};
+}
+
+struct WgRowK {
+  Vol v;
+  const bf16* in;    // C = 32
+  const bf16* dpre;  // C = 32
+  float* part;       // per block: [27][32][32] then [32] bias
+  int ntask;         // (X/32 rounded up) * (Y/kWgRows rounded up) * Z
+};
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_wgrad_rows_kernel(WgRowK a) {
+  constexpr int C = 32, R = kWgRows;
+  __shared__ __attribute__((aligned(16))) bf16 dp[R * kWgDpRow];
+  __shared__ __attribute__((aligned(16))) bf16 inr[kWgInRows * kWgInRow];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + kWgVox - 1) / kWgVox, sy = (a.v.Y + R - 1) / R;
+  bf16x8 pre[kWgPerThread];
+  auto origin = [&](int t, int& x0, int& y0, int& z) {
+    x0 = (t % sx) * kWgVox;
+    y0 = ((t / sx) % sy) * R;
+    z = t / (sx * sy);
+  };
+  // Chunk e < kWgDpChunks: dPre row e / 128, voxel (e % 128) / 4, channels
+  // 8 (e % 4). Otherwise input row ri = e' / 136 (dz = ri / (R+2) - 1, row
+  // y0 - 1 + ri % (R+2)), voxel x0 - 1 + (e' % 136) / 4.
+  auto load_task = [&](int t) {
+    int x0, y0, z;
+    origin(t, x0, y0, z);
+#pragma unroll
+    for (int q = 0; q < kWgPerThread; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (q * 256 + 255 >= kWgChunks && e >= kWgChunks) continue;
+      const int c8 = (e & 3) * 8;
+      int64_t p;
+      if (q * 256 < kWgDpChunks) {
+        const int x = min(x0 + (e % (kWgVox * 4)) / 4, a.v.X - 1);
+        const int y = min(y0 + e / (kWgVox * 4), a.v.Y - 1);
+        p = a.v.vox(x, y, z) * C + c8;
+        pre[q] = *reinterpret_cast<const bf16x8*>(a.dpre + p);
+      } else {
+        const int f = e - kWgDpChunks, ri = f / (kWgInVox * 4);
+        const int x = min(x0 - 1 + (f % (kWgInVox * 4)) / 4, a.v.X);
+        const int y = min(y0 - 1 + ri % (R + 2), a.v.Y);
+        p = a.v.vox(x, y, z + ri / (R + 2) - 1) * C + c8;
+        pre[q] = *reinterpret_cast<const bf16x8*>(a.in + p);
+      }
+    }
+  };
+  auto store_task = [&](int t) {
+    int x0, y0, z;
+    origin(t, x0, y0, z);
+#pragma unroll
+    for (int q = 0; q < kWgPerThread; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (q * 256 + 255 >= kWgChunks && e >= kWgChunks) continue;
+      const int c8 = (e & 3) * 8;
+      if (q * 256 < kWgDpChunks) {
+        const int r = e / (kWgVox * 4), vx = (e % (kWgVox * 4)) / 4;
+        const bool ok = x0 + vx < a.v.X && y0 + r < a.v.Y;
+        *reinterpret_cast<bf16x8*>(&dp[r * kWgDpRow + wg_slot(vx) + c8]) = ok ? pre[q] : zero8();
+      } else {
+        const int f = e - kWgDpChunks, ri = f / (kWgInVox * 4), vx = (f % (kWgInVox * 4)) / 4;
+        *reinterpret_cast<bf16x8*>(&inr[ri * kWgInRow + wg_slot(vx) + c8]) = pre[q];
+      }
+    }
+  };
+  f32x16 acc[7];
+#pragma unroll
+  for (int q = 0; q < 7; ++q) acc[q] = f32x16{};
+  bf16x8 ones;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) ones[e] = (bf16)1.0f;
+  // the wave's full rows (dy, dz) and its single tap of row 8 (dx = w - 1)
+  const int rowA = 2 * w, rowB = 2 * w + 1;
+  const bool extra = w < 3;
+  const TaskWalk tw = xcd_tasks(a.ntask);
+  load_task(min(tw.first, a.ntask - 1));
+  for (int t = tw.first; t < tw.end; t += tw.step) {
+    __syncthreads();  // the previous task's LDS reads are done
+    store_task(t);
+    __syncthreads();
+    load_task(min(t + tw.step, a.ntask - 1));  // in flight while this task computes
+#pragma unroll 1
+    for (int r = 0; r < R; ++r)
+#pragma unroll 1
+      for (int kk = 0; kk < 2; ++kk) {
+        const int vb = 16 * kk + 8 * h;  // first voxel of the lane's K-slice
+        bf16x8 av;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const int row = half ? rowB : rowA;
+          const int dz = row / 3 - 1, dy = row % 3 - 1;
+          const bf16* src = &inr[((dz + 1) * (R + 2) + r + 1 + dy) * kWgInRow + m];
+          bf16 s[10];
+#pragma unroll
+          for (int j = 0; j < 10; ++j) s[j] = src[wg_slot(vb + j)];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            bf16x8 bv;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) bv[e] = s[e + d];
+            acc[3 * half + d] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[3 * half + d], 0, 0, 0);
+          }
+        }
+        if (extra) {
+          // row 8: dz = dy = +1, dx = w - 1
+          const bf16* src = &inr[(2 * (R + 2) + r + 2) * kWgInRow + m];
+          bf16x8 bv;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) bv[e] = src[wg_slot(vb + e + w)];
+          acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[6], 0, 0, 0);
+        } else {
+          // wave 3 (six taps) sums dPre over the voxels: A times a ones column
+          acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, ones, acc[6], 0, 0, 0);
+        }
+      }
+  }
+  // block partials: D[i = co][j = ci]
+  float* out = a.part + (int64_t)blockIdx.x * (kTaps * kCo * C + kCo);
+#pragma unroll
+  for (int q = 0; q < 7; ++q) {
+    if (q == 6 && !extra) break;
+    const int t = q < 6 ? 6 * w + q : 24 + w;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int co = 8 * (r / 4) + 4 * h + (r % 4);
+      out[(t * kCo + co) * C + m] = acc[q][r];
+    }
+  }
+  // bias: every column of wave 3's last accumulator holds sum_v dPre[v][co]
+  if (!extra && m == 0) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) out[kTaps * kCo * C + 8 * (r / 4) + 4 * h + (r % 4)] = acc[6][r];
+  }
+}
+
+// ------------------------------------------ row-blocked 8-channel wgrad
+//
+// Weight gradient of the first layer (8 input channels: the two features
+// and six zero channels), on the tasks and staging of the kernel above. One
+// MFMA covers the three dx taps of a (dy, dz) row: its columns are
+// n = 8 (dx + 1) + ci for n < 24, so lane (n, h) reads input voxel
+// 16kk + 8h + e + dx + 1 of the row's window, channel ci. Column 24 of row
+// 0's MFMA reads ones (the bias: dPre summed over the voxels), the other
+// spare columns read zeros. Wave w takes dPre row w of the task and all
+// nine rows (nine accumulators); the four waves' sums are added through
+// LDS in wave order at the end.
+__host__ __device__ constexpr int wg8_slot(int x) { return 8 * x + 32 * (x >> 3); }
+constexpr int kWg8InRow = wg8_slot(kWgInVox - 1) + 8;
+constexpr int kWg8InChunks = kWgInRows * kWgInVox;  // one 16-byte chunk per voxel
+constexpr int kWg8Chunks = kWgDpChunks + kWg8InChunks;
+constexpr int kWg8PerThread = (kWg8Chunks + 255) / 256;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_wgrad_rows8_kernel(WgRowK a) {
+  constexpr int C = 8, R = kWgRows;
+  static_assert(R == 4, "one dPre row per wave");
+  __shared__ __attribute__((aligned(16))) bf16 dp[R * kWgDpRow];
+  __shared__ __attribute__((aligned(16))) bf16 inr[kWgInRows * kWg8InRow + 16];
+  __shared__ float red[9 * 32 * 32];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + kWgVox - 1) / kWgVox, sy = (a.v.Y + R - 1) / R;
+  constexpr int kOnes = kWgInRows * kWg8InRow, kZeros = kOnes + 8;
+  if (threadIdx.x < 16) inr[kOnes + threadIdx.x] = (bf16)(threadIdx.x < 8 ? 1.0f : 0.0f);
+  bf16x8 pre[kWg8PerThread];
+  auto origin = [&](int t, int& x0, int& y0, int& z) {
+    x0 = (t % sx) * kWgVox;
+    y0 = ((t / sx) % sy) * R;
+    z = t / (sx * sy);
+  };
+  // chunk e < kWgDpChunks: dPre as in the 32-channel kernel; otherwise input
+  // row ri = e' / 34, voxel x0 - 1 + e' % 34 (all 8 channels)
+  auto load_task = [&](int t) {
+    int x0, y0, z;
+    origin(t, x0, y0, z);
+#pragma unroll
+    for (int q = 0; q < kWg8PerThread; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (q * 256 + 255 >= kWg8Chunks && e >= kWg8Chunks) continue;
+      if (q * 256 < kWgDpChunks) {
+        const int x = min(x0 + (e % (kWgVox * 4)) / 4, a.v.X - 1);
+        const int y = min(y0 + e / (kWgVox * 4), a.v.Y - 1);
+        pre[q] = *reinterpret_cast<const bf16x8*>(a.dpre + a.v.vox(x, y, z) * kCo + (e & 3) * 8);
+      } else {
+        const int f = e - kWgDpChunks, ri = f / kWgInVox;
+        const int x = min(x0 - 1 + f % kWgInVox, a.v.X);
+        const int y = min(y0 - 1 + ri % (R + 2), a.v.Y);
+        pre[q] = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x, y, z + ri / (R + 2) - 1) * C);
+      }
+    }
+  };
+  auto store_task = [&](int t) {
+    int x0, y0, z;
+    origin(t, x0, y0, z);
+#pragma unroll
+    for (int q = 0; q < kWg8PerThread; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (q * 256 + 255 >= kWg8Chunks && e >= kWg8Chunks) continue;
+      if (q * 256 < kWgDpChunks) {
+        const int r = e / (kWgVox * 4), vx = (e % (kWgVox * 4)) / 4;
+        const bool ok = x0 + vx < a.v.X && y0 + r < a.v.Y;
+        *reinterpret_cast<bf16x8*>(&dp[r * kWgDpRow + wg_slot(vx) + (e & 3) * 8]) =
+            ok ? pre[q] : zero8();
+      } else {
+        const int f = e - kWgDpChunks;
+        *reinterpret_cast<bf16x8*>(&inr[(f / kWgInVox) * kWg8InRow + wg8_slot(f % kWgInVox)]) =
+            pre[q];
+      }
+    }
+  };
+  f32x16 acc[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) acc[q] = f32x16{};
+  const int dx1 = m >> 3, ci = m & 7;  // column n = m < 24: tap dx = dx1 - 1, channel ci
+  const TaskWalk tw = xcd_tasks(a.ntask);
+  load_task(min(tw.first, a.ntask - 1));
+  for (int t = tw.first; t < tw.end; t += tw.step) {
+    __syncthreads();  // the previous task's LDS reads are done
+    store_task(t);
+    __syncthreads();
+    load_task(min(t + tw.step, a.ntask - 1));  // in flight while this task computes
+#pragma unroll 1
+    for (int kk = 0; kk < 2; ++kk) {
+      const int vb = 16 * kk + 8 * h;
+      bf16x8 av;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) av[e] = dp[w * kWgDpRow + wg_slot(vb + e) + m];
+#pragma unroll
+      for (int row = 0; row < 9; ++row) {
+        const int dz = row / 3 - 1, dy = row % 3 - 1;
+        const int ri = (dz + 1) * (R + 2) + w + 1 + dy;
+        const int spare = (row == 0 && m == 24) ? kOnes : kZeros;
+        bf16x8 bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          bv[e] = inr[m < 24 ? ri * kWg8InRow + wg8_slot(vb + e + dx1) + ci : spare];
+        acc[row] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[row], 0, 0, 0);
+      }
+    }
+  }
+  // the four waves' sums, added in wave order: red[row][co][n]
+#pragma unroll 1
+  for (int ww = 0; ww < 4; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int row = 0; row < 9; ++row)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int co = 8 * (r / 4) + 4 * h + (r % 4);
+          float& d = red[(row * 32 + co) * 32 + m];
+          d = ww == 0 ? acc[row][r] : d + acc[row][r];
+        }
+    }
+    __syncthreads();
+  }
+  float* out = a.part + (int64_t)blockIdx.x * (kTaps * kCo * C + kCo);
+  for (int i = threadIdx.x; i < 9 * 32 * 32; i += blockDim.x) {
+    const int row = i >> 10, co = (i >> 5) & 31, n = i & 31;
+    if (n < 24) out[((3 * row + (n >> 3)) * kCo + co) * C + (n & 7)] = red[i];
+    else if (n == 24 && row == 0) out[kTaps * kCo * C + co] = red[i];
+  }
+}
+
 // Sums block partials: dw[27*32*CIN], db[32]. Eight interleaved running
 // sums (block b goes to sum b % 8) keep eight loads in flight per thread;
 // they are combined in a fixed order, so the result does not depend on the
@@ -596,7 +914,7 @@ __global__ void target_kernel(ms_grid g, const double* u, Vol v, const double* s
 
 int conv_grid_blocks() { return 1024; }
 
-// 32-channel layers use the row-blocked kernel; MS_CONV_ROWS=0 selects the
+// 32-channel layers use the row-blocked kernels; MS_CONV_ROWS=0 selects the
 // one-row kernels instead (a cross-check).
 bool row_blocked() {
   const char* e = getenv("MS_CONV_ROWS");
@@ -675,11 +993,21 @@ extern "C" int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, c
   WgK a{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(dpre),
         static_cast<float*>(work), ((X + 15) / 16) * Y * Z};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int nb = conv_grid_blocks();
-  if (cin == 8)
+  int nb = conv_grid_blocks();
+  if (row_blocked()) {
+    const int ntask = ((X + kWgVox - 1) / kWgVox) * ((Y + kWgRows - 1) / kWgRows) * Z;
+    nb = std::min(kWgBlocks, ntask);
+    const WgRowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(dpre),
+                   static_cast<float*>(work), ntask};
+    if (cin == 8)
+      hipLaunchKernelGGL(conv_wgrad_rows8_kernel, dim3(nb), dim3(256), 0, s, r);
+    else
+      hipLaunchKernelGGL(conv_wgrad_rows_kernel, dim3(nb), dim3(256), 0, s, r);
+  } else if (cin == 8) {
     hipLaunchKernelGGL(conv_wgrad_kernel<8>, dim3(nb), dim3(256), 0, s, a);
-  else
+  } else {
     hipLaunchKernelGGL(conv_wgrad_kernel<32>, dim3(nb), dim3(256), 0, s, a);
+  }
   MS_LAUNCH_CHECK();
   const int n = kTaps * kCo * cin;
   hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + kCo + 255) / 256), dim3(256), 0, s,

@@ -222,3 +222,42 @@ def test_row_blocked_conv_on_ragged_extents():
     # halos stay zero
     o = out.float().view(nz + 2, ny + 2, nx + 2, 32)
     assert torch.all(o[:, -1] == 0) and torch.all(o[:, :, -1] == 0) and torch.all(o[-1] == 0)
+
+
+@pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
+@pytest.mark.parametrize("shape", [(70, 9, 3), (64, 64, 40)])
+def test_row_blocked_wgrad(shape, cin, cinp):
+    """Weight gradient of the first layer (2 channels padded to 8) and of a
+    32-channel layer: x past a 32-voxel task and y past a 4-row task
+    (70 x 9 x 3), and a volume with several tasks per block (64 x 64 x 40:
+    1280 tasks over 512 blocks), against the oracle. The output-gradient halo
+    holds nonzero values, which must not enter the sums. A second call gives
+    the same bits (fixed reduction order)."""
+    nx, ny, nz = shape
+    r = synth.rng(13)
+    x = cnn.round_bf16(np.maximum(r.standard_normal((cin, nz, ny, nx)), 0.0))
+    g = cnn.round_bf16(r.standard_normal((32, nz, ny, nx)))
+    xin = _bf16_act(x, cinp)
+    gh = torch.full((nz + 2, ny + 2, nx + 2, 32), 3.0, dtype=torch.float32)
+    gh[1:-1, 1:-1, 1:-1] = torch.from_numpy(np.transpose(g, (1, 2, 3, 0)).copy())
+    gin = gh.to(torch.bfloat16).cuda().reshape(-1)
+    work = torch.empty(ms.lib.conv3d_bf16_wgrad_workspace_bytes(cinp), dtype=torch.uint8,
+                       device="cuda")
+    res = []
+    for _ in range(2):
+        dw = torch.zeros(27 * 32 * cinp, dtype=torch.float32, device="cuda")
+        db = torch.zeros(32, dtype=torch.float32, device="cuda")
+        assert ms.lib.conv3d_bf16_wgrad(nx, ny, nz, cinp, ms._ptr(xin), ms._ptr(gin),
+                                        ms._ptr(dw), ms._ptr(db), ms._ptr(work), work.numel(),
+                                        None) == 0
+        torch.cuda.synchronize()
+        res.append((dw.cpu().numpy(), db.cpu().numpy()))
+    assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
+    ref_dw, ref_db = cnn.conv3d_wgrad(x, g)
+    mag_dw, mag_db = cnn.conv3d_wgrad(np.abs(x), np.abs(g))
+    dwp = res[0][0].reshape(27, 32, cinp)
+    assert np.all(dwp[:, :, cin:] == 0)  # zero input channels get zero gradients
+    got_dw = wsm.to_oracle_weights(dwp, cin, 32)
+    # BF16 products are exact in FP32; only the FP32 sums round
+    assert np.all(np.abs(got_dw - ref_dw) <= 1e-5 * mag_dw + 1e-6)
+    assert np.all(np.abs(res[0][1] - ref_db) <= 1e-5 * mag_db + 1e-6)
