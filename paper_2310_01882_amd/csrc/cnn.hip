@@ -607,31 +607,36 @@ void conv_wgrad_rows_kernel(WgRowK a) {
 // ------------------------------------------ row-blocked 8-channel wgrad
 //
 // Weight gradient of the first layer (8 input channels: the two features
-// and six zero channels), on the tasks and staging of the kernel above. One
+// and six zero channels), staged like the kernel above but with tasks of
+// kWg8Rows rows (this layer has a third of the MFMAs per voxel, so a task
+// needs more rows to cover the latency of the next task's loads). One
 // MFMA covers the three dx taps of a (dy, dz) row: its columns are
 // n = 8 (dx + 1) + ci for n < 24, so lane (n, h) reads input voxel
 // 16kk + 8h + e + dx + 1 of the row's window, channel ci. Column 24 of row
 // 0's MFMA reads ones (the bias: dPre summed over the voxels), the other
-// spare columns read zeros. Wave w takes dPre row w of the task and all
-// nine rows (nine accumulators); the four waves' sums are added through
-// LDS in wave order at the end.
+// spare columns read zeros. Wave w takes dPre rows w, w + 4, ... of the
+// task and all nine (dy, dz) rows (nine accumulators); the four waves' sums
+// are added through LDS in wave order at the end.
 __host__ __device__ constexpr int wg8_slot(int x) { return 8 * x + 32 * (x >> 3); }
+constexpr int kWg8Rows = 8;
+constexpr int kWg8InRows = 3 * (kWg8Rows + 2);
 constexpr int kWg8InRow = wg8_slot(kWgInVox - 1) + 8;
-constexpr int kWg8InChunks = kWgInRows * kWgInVox;  // one 16-byte chunk per voxel
-constexpr int kWg8Chunks = kWgDpChunks + kWg8InChunks;
+constexpr int kWg8DpChunks = kWg8Rows * kWgVox * 4;
+constexpr int kWg8InChunks = kWg8InRows * kWgInVox;  // one 16-byte chunk per voxel
+constexpr int kWg8Chunks = kWg8DpChunks + kWg8InChunks;
 constexpr int kWg8PerThread = (kWg8Chunks + 255) / 256;
+static_assert(kWg8DpChunks % 256 == 0 && kWg8Rows % 4 == 0, "whole load rounds and row sets");
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv_wgrad_rows8_kernel(WgRowK a) {
-  constexpr int C = 8, R = kWgRows;
-  static_assert(R == 4, "one dPre row per wave");
+  constexpr int C = 8, R = kWg8Rows;
   __shared__ __attribute__((aligned(16))) bf16 dp[R * kWgDpRow];
-  __shared__ __attribute__((aligned(16))) bf16 inr[kWgInRows * kWg8InRow + 16];
+  __shared__ __attribute__((aligned(16))) bf16 inr[kWg8InRows * kWg8InRow + 16];
   __shared__ float red[9 * 32 * 32];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 31, h = lane >> 5;
   const int sx = (a.v.X + kWgVox - 1) / kWgVox, sy = (a.v.Y + R - 1) / R;
-  constexpr int kOnes = kWgInRows * kWg8InRow, kZeros = kOnes + 8;
+  constexpr int kOnes = kWg8InRows * kWg8InRow, kZeros = kOnes + 8;
   if (threadIdx.x < 16) inr[kOnes + threadIdx.x] = (bf16)(threadIdx.x < 8 ? 1.0f : 0.0f);
   bf16x8 pre[kWg8PerThread];
   auto origin = [&](int t, int& x0, int& y0, int& z) {
@@ -639,8 +644,8 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
     y0 = ((t / sx) % sy) * R;
     z = t / (sx * sy);
   };
-  // chunk e < kWgDpChunks: dPre as in the 32-channel kernel; otherwise input
-  // row ri = e' / 34, voxel x0 - 1 + e' % 34 (all 8 channels)
+  // chunk e < kWg8DpChunks: dPre as in the 32-channel kernel; otherwise
+  // input row ri = e' / 34, voxel x0 - 1 + e' % 34 (all 8 channels)
   auto load_task = [&](int t) {
     int x0, y0, z;
     origin(t, x0, y0, z);
@@ -648,12 +653,12 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
     for (int q = 0; q < kWg8PerThread; ++q) {
       const int e = threadIdx.x + 256 * q;
       if (q * 256 + 255 >= kWg8Chunks && e >= kWg8Chunks) continue;
-      if (q * 256 < kWgDpChunks) {
+      if (q * 256 < kWg8DpChunks) {
         const int x = min(x0 + (e % (kWgVox * 4)) / 4, a.v.X - 1);
         const int y = min(y0 + e / (kWgVox * 4), a.v.Y - 1);
         pre[q] = *reinterpret_cast<const bf16x8*>(a.dpre + a.v.vox(x, y, z) * kCo + (e & 3) * 8);
       } else {
-        const int f = e - kWgDpChunks, ri = f / kWgInVox;
+        const int f = e - kWg8DpChunks, ri = f / kWgInVox;
         const int x = min(x0 - 1 + f % kWgInVox, a.v.X);
         const int y = min(y0 - 1 + ri % (R + 2), a.v.Y);
         pre[q] = *reinterpret_cast<const bf16x8*>(a.in + a.v.vox(x, y, z + ri / (R + 2) - 1) * C);
@@ -667,13 +672,13 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
     for (int q = 0; q < kWg8PerThread; ++q) {
       const int e = threadIdx.x + 256 * q;
       if (q * 256 + 255 >= kWg8Chunks && e >= kWg8Chunks) continue;
-      if (q * 256 < kWgDpChunks) {
+      if (q * 256 < kWg8DpChunks) {
         const int r = e / (kWgVox * 4), vx = (e % (kWgVox * 4)) / 4;
         const bool ok = x0 + vx < a.v.X && y0 + r < a.v.Y;
         *reinterpret_cast<bf16x8*>(&dp[r * kWgDpRow + wg_slot(vx) + (e & 3) * 8]) =
             ok ? pre[q] : zero8();
       } else {
-        const int f = e - kWgDpChunks;
+        const int f = e - kWg8DpChunks;
         *reinterpret_cast<bf16x8*>(&inr[(f / kWgInVox) * kWg8InRow + wg8_slot(f % kWgInVox)]) =
             pre[q];
       }
@@ -691,15 +696,16 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
     __syncthreads();
     load_task(min(t + tw.step, a.ntask - 1));  // in flight while this task computes
 #pragma unroll 1
-    for (int kk = 0; kk < 2; ++kk) {
-      const int vb = 16 * kk + 8 * h;
+    for (int rk = 0; rk < 2 * R / 4; ++rk) {
+      const int r = w + 4 * (rk >> 1);        // the wave's dPre row
+      const int vb = 16 * (rk & 1) + 8 * h;  // first voxel of the lane's K-slice
       bf16x8 av;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = dp[w * kWgDpRow + wg_slot(vb + e) + m];
+      for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
 #pragma unroll
       for (int row = 0; row < 9; ++row) {
         const int dz = row / 3 - 1, dy = row % 3 - 1;
-        const int ri = (dz + 1) * (R + 2) + w + 1 + dy;
+        const int ri = (dz + 1) * (R + 2) + r + 1 + dy;
         const int spare = (row == 0 && m == 24) ? kOnes : kZeros;
         bf16x8 bv;
 #pragma unroll
@@ -995,7 +1001,8 @@ extern "C" int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, c
   hipStream_t s = static_cast<hipStream_t>(stream);
   int nb = conv_grid_blocks();
   if (row_blocked()) {
-    const int ntask = ((X + kWgVox - 1) / kWgVox) * ((Y + kWgRows - 1) / kWgRows) * Z;
+    const int rows = cin == 8 ? kWg8Rows : kWgRows;
+    const int ntask = ((X + kWgVox - 1) / kWgVox) * ((Y + rows - 1) / rows) * Z;
     nb = std::min(kWgBlocks, ntask);
     const WgRowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(dpre),
                    static_cast<float*>(work), ntask};
