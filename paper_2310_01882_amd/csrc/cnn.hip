@@ -613,10 +613,12 @@ void conv_wgrad_rows_kernel(WgRowK a) {
 // MFMA covers the three dx taps of a (dy, dz) row: its columns are
 // n = 8 (dx + 1) + ci for n < 24, so lane (n, h) reads input voxel
 // 16kk + 8h + e + dx + 1 of the row's window, channel ci. Column 24 of row
-// 0's MFMA reads ones (the bias: dPre summed over the voxels), the other
-// spare columns read zeros. Wave w takes dPre rows w, w + 4, ... of the
-// task and all nine (dy, dz) rows (nine accumulators); the four waves' sums
-// are added through LDS in wave order at the end.
+// 0's MFMA reads ones (the bias: dPre summed over the voxels); the other
+// spare columns are never stored, and their lanes read the addresses of
+// lanes n - 24 (same-address reads share a bank access). Wave w takes dPre
+// rows w, w + 4, ... of the task and all nine (dy, dz) rows (nine
+// accumulators); the four waves' sums are added through LDS in wave order
+// at the end.
 __host__ __device__ constexpr int wg8_slot(int x) { return 8 * x + 32 * (x >> 3); }
 constexpr int kWg8Rows = 8;
 constexpr int kWg8InRows = 3 * (kWg8Rows + 2);
@@ -631,13 +633,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv_wgrad_rows8_kernel(WgRowK a) {
   constexpr int C = 8, R = kWg8Rows;
   __shared__ __attribute__((aligned(16))) bf16 dp[R * kWgDpRow];
-  __shared__ __attribute__((aligned(16))) bf16 inr[kWg8InRows * kWg8InRow + 16];
+  __shared__ __attribute__((aligned(16))) bf16 inr[kWg8InRows * kWg8InRow + 8];
   __shared__ float red[9 * 32 * 32];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 31, h = lane >> 5;
   const int sx = (a.v.X + kWgVox - 1) / kWgVox, sy = (a.v.Y + R - 1) / R;
-  constexpr int kOnes = kWg8InRows * kWg8InRow, kZeros = kOnes + 8;
-  if (threadIdx.x < 16) inr[kOnes + threadIdx.x] = (bf16)(threadIdx.x < 8 ? 1.0f : 0.0f);
+  constexpr int kOnes = kWg8InRows * kWg8InRow;
+  if (threadIdx.x < 8) inr[kOnes + threadIdx.x] = (bf16)1.0f;
   bf16x8 pre[kWg8PerThread];
   auto origin = [&](int t, int& x0, int& y0, int& z) {
     x0 = (t % sx) * kWgVox;
@@ -687,7 +689,8 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
   f32x16 acc[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) acc[q] = f32x16{};
-  const int dx1 = m >> 3, ci = m & 7;  // column n = m < 24: tap dx = dx1 - 1, channel ci
+  // column n = m < 24: tap dx = dx1 - 1, channel ci; spare columns alias n - 24
+  const int dx1 = m < 24 ? m >> 3 : 0, ci = m & 7;
   const TaskWalk tw = xcd_tasks(a.ntask);
   load_task(min(tw.first, a.ntask - 1));
   for (int t = tw.first; t < tw.end; t += tw.step) {
@@ -706,11 +709,11 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
       for (int row = 0; row < 9; ++row) {
         const int dz = row / 3 - 1, dy = row % 3 - 1;
         const int ri = (dz + 1) * (R + 2) + r + 1 + dy;
-        const int spare = (row == 0 && m == 24) ? kOnes : kZeros;
+        const bool ones = row == 0 && m == 24;
         bf16x8 bv;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          bv[e] = inr[m < 24 ? ri * kWg8InRow + wg8_slot(vb + e + dx1) + ci : spare];
+          bv[e] = inr[ones ? kOnes : ri * kWg8InRow + wg8_slot(vb + e + dx1) + ci];
         acc[row] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[row], 0, 0, 0);
       }
     }
