@@ -760,6 +760,29 @@ __global__ void wgrad_reduce_kernel(const float* part, int nblocks, int n, float
   else db[i - n] = t;
 }
 
+// First pass of the row-blocked kernels' reduction: slice y of the grid
+// sums block partials [y per, (y + 1) per) in the order above into
+// slices[y]; wgrad_reduce_kernel then sums the slices (as if they were
+// blocks). Sixteen slices give the reduction sixteen times the parallelism
+// of one pass over the blocks.
+constexpr int kWgSlices = 16;
+
+__global__ void wgrad_slice_kernel(const float* part, int nblocks, int n, int per,
+                                   float* slices) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n + kCo) return;
+  const int64_t stride = n + kCo;
+  const int b0 = blockIdx.y * per, b1 = min(nblocks, b0 + per);
+  float s[8] = {};
+  int b = b0;
+  for (; b + 8 <= b1; b += 8)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) s[e] += part[(int64_t)(b + e) * stride + i];
+  for (int e = 0; b < b1; ++b, ++e) s[e] += part[(int64_t)b * stride + i];
+  slices[blockIdx.y * stride + i] =
+      ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
 // ------------------------------------------------- loss, Adam, features
 
 // loss partials and dPre of the last layer: d = 2 (pred - target) / N in
@@ -921,7 +944,7 @@ __global__ void target_kernel(ms_grid g, const double* u, Vol v, const double* s
   }
 }
 
-int conv_grid_blocks() { return 1024; }
+constexpr int conv_grid_blocks() { return 1024; }
 
 // 32-channel layers use the row-blocked kernels; MS_CONV_ROWS=0 selects the
 // one-row kernels instead (a cross-check).
@@ -1020,8 +1043,22 @@ extern "C" int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, c
   }
   MS_LAUNCH_CHECK();
   const int n = kTaps * kCo * cin;
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((n + kCo + 255) / 256), dim3(256), 0, s,
-                     static_cast<const float*>(work), nb, n, dw, db);
+  const int64_t stride = n + kCo;
+  const dim3 rgrid((unsigned)((stride + 255) / 256));
+  if (row_blocked()) {
+    // the row-blocked kernels use at most kWgBlocks of the workspace's
+    // conv_grid_blocks() partial slots; the slices go after them
+    static_assert(kWgBlocks + kWgSlices <= conv_grid_blocks(), "slices fit the workspace");
+    float* slices = static_cast<float*>(work) + (int64_t)nb * stride;
+    hipLaunchKernelGGL(wgrad_slice_kernel, dim3(rgrid.x, kWgSlices), dim3(256), 0, s,
+                       static_cast<const float*>(work), nb, n, (nb + kWgSlices - 1) / kWgSlices,
+                       slices);
+    MS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(wgrad_reduce_kernel, rgrid, dim3(256), 0, s, slices, kWgSlices, n, dw, db);
+  } else {
+    hipLaunchKernelGGL(wgrad_reduce_kernel, rgrid, dim3(256), 0, s,
+                       static_cast<const float*>(work), nb, n, dw, db);
+  }
   MS_LAUNCH_CHECK();
   return MS_OK;
 }
