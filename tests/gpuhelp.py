@@ -33,3 +33,12 @@ def empty_like_layout(t: torch.Tensor, fill=float("nan")) -> torch.Tensor:
 
 def note(msg: str):
     print(msg, file=sys.stderr, flush=True)
+
+
+def on_slab(fn, arrays, z0, k, n):
+    """``fn`` (a 3x3x3 "same" operator of [C, Z, Y, X] arrays) on output
+    planes z0 .. z0+k-1 of an n-plane volume, run on the planes those outputs
+    read (z0-1 .. z0+k, clipped to the volume): the zero padding beyond a cut
+    plane only reaches that plane's outputs, which are not returned."""
+    lo, hi = max(z0 - 1, 0), min(z0 + k + 1, n)
+    return fn(*[a[:, lo:hi] for a in arrays])[:, z0 - lo:z0 - lo + k]

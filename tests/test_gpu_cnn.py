@@ -9,7 +9,7 @@ import torch
 
 import oracle
 import synth
-from gpuhelp import dev, note
+from gpuhelp import dev, note, on_slab
 from oracle import cnn
 
 pytestmark = pytest.mark.gpu
@@ -293,3 +293,50 @@ def test_wgrad_at_full_size_on_sampled_outputs(cin, cinp):
     got_dw = wsm.to_oracle_weights(dwp, cin, 32)[:co, :ci]
     assert np.array_equal(got_dw, ref_dw)
     assert np.array_equal(db.cpu().numpy()[:co].astype(np.float64), ref_db)
+
+
+@pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
+def test_forward_and_input_gradient_at_full_size(cin, cinp):
+    """Forward (bias, ReLU, BF16 and FP32 outputs) and input gradient (ReLU
+    mask) at 128^3 in the launch the benchmarks time, against the oracle on
+    every channel of the z planes 0-1, 63-64 and 126-127 (the oracle runs on
+    the planes those outputs read). Inputs, weights and biases are k/8
+    (|k| <= 7): a sum of 27 x cin such products is exact in FP32, so the
+    BF16 outputs must equal the oracle's rounded values bit for bit and the
+    FP32 output its exact value."""
+    n = 128
+    note(f"case: forward and input gradient 128^3 cin={cinp}")
+    r = synth.rng(19)
+    x = np.maximum(r.integers(-7, 8, (cin, n, n, n), dtype=np.int8), 0).astype(np.float32) / 8
+    g = r.integers(-7, 8, (32, n, n, n), dtype=np.int8).astype(np.float32) / 8
+    w = np.zeros((27, 32, cinp), np.float32)
+    w[:, :, :cin] = r.integers(-7, 8, (27, 32, cin)).astype(np.float32) / 8
+    b = r.integers(-7, 8, 32).astype(np.float32) / 8
+    wt = torch.from_numpy(w).cuda()
+    wf = torch.empty(27 * 32 * cinp, dtype=torch.bfloat16, device="cuda")
+    wd = torch.empty_like(wf)
+    assert ms.lib.cnn_pack_weights(cinp, ms._ptr(wt), ms._ptr(wf), ms._ptr(wd), None) == 0
+    bt = torch.from_numpy(b).cuda()
+    xin, gin = _bf16_act(x, cinp), _bf16_act(g, 32)
+    out = torch.zeros((n + 2) ** 3 * 32, dtype=torch.bfloat16, device="cuda")
+    out32 = torch.zeros((n + 2, n + 2, n + 2), dtype=torch.float32, device="cuda")
+    din = torch.zeros_like(xin)
+    assert ms.lib.conv3d_bf16_fwd(n, n, n, cinp, ms._ptr(xin), ms._ptr(wf), ms._ptr(bt),
+                                  ms._ptr(out), ms._ptr(out32), 1, None) == 0
+    assert ms.lib.conv3d_bf16_dgrad(n, n, n, cinp, ms._ptr(gin), ms._ptr(wd), ms._ptr(xin),
+                                    ms._ptr(din), None) == 0
+    torch.cuda.synchronize()
+    shape = (n, n, n)
+    got = _act_np(out, 32, 32, shape)
+    got32 = out32[1:-1, 1:-1, 1:-1].cpu().numpy().astype(np.float64)
+    got_din = _act_np(din, cin, cinp, shape)
+    del xin, gin, out, out32, din
+    wo = wsm.to_oracle_weights(w, cin, 32)
+    b64 = b.astype(np.float64)
+    for z0 in (0, 63, 126):
+        ref = on_slab(lambda a: np.maximum(cnn.conv3d(a, wo, b64), 0.0), [x], z0, 2, n)
+        assert np.array_equal(got[:, z0:z0 + 2], cnn.round_bf16(ref)), z0
+        assert np.array_equal(got32[z0:z0 + 2], ref[0]), z0
+        ref_din = on_slab(lambda gg, xx: cnn.conv3d_dgrad(gg, wo) * (xx > 0), [g, x], z0, 2,
+                           n)
+        assert np.array_equal(got_din[:, z0:z0 + 2], cnn.round_bf16(ref_din)), z0

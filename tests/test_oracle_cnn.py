@@ -137,3 +137,23 @@ def test_features_scale_free():
     assert s2 == pytest.approx(3 * s1)
     np.testing.assert_allclose(a, b, rtol=1e-14)
     assert np.max(np.abs(a)) == pytest.approx(1.0)
+
+
+def test_slab_evaluation_equals_the_whole_volume():
+    """The full-size GPU tests evaluate the convolutions on the planes a few
+    output planes read; that equals the whole-volume evaluation there, at
+    the bottom, in the middle and at the top."""
+    from gpuhelp import on_slab
+
+    r = synth.rng(23)
+    x = r.standard_normal((3, 9, 5, 6))
+    g = r.standard_normal((4, 9, 5, 6))
+    w = r.standard_normal((4, 3, 3, 3, 3))
+    b = r.standard_normal(4)
+    full = cnn.conv3d(x, w, b)
+    fulld = cnn.conv3d_dgrad(g, w)
+    for z0 in (0, 3, 7):
+        assert np.array_equal(on_slab(lambda a: cnn.conv3d(a, w, b), [x], z0, 2, 9),
+                              full[:, z0:z0 + 2])
+        assert np.array_equal(on_slab(lambda a: cnn.conv3d_dgrad(a, w), [g], z0, 2, 9),
+                              fulld[:, z0:z0 + 2])
