@@ -1,6 +1,7 @@
 """Pins of the CNN oracle: library convolution, exact special cases, finite
-differences for the backward pass, Adam's closed-form first step, BF16
-rounding of known values, and the boundary lift."""
+differences for the backward pass, Adam's closed form on a constant gradient
+at every step, the MSE loss and its gradient (closed form, scikit-learn,
+finite differences), BF16 rounding of known values, and the boundary lift."""
 
 import numpy as np
 import pytest
@@ -157,3 +158,63 @@ def test_slab_evaluation_equals_the_whole_volume():
                               full[:, z0:z0 + 2])
         assert np.array_equal(on_slab(lambda a: cnn.conv3d_dgrad(a, w), [g], z0, 2, 9),
                               fulld[:, z0:z0 + 2])
+
+
+@pytest.mark.parametrize("b1,b2", [(0.9, 0.999), (0.5, 0.75)])
+def test_adam_constant_gradient_closed_form_every_step(b1, b2):
+    """With a constant gradient g the bias-corrected moments are exactly g
+    and g^2 at every step t (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so
+    each step moves p by lr * g / (|g| + eps): p_t = p_0 - t lr g / (|g| + eps)."""
+    p0 = np.array([1.0, -2.0, 0.5, 3.0, -0.25])
+    g = np.array([0.3, -4.0, 2.5e-2, 1e-3, -7.0])
+    m, v = np.zeros(5), np.zeros(5)
+    lr, eps = 1e-2, 1e-8
+    p = p0.copy()
+    for t in range(1, 7):
+        p = cnn.adam_step(p, g, m, v, t, lr=lr, b1=b1, b2=b2, eps=eps)
+        np.testing.assert_allclose(m, (1 - b1 ** t) * g, rtol=1e-13)
+        np.testing.assert_allclose(v, (1 - b2 ** t) * g * g, rtol=1e-13)
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + eps), rtol=1e-12)
+
+
+def test_adam_first_moment_decays_after_the_gradient_stops():
+    """After one step with gradient g and t - 1 steps with zero gradient,
+    m_t = (1 - b1) b1^(t-1) g and v_t = (1 - b2) b2^(t-1) g^2, so the step
+    at t is lr * m_t/(1 - b1^t) / (sqrt(v_t/(1 - b2^t)) + eps), written
+    here with the powers expanded by hand for t = 3."""
+    b1, b2, lr, eps = 0.9, 0.999, 1e-3, 0.0
+    g = np.array([2.0, -0.5])
+    m, v = np.zeros(2), np.zeros(2)
+    p = cnn.adam_step(np.zeros(2), g, m, v, 1, lr=lr, b1=b1, b2=b2, eps=eps)
+    p = cnn.adam_step(p, np.zeros(2), m, v, 2, lr=lr, b1=b1, b2=b2, eps=eps)
+    before = p.copy()
+    p = cnn.adam_step(p, np.zeros(2), m, v, 3, lr=lr, b1=b1, b2=b2, eps=eps)
+    mhat = 0.1 * 0.81 * g / (1 - 0.729)
+    vhat = 0.001 * 0.998001 * g * g / (1 - 0.997002999)
+    np.testing.assert_allclose(before - p, lr * mhat / np.sqrt(vhat), rtol=1e-12)
+
+
+def test_mse_closed_form_on_a_constant_offset():
+    """pred = target + c on N voxels: loss c^2, gradient 2c/N everywhere."""
+    r = synth.rng(31)
+    target = r.standard_normal((4, 5, 6))
+    for c in (0.75, -3.0):
+        loss, grad = cnn.mse_and_grad(target + c, target)
+        assert loss == pytest.approx(c * c, rel=1e-14)
+        np.testing.assert_allclose(grad, np.full(target.shape, 2 * c / target.size), rtol=1e-12)
+
+
+def test_mse_gradient_matches_central_finite_differences():
+    r = synth.rng(32)
+    pred = r.standard_normal((3, 4, 5))
+    target = r.standard_normal((3, 4, 5))
+    loss, grad = cnn.mse_and_grad(pred, target)
+    from sklearn.metrics import mean_squared_error
+    assert loss == pytest.approx(mean_squared_error(target.ravel(), pred.ravel()), rel=1e-13)
+    eps = 1e-6
+    for idx in [(0, 0, 0), (1, 2, 3), (2, 3, 4), (0, 3, 1)]:
+        pp, pm = pred.copy(), pred.copy()
+        pp[idx] += eps
+        pm[idx] -= eps
+        fd = (cnn.mse_and_grad(pp, target)[0] - cnn.mse_and_grad(pm, target)[0]) / (2 * eps)
+        assert grad[idx] == pytest.approx(fd, rel=1e-6, abs=1e-10)
