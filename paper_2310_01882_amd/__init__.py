@@ -559,6 +559,21 @@ def autotune_sweeps(u, u_tmp, f=None, sweeps_per_trial=10, stream=None) -> dict:
     return {k: getattr(best, k) for k in _TUNING_FIELDS}
 
 
+def sweep_shape(*fields) -> dict:
+    """The tile shape a sweep over these fields (same grid and dtype) would
+    launch with: the tuned entry for their grid and alignment if there is
+    one, else the default (vec_ok is the widest lane the alignment allows)."""
+    for i, t in enumerate(fields):
+        _field_check(t, f"fields[{i}]", fields[0].dtype)
+        _same_layout(fields[0], t, "fields")
+    arr = (ctypes.c_void_p * len(fields))(*[t.data_ptr() for t in fields])
+    out = Tuning()
+    g = grid_of(fields[0])
+    _check(lib.ms_sweep_shape(ctypes.byref(g), _dtype_code(fields[0]), arr, len(fields),
+                              ctypes.byref(out)))
+    return {k: getattr(out, k) for k in _TUNING_FIELDS}
+
+
 def tuning_table() -> list:
     n = lib.ms_tuning_get(None, 0)
     arr = (Tuning * max(n, 1))()

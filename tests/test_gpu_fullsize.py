@@ -1,0 +1,135 @@
+"""Full-size parity at the 512^3 configuration, in the launch configuration
+the benchmark times.
+
+The benchmark allocates its fields with ``field_from`` (interior rows on
+128-byte boundaries), which lets the sweep use 16-byte lanes: the
+register-tiled kernel with two FP64 cells per lane, two rows per lane and
+two waves across x. These tests build their fields the same way, check that
+the library picks that shape, and compare the result with the oracle over
+the whole grid. The FP32-refined solves to a 1e-8 relative residual are
+checked by the oracle's own FP64 residual of the returned field."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpuhelp import host, note
+
+pytestmark = pytest.mark.gpu
+
+import paper_2310_01882_amd as ms  # noqa: E402
+
+N = 512
+NORM_RTOL = 1e-13
+# the default shape of the benchmark's sweep on aligned FP64 fields
+BENCH_SHAPE = {"vec_ok": 2, "vec": 2, "wx": 2, "rows": 2}
+
+
+@pytest.fixture(scope="module")
+def problem512():
+    """The benchmark's inputs: 8 Gaussian sources (seed 1), zero Dirichlet
+    halo; a non-zero start (3 f) so that the first sweep exercises every
+    neighbour, and the oracle's first four sweeps from it."""
+    note("case: 512^3 oracle trajectory (4 sweeps)")
+    f = synth.gaussian_sources(N, N, N, 8, 1)
+    u = synth.zeros(N, N, N)
+    u[1:-1, 1:-1, 1:-1] = f[1:-1, 1:-1, 1:-1] * 3.0
+    traj, hist = [u], []
+    for _ in range(4):
+        hist.append(oracle.residual_norm(traj[-1], f))
+        traj.append(oracle.jacobi_sweep(traj[-1], f))
+    hist.append(oracle.residual_norm(traj[-1], f))
+    return u, f, traj, hist
+
+
+def _fields(u, f):
+    du, dt, df = ms.field_from(u), ms.field_from(u), ms.field_from(f)
+    return du, dt, df
+
+
+def test_benchmark_sweep_kernel_bit_exact_at_512cubed(problem512):
+    u, f, traj, hist = problem512
+    ms.tuning_clear()
+    du, dt, df = _fields(u, f)
+    shape = ms.sweep_shape(du, dt, df)
+    assert {k: shape[k] for k in BENCH_SHAPE} == BENCH_SHAPE, shape
+    for n in (2, 3):
+        note(f"case: 512^3 x {n} sweeps, shape {shape}")
+        du, dt, _ = _fields(u, f)
+        res = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        out = ms.jacobi_sweeps(du, dt, n, f=df, res=res)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), traj[n]), n
+        np.testing.assert_allclose(host(res), hist[:n] + [oracle.residual_norm(traj[n], f)],
+                                   rtol=NORM_RTOL)
+        del du, dt, out
+
+
+@pytest.mark.parametrize("variant", ["default", "columns", "lds"])
+def test_two_sweep_pass_bit_exact_against_the_oracle_at_512cubed(problem512, variant,
+                                                                 monkeypatch):
+    """Two sweeps per pass over memory (the benchmark's temporal_block_2
+    line), four sweeps in two passes and three in a pass plus a single
+    sweep, compared with the oracle's plain sweeps over the whole grid."""
+    if variant != "default":
+        monkeypatch.setenv("MS_TB_VARIANT", {"columns": "2", "lds": "0"}[variant])
+    u, f, traj, hist = problem512
+    _, _, df = _fields(u, f)
+    for n in (4, 3):
+        note(f"case: 512^3 two-sweep pass ({variant}) x {n} sweeps")
+        du, dt, _ = _fields(u, f)
+        res = torch.zeros(n + 1, dtype=torch.float64, device="cuda")
+        out = ms.jacobi_sweeps(du, dt, n, f=df, res=res, temporal_block=2)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(out), traj[n]), n
+        np.testing.assert_allclose(host(res)[:n], hist[:n], rtol=NORM_RTOL)
+        del du, dt, out
+
+
+def _refined_to_1e8(n, capsys, chunk):
+    """Zero start, 8 Gaussian sources (seed 1), FP32 sweeps inside FP64
+    refinement to a 1e-8 relative residual (two sweeps per pass), solved in
+    calls of at most ``chunk`` inner sweeps that resume from the previous
+    answer, with a progress line after each."""
+    f_h = synth.gaussian_sources(n, n, n, 8, 1)
+    u_h = synth.zeros(n, n, n)
+    u, f = ms.field_from(u_h), ms.field_from(f_h)
+    opts = dict(precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8, temporal_block=2,
+                max_sweeps=chunk)
+    work = ms.jacobi_workspace(u, ms.solve_opts(**opts))
+    total = 0
+    for call in range(40):
+        info = ms.jacobi_solve(u, f, work=work, **opts)
+        total += info.sweeps
+        with capsys.disabled():
+            print(f"\n[{n}^3 refined] call {call}: {total} inner sweeps, "
+                  f"rel {info.rel_final:.3e}", flush=True)
+        if info.status == ms.MS_OK:
+            break
+    assert info.status == ms.MS_OK
+    x = host(u)
+    del u, f, work
+    torch.cuda.empty_cache()
+    rel = oracle.residual_norm(x, f_h) / oracle.residual_norm(u_h, f_h)
+    return rel, total, info
+
+
+def test_refined_256cubed_reaches_1e8_checked_by_the_oracle(capsys):
+    rel, total, info = _refined_to_1e8(256, capsys, chunk=400000)
+    note(f"256^3 refined: {total} inner sweeps, library rel {info.rel_final:.3e}, "
+         f"oracle rel {rel:.3e}")
+    assert rel <= 1e-8
+    assert rel == pytest.approx(info.rel_final, rel=1e-9)
+
+
+@pytest.mark.timeout(900)
+def test_refined_512cubed_reaches_1e8_checked_by_the_oracle(capsys):
+    """The 512^3 configuration's FP32-storage variant (about 8e5 inner
+    sweeps, three minutes on the GPU)."""
+    rel, total, info = _refined_to_1e8(N, capsys, chunk=100000)
+    note(f"512^3 refined: {total} inner sweeps, library rel {info.rel_final:.3e}, "
+         f"oracle rel {rel:.3e}")
+    assert rel <= 1e-8
+    assert rel == pytest.approx(info.rel_final, rel=1e-9)

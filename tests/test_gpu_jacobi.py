@@ -138,22 +138,6 @@ def test_eigenmode_decay_on_gpu():
         assert res[k] / res[0] == pytest.approx(rho ** k, rel=1e-9)
 
 
-def test_full_size_512cubed_sweeps_bit_exact():
-    """512^3 interior, 8 Gaussian sources, zero Dirichlet halo, zero start,
-    in the launch configuration the benchmark uses: two sweeps compared in
-    full, plus the residual history."""
-    note("case: 512^3 x 2 sweeps (full compare)")
-    n = 512
-    f = synth.gaussian_sources(n, n, n, 8, 1)
-    u = synth.zeros(n, n, n)
-    # a non-trivial start so the first sweep exercises every neighbour
-    u[1:-1, 1:-1, 1:-1] = f[1:-1, 1:-1, 1:-1] * 3.0
-    got, res = _run_sweeps(u, f, 2)
-    want, hist = oracle.jacobi_sweeps(u, f, 2)
-    assert np.array_equal(got, want)
-    np.testing.assert_allclose(res, hist, rtol=NORM_RTOL)
-
-
 GEOMETRIES = (
     [{"MS_SWEEP_VARIANT": "0", "MS_SWEEP_ROWS": r} for r in ("4", "8")]
     + [{"MS_SWEEP_VARIANT": "1", "MS_SWEEP_VEC": v, "MS_SWEEP_ROWS": r, "MS_SWEEP_WX": w}
@@ -218,23 +202,6 @@ def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype, variant
                     else oracle.residual_norm_f32_storage(want, f))
         assert np.array_equal(host(out), want), (dims, n)
         np.testing.assert_allclose(host(res), hist, rtol=NORM_RTOL)
-
-
-@pytest.mark.parametrize("variant", list(TB_VARIANTS))
-def test_temporal_blocking_at_benchmark_size(variant, monkeypatch):
-    monkeypatch.setenv("MS_TB_VARIANT", TB_VARIANTS[variant])
-    note(f"case: tb2 {variant} 512^3 x 4 sweeps vs plain")
-    n = 512
-    f = ms.field_from(synth.gaussian_sources(n, n, n, 8, 1))
-    outs = []
-    for tb in (1, 2):
-        u, t = ms.alloc_field(n, n, n), ms.alloc_field(n, n, n)
-        res = torch.zeros(5, dtype=torch.float64, device="cuda")
-        o = ms.jacobi_sweeps(u, t, 4, f=f, res=res, temporal_block=tb)
-        outs.append((o.clone(), res.clone()))
-        del u, t
-    assert torch.equal(outs[0][0], outs[1][0])
-    np.testing.assert_allclose(host(outs[0][1]), host(outs[1][1]), rtol=NORM_RTOL)
 
 
 def test_autotuned_shape_is_used_and_bit_exact():

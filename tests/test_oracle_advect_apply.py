@@ -177,27 +177,26 @@ def test_advection_converges_at_second_order_to_the_continuous_operator():
 
 # ------------------------------------------------------------- stencil apply
 
-def test_listing1_four_point_average_matches_a_direct_loop():
-    """The paper's Listing 1 on its own 256x256 array (loops 2..255), run as
-    written (reading the old values: stencil.apply is out-of-place)."""
+def test_listing1_four_point_average_matches_array_slicing():
+    """Listing 1's two-dimensional average on its own 256x256 array (loop
+    bounds, offsets and factor from the golden file), against the same
+    average written independently with numpy slices: each interior point
+    takes a quarter of the sum of its four axis neighbours in the old array
+    (stencil.apply is out-of-place)."""
     facts = json.load(open(GOLDEN))["listing1"]
     n = 256
-    data = synth.rng(7).random((n, n))  # data[i-1][j-1] holds data(j, i)
-    ref = [[data[i][j] for j in range(n)] for i in range(n)]
-    lo, hi = facts["loop_lo"], facts["loop_hi"]
-    want = {}
-    for i in range(lo, hi + 1):
-        for j in range(lo, hi + 1):
-            want[(i, j)] = (ref[i - 2][j - 1] + ref[i][j - 1] + ref[i - 1][j - 2]
-                            + ref[i - 1][j]) * facts["scale"]
-    # The grid: first Fortran index j is x (contiguous), second i is y, nz = 1.
+    assert (facts["loop_lo"], facts["loop_hi"]) == (2, n - 1)  # 1-based: interior 1..n-2
+    d = synth.rng(7).random((n, n))  # d[y, x]; x is the first (contiguous) index
+    want = (d[:-2, 1:-1] + d[2:, 1:-1] + d[1:-1, :-2] + d[1:-1, 2:]) * facts["scale"]
     grid = np.zeros((3, n, n))
-    grid[1] = data
+    grid[1] = d
     taps = [(dx, dy, 0, 1.0) for dx, dy in facts["offsets_first_second_index"]]
     got = oracle.stencil_apply(taps, grid, scale=facts["scale"])
     assert got.shape == (1, n - 2, n - 2)  # output bounds [0,254) x [0,254)
-    for (i, j), val in want.items():
-        assert got[0, i - 2, j - 2] == pytest.approx(val, rel=1e-15)
+    np.testing.assert_allclose(got[0], want, rtol=1e-15, atol=0)
+    # the offsets name the four axis neighbours, once each
+    assert sorted(map(tuple, facts["offsets_first_second_index"])) == [(-1, 0), (0, -1), (0, 1),
+                                                                      (1, 0)]
 
 
 def test_delta_tap_is_an_exact_shift():
