@@ -19,7 +19,9 @@ from dataclasses import dataclass
 import torch  # loads the HIP runtime the library binds to
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmistencil.so")
+# MS_LIB_PATH selects another build of the same library (the host-sanitizer
+# build of sanitize.py); the default is the in-tree library.
+LIB_PATH = os.environ.get("MS_LIB_PATH") or os.path.join(_HERE, "libmistencil.so")
 
 MS_OK = 0
 MS_NOT_CONVERGED = 1
