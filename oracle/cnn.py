@@ -181,3 +181,67 @@ def output_scale(nx, ny, nz):
     the square of the domain size; the network predicts u / (s * lambda)."""
     n = max(nx, ny, nz)
     return n * n / 8.0
+
+
+# ------------------------------------------------------- start selection
+#
+# Reading (the paper has no learned part): plain Jacobi from the zero
+# interior is the guess's fallback. Three rules decide whether a solve starts
+# from the network's guess or from u0 (u with its interior zeroed):
+#   "residual"   -- the guess iff ||r(guess)|| < ||r(u0)||;
+#   "slow_modes" -- the guess iff the projection of r(guess) on the two
+#                   slowest-decaying eigenvectors of the Jacobi iteration is
+#                   shorter than that of r(u0): these two components decay
+#                   by rho per sweep, slower than every other, so they set
+#                   the sweep count at a tight tolerance, while the residual
+#                   norm of a guess is dominated by fast-decaying,
+#                   high-frequency components;
+#   "force"      -- always the guess.
+# Ties go to u0.
+
+RULES = ("residual", "slow_modes", "force")
+
+
+def slowest_modes(nx, ny, nz):
+    """phi(i, j, k) = sin(pi (i+1)/(nx+1)) sin(pi (j+1)/(ny+1)) sin(pi (k+1)/(nz+1))
+    and psi = (-1)^(i+j+k) phi over the interior (arrays [Z, Y, X]): the
+    eigenvectors of the 7-point operator with a zero Dirichlet halo whose
+    Jacobi iteration factors are +rho and -rho, rho = the mean of the three
+    cos(pi/(n+1))."""
+    def axis(n):
+        return np.sin(np.pi * np.arange(1, n + 1) / (n + 1))
+    phi = axis(nz)[:, None, None] * axis(ny)[None, :, None] * axis(nx)[None, None, :]
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sign = 1.0 - 2.0 * ((i + j + k) % 2)
+    return phi, sign * phi
+
+
+def slow_mode_norm(r):
+    """sqrt(<r, phi>^2 + <r, psi>^2) for an interior array r [Z, Y, X]."""
+    r = np.asarray(r, dtype=np.float64)
+    phi, psi = slowest_modes(r.shape[2], r.shape[1], r.shape[0])
+    p, q = float(np.sum(r * phi)), float(np.sum(r * psi))
+    return float(np.sqrt(p * p + q * q))
+
+
+def start_choice(u, f, guess, rule):
+    """Whether a solve of L(x) = f (Dirichlet halo of u) starts from `guess`
+    (interior array [Z, Y, X]) under `rule`; also returns the four measures
+    (||r(guess)||, ||r(u0)||, slow(r(guess)), slow(r(u0))), all in FP64."""
+    from .stencil import residual
+    if rule not in RULES:
+        raise ValueError(rule)
+    u0 = np.array(u, dtype=np.float64, copy=True)
+    u0[1:-1, 1:-1, 1:-1] = 0.0
+    xg = u0.copy()
+    xg[1:-1, 1:-1, 1:-1] = guess
+    rg, r0 = residual(xg, f), residual(u0, f)
+    meas = (float(np.sqrt(np.sum(rg * rg))), float(np.sqrt(np.sum(r0 * r0))),
+            slow_mode_norm(rg), slow_mode_norm(r0))
+    if rule == "force":
+        use = True
+    elif rule == "residual":
+        use = meas[0] < meas[1]
+    else:
+        use = meas[2] < meas[3]
+    return use, meas
