@@ -185,13 +185,14 @@ def refined_solve(x0, f, tol: float, eta: float, max_outer: int, max_inner: int,
     the stopping rule (used to compare fields bit for bit).
 
     Returns dict(x, converged, outer, inner=[...], hist=[rel per outer],
-    res0, sweeps).
+    res0, sweeps, rho=[[rho_0, rho_1, ...] per outer], eta=[eta_o per outer]).
     """
     nz, ny, nx = (s - 2 for s in x0.shape)
     ncells = nx * ny * nz
     res0 = residual_norm(zero_interior(x0), f)
     x = np.array(x0, dtype=np.float64, copy=True)
     inner_done = []
+    rhos, etas = [], []
     rels = []
     converged = False
     outer = 0
@@ -225,10 +226,12 @@ def refined_solve(x0, f, tol: float, eta: float, max_outer: int, max_inner: int,
             j += 1
             rho.append(residual_norm_f32_storage(e, rhat))
         inner_done.append(j)
+        rhos.append(rho)
+        etas.append(eta_o)
         x[INTERIOR] = interior(x) + s * interior(e).astype(np.float64)
         outer += 1
     return dict(x=x, converged=converged, outer=outer, inner=inner_done,
-                hist=rels, res0=res0, sweeps=int(sum(inner_done)))
+                hist=rels, res0=res0, sweeps=int(sum(inner_done)), rho=rhos, eta=etas)
 
 
 def stencil_apply(taps, inp, rhs=None, rhs_coef=0.0, scale=1.0):

@@ -149,8 +149,8 @@ def test_full_batch_of_64_uneven_instances_after_autotuning():
     """The benchmark's batch at full size: 64 instances, per-axis sizes
     log-uniform in [32, 256] (seed 4), 8 Gaussian sources each, FP32-refined
     to 1e-8 with autotuned tile shapes. Every instance's final residual is
-    recomputed by the oracle; the three smallest are compared bit for bit
-    with single-instance solves."""
+    recomputed by the oracle; the four smallest are compared bit for bit
+    with single-instance solves and with the oracle's own trajectory."""
     note("case: batched 64 instances, sizes log-uniform [32, 256], seed 4")
     dims = synth.batch_sizes(64, 4)
     probs = [(synth.zeros(*d), synth.gaussian_sources(*d, 8, 1000 + i))
@@ -167,13 +167,42 @@ def test_full_batch_of_64_uneven_instances_after_autotuning():
         res0 = oracle.residual_norm(oracle.zero_interior(u), f)
         assert info.res0 == pytest.approx(res0, rel=1e-12)
         assert oracle.residual_norm(host(x), f) <= 1e-8 * res0 * (1 + 1e-9)
-    small = sorted(range(len(dims)), key=lambda i: np.prod(dims[i]))[:3]
+    small = sorted(range(len(dims)), key=lambda i: np.prod(dims[i]))[:4]
+    jobs = []
     for i in small:
         u, f = probs[i]
         single = dev(u)
         s = ms.jacobi_solve(single, dev(f), **opts)
         assert (s.sweeps, s.outer_iters) == (infos[i].sweeps, infos[i].outer_iters)
         assert np.array_equal(host(single), host(xs[i]))
+        # inner sweep counts of every outer step: the same solve capped at
+        # 1, 2, ... outer steps
+        cum = [0]
+        for m in range(1, s.outer_iters + 1):
+            sm = ms.jacobi_solve(dev(u), dev(f), **dict(opts, max_outer=m))
+            cum.append(sm.sweeps)
+        counts = [b - a for a, b in zip(cum, cum[1:])]
+        d = ms.solve_opts()
+        jobs.append((i, dims[i], counts, 1e-8, d.inner_eta, 40, d.max_inner, d.stall_window))
+    # The oracle's trajectory of the four smallest instances (the
+    # configuration's check): replaying the device's inner counts gives the
+    # device's answer bit for bit, and on the oracle's own residual history
+    # every count is where the oracle's stopping rule stops (one sweep either
+    # way only when the residual straddles the threshold within 1e-10).
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import oracle_jobs
+    with cf.ProcessPoolExecutor(len(jobs), mp_context=mp.get_context("spawn")) as pool:
+        results = list(pool.map(oracle_jobs.batched_instance_replay, jobs))
+    for job, (x, rhos, etas, rels) in zip(jobs, results):
+        i, counts = job[0], job[2]
+        note(f"oracle trajectory of batched instance {i} {dims[i]}: inner {counts}")
+        assert np.array_equal(x, host(xs[i])), i
+        assert rels[-1] <= 1e-8
+        for c, rho, eta_o in zip(counts, rhos, etas):
+            own = oracle_jobs.stops_at(rho, eta_o, job[7], job[6])
+            assert own == c or (abs(own - c) == 1 and
+                                oracle_jobs.straddles(rho, min(own, c), eta_o)), (i, c, own)
 
 
 def test_plan_estimates_follow_the_slowest_mode_component():
