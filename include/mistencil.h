@@ -521,6 +521,76 @@ int cnn_guess(const ms_grid* g, const float* uhat, const double* scale, double l
 int cnn_target(const ms_grid* g, const double* u, const double* scale, double lambda,
                float* out, void* stream);
 
+/* ---- learned warm start, whole path --------------------------------------
+ * The network above behind two calls: an initial guess for jacobi_solve
+ * (warmstart_forward) and one training step on a solved instance
+ * (warmstart_train_step). Every arithmetic step runs on the device.
+ *
+ * Parameters: one caller-owned device buffer of warmstart_params_bytes()
+ * bytes, three blocks of warmstart_params_floats() floats: the FP32 master
+ * parameters, then Adam's first and second moments in the same layout
+ * (zero before the first training step). Master layout: layer l = 0..3
+ * starts at float warmstart_layer_offset(l) and holds its weights
+ * [27][32][cin_l] (cin = 8, 32, 32, 32; tap t = (dx+1) + 3(dy+1) + 9(dz+1);
+ * input channels beyond the real 2 of layer 0 and output channels beyond the
+ * real 1 of layer 3 are zero) followed by its 32 biases.
+ * The guess is x = s * out_scale * u_hat with s = max(max|f|, max|g|) of the
+ * features; out_scale is a property of the trained parameters (the trainer
+ * stores it beside them).
+ *
+ * work: device workspace of warmstart_workspace_bytes(g, train) bytes (train
+ * = 0 for warmstart_forward, 1 for warmstart_train_step); activations in it
+ * are rewritten on every call. */
+#define MS_START_RESIDUAL 0   /* keep the guess iff ||r(x)|| < ||r(u0)|| */
+#define MS_START_SLOW_MODES 1 /* keep it iff its slowest components are smaller */
+#define MS_START_FORCE 2      /* always keep the guess */
+size_t warmstart_params_floats(void);
+size_t warmstart_params_bytes(void);
+size_t warmstart_layer_offset(int layer);
+size_t warmstart_workspace_bytes(const ms_grid* g, int train);
+
+/* Initial guess for L(x) = f with the Dirichlet halo of u (u's interior is
+ * not read). Writes the guess into x's interior (x: grid g, FP64; its halo
+ * must hold the same Dirichlet values as u's; x may be u, must not overlap
+ * f), then chooses the start: with u0 = u with its interior zeroed,
+ *   MS_START_RESIDUAL:   keep the guess iff ||r(x)|| < ||r(u0)||;
+ *   MS_START_SLOW_MODES: keep it iff the projection of r(x) on the two
+ *     slowest-decaying eigenvectors of the Jacobi iteration (phi = the
+ *     product of sin(pi (i+1)/(n+1)) over the axes, eigenvalue rho; psi =
+ *     (-1)^(i+j+k) phi, eigenvalue -rho) is shorter than that of r(u0)
+ *     (these two set the sweep count at tight tolerances);
+ *   MS_START_FORCE:      always keep it;
+ * and zeroes x's interior again when u0 wins (x is then u0 exactly). All
+ * measures in FP64, r = f - (S - 6x). used (device int, may be NULL): 1 if
+ * the guess was kept. measures (device, 4 doubles, may be NULL):
+ * ||r(x)||, ||r(u0)||, slow(r(x)), slow(r(u0)). f may be NULL. Async. */
+int warmstart_forward(const ms_grid* g, const double* u, const double* f,
+                      const float* params, double out_scale, int rule, double* x,
+                      void* work, size_t work_bytes, int* used, double* measures,
+                      void* stream);
+
+/* One training step on a solved instance: forward pass on (u's halo, f),
+ * target u_solved / (s * out_scale) in FP32 (u_solved: the solved field on
+ * grid g), MSE loss mean over the interior voxels, gradients of every
+ * layer, then one Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr,
+ * 1-based step count `step`) on params (master and moments updated in
+ * place). loss (device double, may be NULL) receives the loss before the
+ * update, reduced in a fixed order. Async. */
+int warmstart_train_step(const ms_grid* g, const double* u, const double* f,
+                         const double* u_solved, float* params, double out_scale,
+                         float lr, int step, void* work, size_t work_bytes,
+                         double* loss, void* stream);
+
+/* ---- bandwidth probe ------------------------------------------------------
+ * Not a stencil: out[i] = a[i] + b[i] (b non-NULL: two reads, one write) or
+ * out[i] = a[i] (b NULL: one read, one write) over n doubles (n even; all
+ * arrays 16-byte aligned device memory; out must not overlap a or b), in
+ * 16-byte lanes with nontemporal stores, on `blocks` blocks of 256 threads.
+ * Measures the achievable HBM bandwidth of the stencils' access patterns.
+ * Async. */
+int ms_stream_probe(const double* a, const double* b, double* out, int64_t n,
+                    int blocks, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -57,7 +57,10 @@ constexpr int kAdvTX = 64;
 constexpr int kAdvLX = kAdvTX + 2;  // 66
 
 // kAdvRows rows per thread: tile 64 x 4*kAdvRows, LDS 4 x 3 x (tile + ring).
-template <int kAdvRows>
+// GUARD: centre loads predicated on the cell lying inside the field (the
+// earlier form, kept as a cross-check); otherwise they are unconditional
+// loads of clamped addresses.
+template <int kAdvRows, bool GUARD>
 __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
   constexpr int kAdvTY = kWavesY * kAdvRows;
   constexpr int kAdvLY = kAdvTY + 2;
@@ -80,13 +83,19 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
   double* __restrict__ out[3] = {a.su, a.sv, a.sw};
 
   // Centre cells of this thread: column i, rows j0 + wy*R + r.
+  // Centre loads are unconditional: a cell outside the field (i > nx or
+  // j > ny, which only inactive cells read) loads its clamped neighbour
+  // instead, so no load waits behind an execution-mask branch. Ring loads
+  // stay predicated on ring ownership, which is wave-uniform for most waves
+  // (the last wave owns no ring cell and issues no ring load).
   const int i = i0 + lane;
-  int64_t coff[kAdvRows];
+  int64_t coff[kAdvRows], aoff[kAdvRows];
   bool cld[kAdvRows], cact[kAdvRows];
 #pragma unroll
   for (int r = 0; r < kAdvRows; ++r) {
     const int j = j0 + wy * kAdvRows + r;
-    coff[r] = (int64_t)(j + 1) * sy + (i + 1);
+    coff[r] = (int64_t)(min(j, ny) + 1) * sy + (min(i, nx) + 1);
+    aoff[r] = (int64_t)(min(j, ny - 1) + 1) * sy + (min(i, nx - 1) + 1);
     cld[r] = i <= nx && j <= ny;
     cact[r] = i < nx && j < ny;
   }
@@ -106,8 +115,8 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
       rrow = t - 2 * kAdvLX - kAdvTY + 1; rcol = kAdvLX - 1; rown = true;
     }
   }
-  const int ri = i0 - 1 + rcol, rj = j0 - 1 + rrow;
-  const bool rld = rown && ri <= nx && rj <= ny;
+  const int ri = rown ? min(i0 - 1 + rcol, nx) : -1;
+  const int rj = rown ? min(j0 - 1 + rrow, ny) : -1;
   const int64_t roff = (int64_t)(rj + 1) * sy + (ri + 1);
 
   auto plane = [&](int k) { return (int64_t)(k + 1) * sz; };
@@ -116,8 +125,9 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
 #pragma unroll
-      for (int r = 0; r < kAdvRows; ++r) c[q][r] = cld[r] ? fld[q][plane(k) + coff[r]] : 0.0;
-      rg[q] = rld ? fld[q][plane(k) + roff] : 0.0;
+      for (int r = 0; r < kAdvRows; ++r)
+        c[q][r] = (!GUARD || cld[r]) ? fld[q][plane(k) + coff[r]] : 0.0;
+      rg[q] = rown ? fld[q][plane(k) + roff] : 0.0;
     }
   };
   auto store_level = [&](const double (&c)[3][kAdvRows], const double (&rg)[3], int b) {
@@ -134,12 +144,13 @@ __global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
   double um1[kAdvRows], vm1[kAdvRows], wm1[kAdvRows], wm1x[kAdvRows], wm1y[kAdvRows];
 #pragma unroll
   for (int r = 0; r < kAdvRows; ++r) {
-    const int64_t p = plane(z0 - 1) + coff[r];
-    um1[r] = cact[r] ? a.u[p] : 0.0;
-    vm1[r] = cact[r] ? a.v[p] : 0.0;
-    wm1[r] = cact[r] ? a.w[p] : 0.0;
-    wm1x[r] = cact[r] ? a.w[p + 1] : 0.0;
-    wm1y[r] = cact[r] ? a.w[p + sy] : 0.0;
+    const int64_t p = plane(z0 - 1) + aoff[r];
+    const bool ld = !GUARD || cact[r];
+    um1[r] = ld ? a.u[p] : 0.0;
+    vm1[r] = ld ? a.v[p] : 0.0;
+    wm1[r] = ld ? a.w[p] : 0.0;
+    wm1x[r] = ld ? a.w[p + 1] : 0.0;
+    wm1y[r] = ld ? a.w[p + sy] : 0.0;
   }
   {
     double c[3][kAdvRows], rg[3];
@@ -303,10 +314,11 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   if (nb > 0x7fffffffLL) return set_error(MS_EUNSUPPORTED, "advect_source: grid too large");
   a.zc = zc;
   a.nblocks = (int)nb;
-  if (rows == 1)
-    hipLaunchKernelGGL(advect_staged_kernel<1>, dim3(a.nblocks), dim3(kThreads), 0, s, a);
-  else
-    hipLaunchKernelGGL(advect_staged_kernel<2>, dim3(a.nblocks), dim3(kThreads), 0, s, a);
+  // MS_ADVECT_GUARD=1: the predicated centre loads (cross-check)
+  const bool guard = env_int("MS_ADVECT_GUARD") == 1;
+  auto* kern = rows == 1 ? (guard ? advect_staged_kernel<1, true> : advect_staged_kernel<1, false>)
+                         : (guard ? advect_staged_kernel<2, true> : advect_staged_kernel<2, false>);
+  hipLaunchKernelGGL(kern, dim3(a.nblocks), dim3(kThreads), 0, s, a);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

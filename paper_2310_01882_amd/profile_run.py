@@ -100,9 +100,9 @@ def main():
         net = wsm.WarmStart(n, n, n, seed=0)
         u = ms.alloc_field(n, n, n)
         f = ms.field_from(synth.gaussian_sources(n, n, n, 4, 7))
-        target = torch.zeros_like(net.out32)
+        solved = ms.alloc_field(n, n, n)  # a stand-in solution: the time does not depend on it
         for _ in range(args.steps):
-            net.train_step(u, f, target)
+            net.train_step(u, f, solved)
         torch.cuda.synchronize()
         print(f"{args.steps} warm-start training steps at {n}^3 done", flush=True)
         return
