@@ -195,6 +195,23 @@ int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
                      double* res_dev, void* work, size_t work_bytes,
                      void* stream);
 
+/* As jacobi_sweeps_tb, for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid it): no
+ * workspace argument, and the call allocates nothing. The residual partials
+ * live in a fixed device array of jacobi_sweeps_noalloc_scratch_bytes()
+ * bytes (2 MiB) per GPU, held until the process ends; every grid that
+ * jacobi_sweeps accepts fits it (a larger need returns MS_EWORKSPACE).
+ * Calls on one GPU share that array: calls that overlap in time on one GPU
+ * (different streams, or different host threads) race and must not be
+ * issued; calls in sequence on one stream are safe. Nothing in the array
+ * has to start at zero. Results are bit-identical to jacobi_sweeps_tb.
+ * The first call on each device looks the array's address up (with that
+ * device current). Async. */
+size_t jacobi_sweeps_noalloc_scratch_bytes(void);
+int jacobi_sweeps_noalloc(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                          const void* f, int64_t n, int temporal_block,
+                          double* res_dev, void* stream);
+
 /* ---- Jacobi sweeps on a field held in host memory -------------------------
  * Exactly n >= 0 sweeps of jacobi_sweeps on a field that stays in host
  * memory (Section 4.3's data management taken to fields larger than the

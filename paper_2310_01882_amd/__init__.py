@@ -113,6 +113,8 @@ SIGNATURES = {
     "jacobi_sweeps_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
     "jacobi_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "jacobi_sweeps_tb": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _P, _P, _SZ, _P]),
+    "jacobi_sweeps_noalloc_scratch_bytes": (_SZ, []),
+    "jacobi_sweeps_noalloc": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _P, _P]),
     "rbgs_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _P, _P, _SZ, _P]),
     "jacobi_sweeps_streamed_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), _I, _I, _I]),
     "jacobi_sweeps_streamed": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I64, _I, _I, _P, _SZ,
@@ -365,6 +367,27 @@ def stream_probe(a, out, b=None, blocks=2048, stream=None):
     _check(lib.ms_stream_probe(_ptr(a), _ptr(b), _ptr(out), a.numel(), int(blocks),
                                _stream(stream)))
     return out
+
+
+def jacobi_sweeps_noalloc(u, u_tmp, n, f=None, res=None, stream=None, temporal_block=1):
+    """``jacobi_sweeps`` through the entry point that allocates nothing: the
+    residual partials live in the library's fixed per-device array, so calls
+    that overlap in time on one GPU race. Same arguments (no ``work``), same
+    results, same returned buffer."""
+    _field_check(u, "u")
+    _field_check(u_tmp, "u_tmp", u.dtype)
+    _same_layout(u, u_tmp, "u/u_tmp")
+    if f is not None:
+        _field_check(f, "f", u.dtype)
+        _same_layout(u, f, "u/f")
+    if res is not None and (res.dtype != torch.float64 or res.numel() < n + 1):
+        raise ValueError("res must be float64 with n + 1 entries")
+    g = grid_of(u)
+    tb = int(temporal_block)
+    _check(lib.jacobi_sweeps_noalloc(ctypes.byref(g), _dtype_code(u), _ptr(u), _ptr(u_tmp),
+                                     _ptr(f), int(n), tb, _ptr(res), _stream(stream)))
+    passes = n if tb == 1 else n // 2 + n % 2
+    return u if passes % 2 == 0 else u_tmp
 
 
 def rbgs_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None):

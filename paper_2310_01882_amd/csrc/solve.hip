@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -320,10 +321,13 @@ extern "C" size_t jacobi_sweeps_workspace_bytes(const ms_grid* g) {
   return align_up(kPartialsBytes, 256);
 }
 
-extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
-                                const void* f, int64_t n, int temporal_block, double* res_dev,
-                                void* work, size_t work_bytes, void* stream) {
-  clear_error();
+namespace ms {
+namespace {
+
+// Arguments of jacobi_sweeps_tb other than the workspace; returns 0 or an
+// MS_* code with the error text set.
+int check_sweeps_args(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,
+                      int64_t n, int temporal_block) {
   if (int rc = check_grid(g, "jacobi_sweeps")) return rc;
   if (dtype != MS_F64 && dtype != MS_F32)
     return set_error(MS_EUNSUPPORTED, "jacobi_sweeps: dtype %d", dtype);
@@ -336,13 +340,15 @@ extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tm
     return set_error(MS_EINVAL, "jacobi_sweeps: u and u_tmp overlap");
   if (f && (overlaps(f, bytes, u, bytes) || overlaps(f, bytes, u_tmp, bytes)))
     return set_error(MS_EINVAL, "jacobi_sweeps: f overlaps a sweep buffer");
-  const size_t need = jacobi_sweeps_workspace_bytes(g);
-  if (!work || work_bytes < need)
-    return set_error(MS_EWORKSPACE, "jacobi_sweeps: workspace needs %zu bytes", need);
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return MS_OK;
+}
+
+// n sweeps on checked arguments; `partials` holds kPartialsBytes. Nothing in
+// it needs to start at zero: every launch writes the slot it later reads.
+int sweeps_on(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f, int64_t n,
+              int temporal_block, double* res_dev, double* partials, hipStream_t s) {
   const void* ptrs[3] = {u, u_tmp, f};
   const SweepGeom geo = sweep_geom(*g, dtype, vec_alignment(*g, dtype, ptrs, 3));
-  double* partials = static_cast<double*>(work);
   void* bufs[3] = {u, u_tmp, u};
   void* last = u;
   if (temporal_block == 1) {
@@ -383,6 +389,80 @@ extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tm
       return rc;
   }
   return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" int jacobi_sweeps_tb(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                                const void* f, int64_t n, int temporal_block, double* res_dev,
+                                void* work, size_t work_bytes, void* stream) {
+  clear_error();
+  if (int rc = check_sweeps_args(g, dtype, u, u_tmp, f, n, temporal_block)) return rc;
+  const size_t need = jacobi_sweeps_workspace_bytes(g);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "jacobi_sweeps: workspace needs %zu bytes", need);
+  return sweeps_on(g, dtype, u, u_tmp, f, n, temporal_block, res_dev,
+                   static_cast<double*>(work), static_cast<hipStream_t>(stream));
+}
+
+// ----------------------------------------------------- jacobi_sweeps_noalloc
+//
+// The same sweeps with the partials table in a fixed device array instead of
+// a caller workspace, for callers that cannot allocate. Each device holds
+// its own copy of the array; its address is looked up once per device, with
+// that device current, and only that address is handed to kernels.
+
+namespace ms {
+namespace {
+
+constexpr size_t kScratchBytes = kPartialsBytes;  // 2 MiB per device
+constexpr int kScratchDevices = 64;
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of the current device's scratch array.
+int scratch_address(void** out) {
+  int dev = -1;
+  MS_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return set_error(MS_EUNSUPPORTED, "jacobi_sweeps_noalloc: device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return set_error(MS_EHIP, "jacobi_sweeps_noalloc: hipGetSymbolAddress failed: %s",
+                       hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return MS_OK;
+}
+
+}  // namespace
+}  // namespace ms
+
+extern "C" size_t jacobi_sweeps_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+extern "C" int jacobi_sweeps_noalloc(const ms_grid* g, int dtype, void* u, void* u_tmp,
+                                     const void* f, int64_t n, int temporal_block,
+                                     double* res_dev, void* stream) {
+  clear_error();
+  if (int rc = check_sweeps_args(g, dtype, u, u_tmp, f, n, temporal_block)) return rc;
+  const size_t need = jacobi_sweeps_workspace_bytes(g);
+  if (need > kScratchBytes)
+    return set_error(MS_EWORKSPACE,
+                     "jacobi_sweeps_noalloc: needs %zu bytes of scratch, the fixed array "
+                     "holds %zu",
+                     need, kScratchBytes);
+  void* p = nullptr;
+  if (int rc = scratch_address(&p)) return rc;
+  return sweeps_on(g, dtype, u, u_tmp, f, n, temporal_block, res_dev, static_cast<double*>(p),
+                   static_cast<hipStream_t>(stream));
 }
 
 extern "C" int rbgs_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, const void* f,

@@ -287,3 +287,16 @@ def test_warmstart_entry_points_validate_before_touching_a_device():
     assert step(ctypes.byref(g), P[0], P[1], P[2], P[3], 4.0, ctypes.c_float(1e-3), 1, P[4],
                 need, None, None) == ms.MS_EWORKSPACE
     assert ms.last_error()
+
+
+def test_noalloc_sweeps_validate_and_report_their_scratch():
+    import paper_2310_01882_amd as ms
+    g = _grid(ms)
+    assert ms.lib.jacobi_sweeps_noalloc_scratch_bytes() >= \
+        ms.lib.jacobi_sweeps_workspace_bytes(ctypes.byref(g))
+    assert ms.lib.jacobi_sweeps_noalloc(ctypes.byref(g), ms.MS_F64, FAKE, FAKE, None, 1, 1, None,
+                                        None) == ms.MS_EINVAL
+    assert ms.lib.jacobi_sweeps_noalloc(ctypes.byref(g), ms.MS_F64, FAKE, FAKE2, None, 1, 3, None,
+                                        None) == ms.MS_EUNSUPPORTED
+    assert ms.lib.jacobi_sweeps_noalloc(ctypes.byref(g), 9, FAKE, FAKE2, None, 1, 1, None,
+                                        None) == ms.MS_EUNSUPPORTED
