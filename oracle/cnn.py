@@ -163,9 +163,49 @@ def boundary_lift(u):
     return g
 
 
+# Half-widths of the cube averages of f/s among the features: windows of
+# side 5, 11, 23, 47 and 95 cells.
+BOX_HALF = (2, 5, 11, 23, 47)
+
+
+def box_sum_axis(a, h, axis):
+    """b[p] = sum of a[p + d e_axis] for d = -h .. h in increasing d, with
+    zero outside the array (a [Z, Y, X] array; axis 0 = z)."""
+    n = a.shape[axis]
+    out = np.zeros_like(a)
+    for d in range(-h, h + 1):
+        lo, hi = max(0, -d), min(n, n - d)  # out[lo:hi] += a[lo+d:hi+d]
+        if lo >= hi:
+            continue
+        dst = [slice(None)] * 3
+        src = [slice(None)] * 3
+        dst[axis] = slice(lo, hi)
+        src[axis] = slice(lo + d, hi + d)
+        out[tuple(dst)] = out[tuple(dst)] + a[tuple(src)]
+    return out
+
+
+def box_mean(a, h):
+    """Mean of a over the (2h+1)^3 cube around each cell, zero outside the
+    interior: sums along x, then y, then z (each in increasing offset), then
+    one division by the cube's volume."""
+    t = box_sum_axis(np.asarray(a, dtype=np.float64), h, 2)
+    t = box_sum_axis(t, h, 1)
+    t = box_sum_axis(t, h, 0)
+    return t / float((2 * h + 1) ** 3)
+
+
 def features(u, f):
-    """Network input [f/s, g/s] and the scale s = max(max|f|, max|g|) (1 if 0).
-    f and u are halo-padded; features cover the interior."""
+    """Network input, 8 channels over the interior, and the scale s =
+    max(max|f|, max|g|) (1 if 0). Channels: f/s, g/s, the cube means of f/s
+    of half-widths BOX_HALF[0..3], phi (the product of sin(pi (i+1)/(n+1))
+    over the axes, i.e. the slowest Jacobi mode: the cell's place in the
+    domain), the cube mean of half-width BOX_HALF[4]. f and u are halo-padded.
+
+    Reading (the paper has no learned part): a 3x3x3 four-layer network sees
+    a 9^3 patch, while the solution at a cell depends on the right-hand side
+    everywhere; the cube means give that patch the source mass around it at
+    several scales, and phi where it sits between the zero boundaries."""
     fi = np.asarray(f, dtype=np.float64)[1:-1, 1:-1, 1:-1] if f is not None else None
     g = boundary_lift(u)
     if fi is None:
@@ -173,14 +213,32 @@ def features(u, f):
     s = max(float(np.max(np.abs(fi))), float(np.max(np.abs(g))))
     if s == 0.0:
         s = 1.0
-    return np.stack([fi / s, g / s]), s
+    fs = fi / s
+    nz, ny, nx = fs.shape
+    phi, _ = slowest_modes(nx, ny, nz)
+    chans = [fs, g / s] + [box_mean(fs, h) for h in BOX_HALF[:4]] + [phi, box_mean(fs, BOX_HALF[4])]
+    return np.stack(chans), s
 
 
-def output_scale(nx, ny, nz):
-    """lambda = max(n)^2 / 8: the solution of a unit-scale source grows like
-    the square of the domain size; the network predicts u / (s * lambda)."""
-    n = max(nx, ny, nz)
-    return n * n / 8.0
+def smooth_guess(x, f, sweeps, omega=2.0 / 3.0):
+    """`sweeps` damped Jacobi sweeps on L(x) = f (Dirichlet halo of x):
+    x <- x + omega * (J(x) - x) with J(x) = (S(x) - f) * fl(1/6) the plain
+    sweep's update, evaluated in that order in FP64.
+
+    Reading: a learned guess carries cell-to-cell errors; in plain Jacobi the
+    modes near the checkerboard decay no faster than the smoothest one, so
+    such errors cost as many sweeps as a wrong smooth component. A damped
+    sweep multiplies every mode by 1 - omega (1 - mu) (mu its plain Jacobi
+    factor), which for omega = 2/3 is at most 1/3 in size for mu <= 0, so a
+    few of them remove those errors and leave the smooth part of the guess
+    nearly untouched."""
+    from .stencil import interior, jacobi_sweep
+    x = np.array(x, dtype=np.float64, copy=True)
+    for _ in range(sweeps):
+        j = interior(jacobi_sweep(x, f))
+        xi = interior(x)
+        x[1:-1, 1:-1, 1:-1] = xi + omega * (j - xi)
+    return x
 
 
 # ------------------------------------------------------- start selection
