@@ -261,16 +261,21 @@ def stream_ceiling(mib=1024, reps=20):
     stream = torch.cuda.current_stream()
     res = {}
     for name, two in (("read1_write1", False), ("read2_write1", True)):
-        best = 0.0
-        for blocks in (1024, 2048, 4096, 8192):
-            def step():
-                ms.stream_probe(a, out, b if two else None, blocks=blocks, stream=stream)
-            secs = event_time(step, reps, 2, stream)
-            best = max(best, (3 if two else 2) * n * 8 * reps / secs / 1e9)
+        best, how = 0.0, None
+        for form in (0, 1, 2):
+            for blocks in (1024, 2048, 4096, 8192):
+                def step():
+                    ms.stream_probe(a, out, b if two else None, blocks=blocks, form=form,
+                                    stream=stream)
+                secs = event_time(step, reps, 2, stream)
+                gbs = (3 if two else 2) * n * 8 * reps / secs / 1e9
+                if gbs > best:
+                    best, how = gbs, {"form": form, "blocks": blocks}
         res[name + "_gbs"] = round(best, 1)
+        res[name + "_best"] = how
     del a, b, out
     torch.cuda.empty_cache()
-    res["kernel"] = "ms_stream_probe (16-byte lanes, nontemporal stores)"
+    res["kernel"] = "ms_stream_probe (16-byte lanes, nontemporal stores; best form and grid)"
     return res
 
 

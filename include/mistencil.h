@@ -479,11 +479,11 @@ int advect_source(const ms_grid* g, const double* u, const double* v,
                   void* stream);
 
 /* ---- learned warm start: 3x3x3 convolutions on BF16 MFMA ----------------
- * Not in the paper: a small 3D CNN (2 -> 32 -> 32 -> 32 -> 1 channels,
- * ReLU after the first three layers) maps [f/s, g/s] (right-hand side and
- * boundary lift g, scaled by s = max(max|f|, max|g|)) to u / (s * lambda),
- * an initial guess for jacobi_solve. These entry points are its training
- * and inference kernels.
+ * Not in the paper: a small 3D CNN (8 -> 32 -> 32 -> 32 -> 1 channels,
+ * ReLU after the first three layers) maps features of the right-hand side
+ * f and the boundary lift g (scaled by s = max(max|f|, max|g|); see
+ * cnn_features) to u / (s * lambda), an initial guess for jacobi_solve.
+ * These entry points are its training and inference kernels.
  *
  * Activations: BF16, channels-last over an X x Y x Z volume with a
  * one-voxel zero halo (the "same" zero padding of the convolution): element
@@ -525,11 +525,16 @@ int cnn_adam(int cin, float* w, float* b, float* mw, float* vw, float* mb, float
              void* stream);
 /* BF16 copies of FP32 master weights in both layouts. */
 int cnn_pack_weights(int cin, const float* w, void* wf, void* wd, void* stream);
-/* Features [f/s, g/s, 0 x 6] (BF16, C = 8) of the Poisson problem (u: halo =
- * Dirichlet values, f may be NULL) and *scale = s (device); part: nparts
- * doubles of scratch. */
+/* Network input (BF16, C = 8) of the Poisson problem (u: halo = Dirichlet
+ * values, f may be NULL) and *scale = s (device). Channels: 0 f/s, 1 g/s,
+ * 2..5 the means of f/s over cubes of side 5, 11, 23, 47 around the cell
+ * (zero outside the interior; sums along x, then y, then z, each over
+ * increasing offsets, then one division by the cube's volume), 6 the
+ * slowest Jacobi mode prod_a sin(pi (i_a+1)/(n_a+1)), 7 the mean over cubes
+ * of side 95. work: cnn_features_workspace_bytes(g) bytes. */
+size_t cnn_features_workspace_bytes(const ms_grid* g);
 int cnn_features(const ms_grid* g, const double* u, const double* f, void* feat,
-                 double* scale, double* part, int nparts, void* stream);
+                 double* scale, void* work, size_t work_bytes, void* stream);
 /* x interior = (*scale) * lambda * uhat (FP64); the halo is not touched. */
 int cnn_guess(const ms_grid* g, const float* uhat, const double* scale, double lambda,
               double* x, void* stream);
@@ -569,7 +574,10 @@ size_t warmstart_workspace_bytes(const ms_grid* g, int train);
 /* Initial guess for L(x) = f with the Dirichlet halo of u (u's interior is
  * not read). Writes the guess into x's interior (x: grid g, FP64; its halo
  * must hold the same Dirichlet values as u's; x may be u, must not overlap
- * f), then chooses the start: with u0 = u with its interior zeroed,
+ * f), applies `smooth` damped Jacobi sweeps to it (even, 0 .. 64:
+ * x <- x + (2/3) (J(x) - x), J(x) = (S(x) - f) * fl(1/6) the plain sweep's
+ * update, FP64, in this order), then chooses the start: with u0 = u with
+ * its interior zeroed,
  *   MS_START_RESIDUAL:   keep the guess iff ||r(x)|| < ||r(u0)||;
  *   MS_START_SLOW_MODES: keep it iff the projection of r(x) on the two
  *     slowest-decaying eigenvectors of the Jacobi iteration (phi = the
@@ -582,9 +590,9 @@ size_t warmstart_workspace_bytes(const ms_grid* g, int train);
  * the guess was kept. measures (device, 4 doubles, may be NULL):
  * ||r(x)||, ||r(u0)||, slow(r(x)), slow(r(u0)). f may be NULL. Async. */
 int warmstart_forward(const ms_grid* g, const double* u, const double* f,
-                      const float* params, double out_scale, int rule, double* x,
-                      void* work, size_t work_bytes, int* used, double* measures,
-                      void* stream);
+                      const float* params, double out_scale, int smooth, int rule,
+                      double* x, void* work, size_t work_bytes, int* used,
+                      double* measures, void* stream);
 
 /* One training step on a solved instance: forward pass on (u's halo, f),
  * target u_solved / (s * out_scale) in FP32 (u_solved: the solved field on
@@ -602,11 +610,13 @@ int warmstart_train_step(const ms_grid* g, const double* u, const double* f,
  * Not a stencil: out[i] = a[i] + b[i] (b non-NULL: two reads, one write) or
  * out[i] = a[i] (b NULL: one read, one write) over n doubles (n even; all
  * arrays 16-byte aligned device memory; out must not overlap a or b), in
- * 16-byte lanes with nontemporal stores, on `blocks` blocks of 256 threads.
+ * 16-byte lanes with nontemporal stores, on `blocks` blocks of 256 threads,
+ * grid-stride. form 0: one element per lane per stride; 1: four strides of
+ * loads issued before their stores; 2: as 1 with nontemporal loads.
  * Measures the achievable HBM bandwidth of the stencils' access patterns.
  * Async. */
 int ms_stream_probe(const double* a, const double* b, double* out, int64_t n,
-                    int blocks, void* stream);
+                    int blocks, int form, void* stream);
 
 #ifdef __cplusplus
 }

@@ -157,15 +157,17 @@ SIGNATURES = {
     "cnn_mse_grad": (_I, [_I, _I, _I, _P, _P, _P, _P, _I, _P]),
     "cnn_adam": (_I, [_I, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _I, _P]),
     "cnn_pack_weights": (_I, [_I, _P, _P, _P, _P]),
-    "cnn_features": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _I, _P]),
+    "cnn_features_workspace_bytes": (_SZ, [ctypes.POINTER(Grid)]),
+    "cnn_features": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _P, _SZ, _P]),
     "cnn_guess": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
     "cnn_target": (_I, [ctypes.POINTER(Grid), _P, _P, _D, _P, _P]),
-    "ms_stream_probe": (_I, [_P, _P, _P, _I64, _I, _P]),
+    "ms_stream_probe": (_I, [_P, _P, _P, _I64, _I, _I, _P]),
     "warmstart_params_floats": (_SZ, []),
     "warmstart_params_bytes": (_SZ, []),
     "warmstart_layer_offset": (_SZ, [_I]),
     "warmstart_workspace_bytes": (_SZ, [ctypes.POINTER(Grid), _I]),
-    "warmstart_forward": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _D, _I, _P, _P, _SZ, _P, _P, _P]),
+    "warmstart_forward": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _D, _I, _I, _P, _P, _SZ, _P, _P,
+                               _P]),
     "warmstart_train_step": (_I, [ctypes.POINTER(Grid), _P, _P, _P, _P, _D, ctypes.c_float, _I,
                                   _P, _SZ, _P, _P]),
     "ms_jit_compile": (_I, [ctypes.c_char_p, _I, ctypes.POINTER(_P)]),
@@ -357,14 +359,14 @@ def jacobi_sweeps(u, u_tmp, n, f=None, res=None, work=None, stream=None, tempora
     return u if passes % 2 == 0 else u_tmp
 
 
-def stream_probe(a, out, b=None, blocks=2048, stream=None):
+def stream_probe(a, out, b=None, blocks=2048, form=0, stream=None):
     """ms_stream_probe: out = a (+ b) over float64 device tensors."""
     for t, name in ((a, "a"), (out, "out"), (b, "b")):
         if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
             raise ValueError(f"{name} must be a contiguous float64 device tensor")
     if out.numel() != a.numel() or (b is not None and b.numel() != a.numel()):
         raise ValueError("a, b and out must have the same size")
-    _check(lib.ms_stream_probe(_ptr(a), _ptr(b), _ptr(out), a.numel(), int(blocks),
+    _check(lib.ms_stream_probe(_ptr(a), _ptr(b), _ptr(out), a.numel(), int(blocks), int(form),
                                _stream(stream)))
     return out
 

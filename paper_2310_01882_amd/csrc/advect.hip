@@ -8,9 +8,9 @@
 // where P on each side is phi at the neighbour on that side times the sum of
 // the two samples of the advecting velocity that straddle that face.
 //
-// Staged kernel (default): a block owns a 64 x 4 (x, y) tile (one row per
-// thread; 64 x 8 with two rows per thread is the alternative) and marches a
-// z-chunk. Planes of u, v, w (tile plus a one-cell ring, corners included)
+// Staged kernel (default): a block of eight waves owns a 64 x 8 (x, y) tile,
+// one row per thread (four-wave blocks with 64 x 4 tiles, or 64 x 8 with two
+// rows per thread, are the alternatives), and marches a z-chunk. Planes of u, v, w (tile plus a one-cell ring, corners included)
 // pass through a ring of four LDS buffers: at level k the block reads level
 // k (all in-plane neighbours) and level k+1 (the four off-column values the
 // upper face needs), writes level k+2 that it loaded into registers two
@@ -60,12 +60,13 @@ constexpr int kAdvLX = kAdvTX + 2;  // 66
 // GUARD: centre loads predicated on the cell lying inside the field (the
 // earlier form, kept as a cross-check); otherwise they are unconditional
 // loads of clamped addresses.
-template <int kAdvRows, bool GUARD>
-__global__ __launch_bounds__(kThreads) void advect_staged_kernel(AdvK a) {
-  constexpr int kAdvTY = kWavesY * kAdvRows;
+// W waves per block, stacked in y: the tile is 64 x (W * kAdvRows).
+template <int kAdvRows, bool GUARD, int W>
+__global__ __launch_bounds__(64 * W) void advect_staged_kernel(AdvK a) {
+  constexpr int kAdvTY = W * kAdvRows;
   constexpr int kAdvLY = kAdvTY + 2;
   constexpr int kAdvRing = 2 * kAdvLX + 2 * kAdvTY;  // ring cells per field
-  static_assert(kAdvRing <= kThreads, "one ring cell per thread");
+  static_assert(kAdvRing <= 64 * W, "one ring cell per thread");
   __shared__ double L[4][3][kAdvLY][kAdvLX];
 
   const int tile = xcd_tile(blockIdx.x, a.nblocks);
@@ -293,15 +294,20 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
     MS_LAUNCH_CHECK();
     return MS_OK;
   }
-  // Staged kernel: one block round of long z marches. MS_ADVECT_ROWS (1 or
-  // 2 rows per thread) and MS_ADVECT_BLOCKS (target grid) are tuning knobs.
-  // Measured at 512 x 512 x 256: one row per thread (38 KB of LDS, four
-  // resident blocks per CU) and 1024 blocks beat two rows (63 KB, two per CU)
-  // by 7%.
+  // Staged kernel: one block round of long z marches. Default: blocks of
+  // eight waves (64 x 8 tiles, one row per thread; 63 KB of LDS, two blocks
+  // per CU) on 512 blocks. Measured at 512 x 512 x 256 on one box: 675 us,
+  // against 692 us on 1024 blocks and 728 us for four-wave blocks (64 x 4
+  // tiles: more ring cells per cell). MS_ADVECT_WAVES (4 or 8),
+  // MS_ADVECT_ROWS (1 or 2 rows per thread, four-wave blocks) and
+  // MS_ADVECT_BLOCKS (target grid) select the alternatives.
   const int rows = env_int("MS_ADVECT_ROWS") == 2 ? 2 : 1;
-  const int64_t want = env_int("MS_ADVECT_BLOCKS") > 0 ? env_int("MS_ADVECT_BLOCKS") : 1024;
+  const int waves = (env_int("MS_ADVECT_WAVES") == 4 || rows == 2) ? 4 : 8;
+  const int64_t want = env_int("MS_ADVECT_BLOCKS") > 0 ? env_int("MS_ADVECT_BLOCKS")
+                       : waves == 8                    ? 512
+                                                       : 1024;
   a.tiles_x = (g->nx + kAdvTX - 1) / kAdvTX;
-  a.tiles_y = (g->ny + kWavesY * rows - 1) / (kWavesY * rows);
+  a.tiles_y = (g->ny + waves * rows - 1) / (waves * rows);
   const int64_t tiles2d = (int64_t)a.tiles_x * a.tiles_y;
   int zc = env_int("MS_ADVECT_ZC");
   if (zc <= 0) {
@@ -316,9 +322,14 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   a.nblocks = (int)nb;
   // MS_ADVECT_GUARD=1: the predicated centre loads (cross-check)
   const bool guard = env_int("MS_ADVECT_GUARD") == 1;
-  auto* kern = rows == 1 ? (guard ? advect_staged_kernel<1, true> : advect_staged_kernel<1, false>)
-                         : (guard ? advect_staged_kernel<2, true> : advect_staged_kernel<2, false>);
-  hipLaunchKernelGGL(kern, dim3(a.nblocks), dim3(kThreads), 0, s, a);
+  void (*kern)(AdvK);
+  if (waves == 8)
+    kern = guard ? advect_staged_kernel<1, true, 8> : advect_staged_kernel<1, false, 8>;
+  else if (rows == 1)
+    kern = guard ? advect_staged_kernel<1, true, 4> : advect_staged_kernel<1, false, 4>;
+  else
+    kern = guard ? advect_staged_kernel<2, true, 4> : advect_staged_kernel<2, false, 4>;
+  hipLaunchKernelGGL(kern, dim3(a.nblocks), dim3(64 * waves), 0, s, a);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

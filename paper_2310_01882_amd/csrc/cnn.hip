@@ -200,9 +200,15 @@ void conv_rows_kernel(RowK a) {
   constexpr int C = 32;
   constexpr int R = kConvRows;
   constexpr int sgn = kDgrad ? -1 : 1;
+  // Weights in LDS as 16-byte chunks ordered [tap][channel half][m][h]
+  // (global order: [tap][m][c8], c8 = 2 * half + h), so that the 64 lanes
+  // of one operand read (fixed tap and half; m = lane % 32, h = lane / 32)
+  // take 64 consecutive chunks: no two lanes of a read share a bank.
   __shared__ bf16x8 wl[kTaps * kCo * C / 8];
-  for (int t = threadIdx.x; t < kTaps * kCo * C / 8; t += blockDim.x)
-    wl[t] = reinterpret_cast<const bf16x8*>(a.w)[t];
+  for (int gi = threadIdx.x; gi < kTaps * kCo * C / 8; gi += blockDim.x) {
+    const int t = gi / (kCo * 4), co = (gi / 4) % kCo, c8 = gi % 4;
+    wl[((t * 2 + c8 / 2) * kCo + co) * 2 + c8 % 2] = reinterpret_cast<const bf16x8*>(a.w)[gi];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = lane & 31, h = lane >> 5;
@@ -232,12 +238,12 @@ void conv_rows_kernel(RowK a) {
 #pragma unroll
     for (int g = 0; g < 18; ++g) {
       if (g + 1 < 18) load_rows(nxt, g + 1);
-      const int dz = g / 6 - 1, dx = (g / 2) % 3 - 1, c0 = (g % 2) * 16 + 8 * h;
+      const int dz = g / 6 - 1, dx = (g / 2) % 3 - 1;
       bf16x8 bv[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         const int t = (dx + 1) + 3 * d + 9 * (dz + 1);  // dy = d - 1
-        bv[d] = wl[((t * kCo + m) * C + c0) / 8];
+        bv[d] = wl[((t * 2 + g % 2) * kCo + m) * 2 + h];
       }
 #pragma unroll
       for (int r = 0; r < R; ++r)
@@ -892,14 +898,34 @@ __global__ __launch_bounds__(256) void feat_max_kernel(ms_grid g, const double* 
   }
 }
 
-__global__ void feat_scale_kernel(const double* part, int nb, double* scale) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 256 threads: the max over the block partials (max is exact
+// and order-independent).
+__global__ __launch_bounds__(256) void feat_scale_kernel(const double* part, int nb,
+                                                         double* scale) {
+  __shared__ double red[kWavesY];
   double r = 0.0;
-  for (int b = 0; b < nb; ++b) r = fmax(r, part[b]);
-  *scale = r > 0.0 ? r : 1.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) r = fmax(r, part[b]);
+  for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_down(r, off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    *scale = m > 0.0 ? m : 1.0;
+  }
 }
 
-// features [f/s, g/s, 0 x 6] in BF16, 8 channels, interior voxels.
+// Feature channels (BF16, 8 per voxel): 0 f/s, 1 g/s, 2..5 cube means of
+// f/s of half-widths kBoxHalf[0..3], 6 the slowest Jacobi mode
+// phi = prod sin(pi (i+1)/(n+1)), 7 the cube mean of half-width kBoxHalf[4].
+constexpr int kBoxHalf[5] = {2, 5, 11, 23, 47};
+constexpr int kBoxChannel[5] = {2, 3, 4, 5, 7};
+
+__device__ __forceinline__ double mode_factor(int i, int n) {
+  return sin((M_PI * (double)(i + 1)) / (double)(n + 1));
+}
+
+// Channels 0, 1 and 6 (the cube means are written by box_z_kernel).
 __global__ void feat_write_kernel(ms_grid g, const double* u, const double* f,
                                   const double* scale, Vol v, bf16* feat) {
   const int64_t n = (int64_t)g.nx * g.ny * g.nz;
@@ -912,7 +938,58 @@ __global__ void feat_write_kernel(ms_grid g, const double* u, const double* f,
     bf16x8 val = zero8();
     val[0] = (bf16)(float)((f ? f[p] : 0.0) / s);
     val[1] = (bf16)(float)(lift(u, g, i, j, k) / s);
+    const double phi = (mode_factor(k, g.nz) * mode_factor(j, g.ny)) * mode_factor(i, g.nx);
+    val[6] = (bf16)(float)phi;
     *reinterpret_cast<bf16x8*>(feat + v.vox(i, j, k) * 8) = val;
+  }
+}
+
+// Separable cube sums of f/s over the interior (zero outside), each pass a
+// sum over offsets -h .. h in increasing order. x pass: from the field f;
+// y pass: between dense interior volumes t[(k * ny + j) * nx + i]; z pass:
+// divides by the cube's volume and writes one feature channel.
+__global__ void box_x_kernel(ms_grid g, const double* f, const double* scale, int h,
+                             double* out) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const double s = *scale;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    double acc = 0.0;
+    if (f) {
+      const int lo = max(-h, -i), hi = min(h, g.nx - 1 - i);
+      for (int d = lo; d <= hi; ++d) acc = acc + f[p + d] / s;
+    }
+    out[t] = acc;
+  }
+}
+
+__global__ void box_y_kernel(int nx, int ny, int nz, int h, const double* in, double* out) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)((t / nx) % ny);
+    const int lo = max(-h, -j), hi = min(h, ny - 1 - j);
+    double acc = 0.0;
+    for (int d = lo; d <= hi; ++d) acc = acc + in[t + (int64_t)d * nx];
+    out[t] = acc;
+  }
+}
+
+__global__ void box_z_kernel(int nx, int ny, int nz, int h, const double* in, Vol v, int ch,
+                             bf16* feat) {
+  const int64_t n = (int64_t)nx * ny * nz;
+  const int64_t pl = (int64_t)nx * ny;
+  const double vol = (double)((2 * h + 1) * (2 * h + 1) * (2 * h + 1));
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % nx), j = (int)((t / nx) % ny), k = (int)(t / pl);
+    const int lo = max(-h, -k), hi = min(h, nz - 1 - k);
+    double acc = 0.0;
+    for (int d = lo; d <= hi; ++d) acc = acc + in[t + (int64_t)d * pl];
+    feat[v.vox(i, j, k) * 8 + ch] = (bf16)(float)(acc / vol);
   }
 }
 
@@ -1100,20 +1177,51 @@ extern "C" int cnn_pack_weights(int cin, const float* w, void* wf, void* wd, voi
   return MS_OK;
 }
 
+namespace ms {
+namespace {
+constexpr int kFeatParts = 1024;
+}  // namespace
+}  // namespace ms
+
+extern "C" size_t cnn_features_workspace_bytes(const ms_grid* g) {
+  if (check_grid(g, "cnn_features_workspace_bytes")) return 0;
+  const size_t vol = (size_t)g->nx * g->ny * g->nz * sizeof(double);
+  return align_up(kFeatParts * sizeof(double), 256) + 2 * align_up(vol, 256);
+}
+
 extern "C" int cnn_features(const ms_grid* g, const double* u, const double* f, void* feat,
-                            double* scale, double* part, int nparts, void* stream) {
+                            double* scale, void* work, size_t work_bytes, void* stream) {
   clear_error();
   if (int rc = check_grid(g, "cnn_features")) return rc;
-  if (!u || !feat || !scale || !part || nparts < 1)
-    return set_error(MS_EINVAL, "cnn_features: bad arguments");
+  if (!u || !feat || !scale) return set_error(MS_EINVAL, "cnn_features: bad arguments");
+  const size_t need = cnn_features_workspace_bytes(g);
+  if (!work || work_bytes < need)
+    return set_error(MS_EWORKSPACE, "cnn_features: workspace needs %zu bytes", need);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(feat_max_kernel, dim3(nparts), dim3(256), 0, s, *g, u, f, part);
+  Workspace ws{static_cast<char*>(work), work_bytes};
+  double* part = ws.take<double>(kFeatParts);
+  const size_t nvox = (size_t)g->nx * g->ny * g->nz;
+  double* t1 = ws.take<double>(nvox);
+  double* t2 = ws.take<double>(nvox);
+  const Vol v{g->nx, g->ny, g->nz};
+  bf16* fb = static_cast<bf16*>(feat);
+  hipLaunchKernelGGL(feat_max_kernel, dim3(kFeatParts), dim3(256), 0, s, *g, u, f, part);
   MS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(feat_scale_kernel, dim3(1), dim3(64), 0, s, part, nparts, scale);
+  hipLaunchKernelGGL(feat_scale_kernel, dim3(1), dim3(256), 0, s, part, kFeatParts, scale);
   MS_LAUNCH_CHECK();
-  hipLaunchKernelGGL(feat_write_kernel, dim3(1024), dim3(256), 0, s, *g, u, f, scale,
-                     Vol{g->nx, g->ny, g->nz}, static_cast<bf16*>(feat));
+  hipLaunchKernelGGL(feat_write_kernel, dim3(1024), dim3(256), 0, s, *g, u, f, scale, v, fb);
   MS_LAUNCH_CHECK();
+  for (int b = 0; b < 5; ++b) {
+    const int h = kBoxHalf[b];
+    hipLaunchKernelGGL(box_x_kernel, dim3(2048), dim3(256), 0, s, *g, f, scale, h, t1);
+    MS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(box_y_kernel, dim3(2048), dim3(256), 0, s, g->nx, g->ny, g->nz, h, t1,
+                       t2);
+    MS_LAUNCH_CHECK();
+    hipLaunchKernelGGL(box_z_kernel, dim3(2048), dim3(256), 0, s, g->nx, g->ny, g->nz, h, t2, v,
+                       kBoxChannel[b], fb);
+    MS_LAUNCH_CHECK();
+  }
   return MS_OK;
 }
 

@@ -10,16 +10,47 @@ namespace {
 
 typedef __attribute__((ext_vector_type(2))) double d2;
 
-template <bool TWO>
+// Three access forms: one 16-byte element per lane per grid stride (0);
+// kU grid strides of loads issued before their stores (1); the same with
+// nontemporal loads (2). The benchmark reports the best.
+constexpr int kU = 4;
+
+template <bool TWO, int FORM>
 __global__ __launch_bounds__(256) void stream_kernel(const d2* __restrict__ a,
                                                      const d2* __restrict__ b,
                                                      d2* __restrict__ out, int64_t n2) {
-  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n2;
-       t += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (FORM > 0) {
+    for (; t + (kU - 1) * stride < n2; t += kU * stride) {
+      d2 v[kU], w[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        v[u] = FORM == 2 ? __builtin_nontemporal_load(a + t + u * stride) : a[t + u * stride];
+      if (TWO) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          w[u] = FORM == 2 ? __builtin_nontemporal_load(b + t + u * stride) : b[t + u * stride];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] += w[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) __builtin_nontemporal_store(v[u], out + t + u * stride);
+    }
+  }
+  for (; t < n2; t += stride) {
     d2 v = a[t];
     if (TWO) v += b[t];
     __builtin_nontemporal_store(v, out + t);
   }
+}
+
+template <int FORM>
+void launch_stream(const d2* a, const d2* b, d2* o, int64_t n2, int blocks, hipStream_t s) {
+  if (b)
+    hipLaunchKernelGGL((stream_kernel<true, FORM>), dim3(blocks), dim3(256), 0, s, a, b, o, n2);
+  else
+    hipLaunchKernelGGL((stream_kernel<false, FORM>), dim3(blocks), dim3(256), 0, s, a, b, o, n2);
 }
 
 }  // namespace
@@ -28,9 +59,9 @@ __global__ __launch_bounds__(256) void stream_kernel(const d2* __restrict__ a,
 using namespace ms;
 
 extern "C" int ms_stream_probe(const double* a, const double* b, double* out, int64_t n,
-                               int blocks, void* stream) {
+                               int blocks, int form, void* stream) {
   clear_error();
-  if (!a || !out || n < 0 || (n & 1) || blocks < 1)
+  if (!a || !out || n < 0 || (n & 1) || blocks < 1 || form < 0 || form > 2)
     return set_error(MS_EINVAL, "ms_stream_probe: bad arguments (n must be even)");
   if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
        reinterpret_cast<uintptr_t>(out)) & 15)
@@ -42,10 +73,9 @@ extern "C" int ms_stream_probe(const double* a, const double* b, double* out, in
   const auto* a2 = reinterpret_cast<const d2*>(a);
   const auto* b2 = reinterpret_cast<const d2*>(b);
   auto* o2 = reinterpret_cast<d2*>(out);
-  if (b)
-    hipLaunchKernelGGL(stream_kernel<true>, dim3(blocks), dim3(256), 0, s, a2, b2, o2, n / 2);
-  else
-    hipLaunchKernelGGL(stream_kernel<false>, dim3(blocks), dim3(256), 0, s, a2, b2, o2, n / 2);
+  if (form == 0) launch_stream<0>(a2, b2, o2, n / 2, blocks, s);
+  else if (form == 1) launch_stream<1>(a2, b2, o2, n / 2, blocks, s);
+  else launch_stream<2>(a2, b2, o2, n / 2, blocks, s);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

@@ -2,16 +2,18 @@
 //
 // warmstart_forward: features of the Poisson problem, the four 3x3x3
 // convolutions (BF16 MFMA, FP32 accumulation), the guess x = s * lambda *
-// u_hat, then the start selection: the residuals of the guess and of u0 (u
-// with its interior zeroed) are measured in one FP64 pass, and x's interior
-// is zeroed again when the selection rule prefers u0.
+// u_hat, a few damped Jacobi sweeps on it, then the start selection: the
+// residuals of the guess and of u0 (u with its interior zeroed) are
+// measured in one FP64 pass, and x's interior is zeroed again when the
+// selection rule prefers u0.
 //
 // warmstart_train_step: the same forward pass keeping every activation, the
 // target u_solved / (s * lambda), the MSE loss reduced on the device, the
 // weight and input gradients of every layer, and one Adam step.
 //
 // Both compose the kernels of cnn.hip (convolutions, features, loss, Adam)
-// with the few kernels below (halo clearing, start selection, loss sum).
+// with the few kernels below (halo clearing, guess smoothing, start
+// selection, loss sum).
 // Activations live in the caller's workspace; their one-voxel halo is the
 // convolution's zero padding, cleared on every call.
 #include "ms_internal.hpp"
@@ -28,6 +30,7 @@ constexpr int kWsCo = 32;
 constexpr int kParts = 1024;    // feature-scale and loss partials
 constexpr int kSelBlocks = 1024;
 constexpr int kSelQ = 6;        // sums of the start selection
+constexpr double kSmoothOmega = 2.0 / 3.0;  // damping of the guess smoother
 
 constexpr int64_t layer_wcount(int l) { return (int64_t)kWsTaps * kWsCo * kCinPad[l]; }
 constexpr int64_t layer_floats(int l) { return layer_wcount(l) + kWsCo; }
@@ -48,6 +51,9 @@ struct WsLayout {
   uint16_t* wf[kLayers];      // BF16 [27][32][cin]
   uint16_t* wd[kLayers];      // BF16 [27][cin][32]
   double* scale;              // 1
+  void* fwork;                // feature workspace
+  size_t fwork_bytes;
+  double* xs;                 // FP64 field (the smoother's second buffer)
   double* parts;              // kParts
   double* sel;                // kSelBlocks x kSelQ
   int* flag;                  // 1
@@ -83,6 +89,9 @@ WsLayout layout(const ms_grid& g, bool train, char* base) {
     L.wd[l] = reinterpret_cast<uint16_t*>(take((size_t)layer_wcount(l) * 2));
   }
   L.scale = reinterpret_cast<double*>(take(sizeof(double)));
+  L.fwork_bytes = cnn_features_workspace_bytes(&g);
+  L.fwork = take(L.fwork_bytes);
+  L.xs = reinterpret_cast<double*>(take((size_t)field_span(g) * sizeof(double)));
   L.parts = reinterpret_cast<double*>(take(kParts * sizeof(double)));
   L.sel = reinterpret_cast<double*>(take((size_t)kSelBlocks * kSelQ * sizeof(double)));
   L.flag = reinterpret_cast<int*>(take(sizeof(int)));
@@ -243,6 +252,32 @@ __global__ __launch_bounds__(256) void select_apply_kernel(ms_grid g, const int*
   }
 }
 
+__global__ __launch_bounds__(256) void copy_field_kernel(const double* src, double* dst,
+                                                         int64_t n) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+// One damped Jacobi sweep on the interior: out = x + omega * (J(x) - x),
+// J(x) = (S(x) - f) * fl(1/6) (S(x) * fl(1/6) without f), in this order.
+__global__ __launch_bounds__(256) void damped_sweep_kernel(ms_grid g, const double* x,
+                                                           const double* f, double omega,
+                                                           double* out) {
+  const int64_t n = (int64_t)g.nx * g.ny * g.nz;
+  const double c6 = 1.0 / 6.0;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny),
+              k = (int)(t / ((int64_t)g.nx * g.ny));
+    const int64_t p = (int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1);
+    const double s = ((((x[p + 1] + x[p - 1]) + x[p + g.sy]) + x[p - g.sy]) + x[p + g.sz]) +
+                     x[p - g.sz];
+    const double jac = f ? (s - f[p]) * c6 : s * c6;
+    out[p] = x[p] + omega * (jac - x[p]);
+  }
+}
+
 // loss = (sum of the partials, fixed order) / n.
 __global__ __launch_bounds__(256) void loss_sum_kernel(const double* parts, int nparts,
                                                        double n, double* loss) {
@@ -284,7 +319,7 @@ int forward_pass(const ms_grid& g, const double* u, const double* f, const float
   if (int rc = zero_halo(L.feat, g, 8, s)) return rc;
   for (int i = 0; i < 3; ++i)
     if (int rc = zero_halo(L.h[i], g, 32, s)) return rc;
-  if (int rc = cnn_features(&g, u, f, L.feat, L.scale, L.parts, kParts, s)) return rc;
+  if (int rc = cnn_features(&g, u, f, L.feat, L.scale, L.fwork, L.fwork_bytes, s)) return rc;
   const void* ins[kLayers] = {L.feat, L.h[0], L.h[1], L.h[2]};
   for (int l = 0; l < kLayers; ++l) {
     const bool last = l == kLayers - 1;
@@ -317,9 +352,9 @@ extern "C" size_t warmstart_workspace_bytes(const ms_grid* g, int train) {
 }
 
 extern "C" int warmstart_forward(const ms_grid* g, const double* u, const double* f,
-                                 const float* params, double out_scale, int rule, double* x,
-                                 void* work, size_t work_bytes, int* used, double* measures,
-                                 void* stream) {
+                                 const float* params, double out_scale, int smooth, int rule,
+                                 double* x, void* work, size_t work_bytes, int* used,
+                                 double* measures, void* stream) {
   clear_error();
   if (int rc = check_common(g, u, params, out_scale, work, work_bytes, false,
                             "warmstart_forward"))
@@ -327,6 +362,8 @@ extern "C" int warmstart_forward(const ms_grid* g, const double* u, const double
   if (!x) return set_error(MS_EINVAL, "warmstart_forward: x required");
   if (rule != MS_START_RESIDUAL && rule != MS_START_SLOW_MODES && rule != MS_START_FORCE)
     return set_error(MS_EINVAL, "warmstart_forward: unknown start rule %d", rule);
+  if (smooth < 0 || smooth > 64 || (smooth & 1))
+    return set_error(MS_EINVAL, "warmstart_forward: smooth must be even, 0 .. 64");
   const size_t bytes = (size_t)field_span(*g) * 8;
   if (f && overlaps(f, bytes, x, bytes))
     return set_error(MS_EINVAL, "warmstart_forward: x overlaps f");
@@ -336,6 +373,18 @@ extern "C" int warmstart_forward(const ms_grid* g, const double* u, const double
   const WsLayout L = layout(*g, false, static_cast<char*>(work));
   if (int rc = forward_pass(*g, u, f, params, L, s)) return rc;
   if (int rc = cnn_guess(g, L.out32, L.scale, out_scale, x, s)) return rc;
+  if (smooth > 0) {
+    const int64_t span = field_span(*g);
+    hipLaunchKernelGGL(copy_field_kernel, dim3(1024), dim3(256), 0, s, x, L.xs, span);
+    MS_LAUNCH_CHECK();
+    for (int m = 0; m < smooth; ++m) {
+      const double* src = (m & 1) ? L.xs : x;
+      double* dst = (m & 1) ? x : L.xs;
+      hipLaunchKernelGGL(damped_sweep_kernel, dim3(1024), dim3(256), 0, s, *g, src, f,
+                         kSmoothOmega, dst);
+      MS_LAUNCH_CHECK();
+    }
+  }
   hipLaunchKernelGGL(select_partials_kernel, dim3(kSelBlocks), dim3(256), 0, s, *g, x, u, f,
                      L.sel);
   MS_LAUNCH_CHECK();

@@ -2,13 +2,15 @@
 for the library's warm-start entry points (every arithmetic step runs in
 libmistencil).
 
-Network: 3x3x3 convolutions 2 -> 32 -> 32 -> 32 -> 1, ReLU after the first
-three, "same" zero padding; input [f/s, g/s] (right-hand side and boundary
-lift, scaled by s = max(max|f|, max|g|)); output u_hat with the guess
-u = s * out_scale * u_hat. 57,985 parameters (stored padded: 8 input
-channels in the first layer, 32 output channels in the last). Trained by
-MSE against Jacobi solutions with Adam (betas 0.9 / 0.999), FP32 master
-weights with BF16 copies.
+Network: 3x3x3 convolutions 8 -> 32 -> 32 -> 32 -> 1, ReLU after the first
+three, "same" zero padding; input: eight feature channels of the
+right-hand side f and the boundary lift g, scaled by s = max(max|f|,
+max|g|) (f/s, g/s, cube means of f/s at five scales, the slowest Jacobi
+mode as position); output u_hat with the guess u = s * out_scale * u_hat,
+then a few damped Jacobi sweeps. 63,169 parameters (stored padded to 32
+output channels in the last layer). Trained by MSE against Jacobi
+solutions with Adam (betas 0.9 / 0.999), FP32 master weights with BF16
+copies.
 
 The product path is two calls: ``guess`` (warmstart_forward: features,
 network, guess, start selection) and ``train_step`` (warmstart_train_step:
@@ -23,11 +25,11 @@ import ctypes
 import numpy as np
 import torch
 
-from . import (MS_START_FORCE, MS_START_RESIDUAL, MS_START_SLOW_MODES, _check, _field_check,
-               _ptr, _same_layout, _stream, grid_of, lib)
+from . import (MS_START_FORCE, MS_START_RESIDUAL, MS_START_SLOW_MODES, Grid, _check,
+               _field_check, _ptr, _same_layout, _stream, grid_of, lib)
 
 # (real input channels, padded input channels, real output channels, ReLU)
-LAYERS = [(2, 8, 32, True), (32, 32, 32, True), (32, 32, 32, True), (32, 32, 1, False)]
+LAYERS = [(8, 8, 32, True), (32, 32, 32, True), (32, 32, 32, True), (32, 32, 1, False)]
 TAPS = 27
 CO = 32
 RULES = {"residual": MS_START_RESIDUAL, "slow_modes": MS_START_SLOW_MODES,
@@ -150,9 +152,10 @@ class WarmStart:
             raise ValueError("field shape does not match the network's volume")
 
     # --------------------------------------------------- product entry points
-    def guess(self, u, f, x, rule="slow_modes", stream=None):
+    def guess(self, u, f, x, rule="slow_modes", smooth=4, stream=None):
         """warmstart_forward: the guess for (u's Dirichlet halo, f) in x's
-        interior, or x's interior zeroed when the start rule prefers u0.
+        interior after `smooth` damped Jacobi sweeps, or x's interior zeroed
+        when the start rule prefers u0.
         Returns device tensors (used [1] int32, measures [4] float64:
         ||r(x)||, ||r(u0)||, slow(r(x)), slow(r(u0)))."""
         self._check_volume(u)
@@ -164,8 +167,9 @@ class WarmStart:
         g = grid_of(u)
         ws = self._workspace(u, False)
         _check(lib.warmstart_forward(ctypes.byref(g), _ptr(u), _ptr(f), _ptr(self.pbuf),
-                                     self.out_scale, RULES[rule], _ptr(x), _ptr(ws), ws.numel(),
-                                     _ptr(self.used), _ptr(self.measures), _stream(stream)))
+                                     self.out_scale, int(smooth), RULES[rule], _ptr(x), _ptr(ws),
+                                     ws.numel(), _ptr(self.used), _ptr(self.measures),
+                                     _stream(stream)))
         return self.used, self.measures
 
     def train_step(self, u, f, u_solved, lr=1e-3, stream=None):
@@ -201,6 +205,9 @@ class WarmStart:
             self.scale = torch.zeros(1, dtype=torch.float64, **z)
             self.nparts = 1024
             self.parts = torch.zeros(self.nparts, dtype=torch.float64, **z)
+            gg = Grid(X, Y, Z, 0, X + 2, (X + 2) * (Y + 2))
+            self.fwork = torch.empty(lib.cnn_features_workspace_bytes(ctypes.byref(gg)),
+                                     dtype=torch.uint8, **z)
             self.wwork = torch.empty(lib.conv3d_bf16_wgrad_workspace_bytes(32),
                                      dtype=torch.uint8, **z)
             self.wf, self.wd, self.gw, self.gb = [], [], [], []
@@ -222,7 +229,8 @@ class WarmStart:
         self._bufs()
         g = grid_of(u)
         _check(lib.cnn_features(ctypes.byref(g), _ptr(u), _ptr(f), _ptr(self.feat),
-                                _ptr(self.scale), _ptr(self.parts), self.nparts, _stream()))
+                                _ptr(self.scale), _ptr(self.fwork), self.fwork.numel(),
+                                _stream()))
 
     def forward(self, u, f):
         """u_hat (FP32, field layout) for the problem (u: Dirichlet halo, f)."""

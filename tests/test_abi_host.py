@@ -256,27 +256,29 @@ def test_warmstart_entry_points_validate_before_touching_a_device():
     g = _grid(ms)
     assert ms.lib.warmstart_params_floats() == ms.lib.warmstart_layer_offset(4)
     assert ms.lib.warmstart_params_bytes() == 12 * ms.lib.warmstart_params_floats()
-    # 57,985 real parameters, stored padded: 27*32*(8+32+32+32) weights + 4*32 biases
+    # 63,169 real parameters, stored padded: 27*32*(8+32+32+32) weights + 4*32 biases
     assert ms.lib.warmstart_params_floats() == 27 * 32 * 104 + 128
     need = ms.lib.warmstart_workspace_bytes(ctypes.byref(g), 0)
     need_t = ms.lib.warmstart_workspace_bytes(ctypes.byref(g), 1)
     assert 0 < need < need_t
     P = [ctypes.c_void_p(0x1000000 * (n + 1)) for n in range(6)]
     fwd = ms.lib.warmstart_forward
-    ok = dict(out_scale=4.0, rule=ms.MS_START_SLOW_MODES, work_bytes=need)
+    ok = dict(out_scale=4.0, smooth=4, rule=ms.MS_START_SLOW_MODES, work_bytes=need)
 
     def call(**kw):
         a = dict(ok, **kw)
-        return fwd(ctypes.byref(g), P[0], P[1], P[2], a["out_scale"], a["rule"], P[3], P[4],
-                   a["work_bytes"], None, None, None)
+        return fwd(ctypes.byref(g), P[0], P[1], P[2], a["out_scale"], a["smooth"], a["rule"],
+                   P[3], P[4], a["work_bytes"], None, None, None)
 
     assert call(rule=7) == ms.MS_EINVAL
+    assert call(smooth=3) == ms.MS_EINVAL
+    assert call(smooth=66) == ms.MS_EINVAL
     assert call(out_scale=0.0) == ms.MS_EINVAL
     assert call(out_scale=float("inf")) == ms.MS_EINVAL
     assert call(work_bytes=need - 1) == ms.MS_EWORKSPACE
     # x overlapping f
-    assert fwd(ctypes.byref(g), P[0], P[1], P[2], 4.0, 0, ctypes.c_void_p(P[1].value + 8), P[4],
-               need, None, None, None) == ms.MS_EINVAL
+    assert fwd(ctypes.byref(g), P[0], P[1], P[2], 4.0, 0, 0, ctypes.c_void_p(P[1].value + 8),
+               P[4], need, None, None, None) == ms.MS_EINVAL
     step = ms.lib.warmstart_train_step
     assert step(ctypes.byref(g), P[0], P[1], P[2], P[3], 4.0, ctypes.c_float(0.0), 1, P[4], need_t,
                 None, None) == ms.MS_EINVAL

@@ -25,9 +25,12 @@ def _advect_gpu(u, v, w, t1, t2, tcx, tcy, pad=(0, 0)):
 @pytest.mark.parametrize("dims", [(1, 1, 1), (5, 4, 3), (64, 16, 8), (67, 19, 13), (130, 70, 9),
                                   (64, 8, 40)])
 @pytest.mark.parametrize("variant", ["staged", "direct", "staged-zc3", "staged-rows2",
-                                     "staged-rows2-zc3", "staged-guard", "staged-rows2-guard"])
+                                     "staged-rows2-zc3", "staged-guard", "staged-rows2-guard",
+                                     "staged-w4", "staged-w4-zc3", "staged-w4-guard"])
 def test_advection_bit_exact(dims, variant, monkeypatch):
     note(f"case: advect {dims} {variant}")
+    if "w4" in variant:
+        monkeypatch.setenv("MS_ADVECT_WAVES", "4")
     if variant.endswith("guard"):
         monkeypatch.setenv("MS_ADVECT_GUARD", "1")
     if variant == "direct":

@@ -49,7 +49,7 @@ def test_forward_guess_matches_the_oracle_network():
     net = wsm.WarmStart(NX, NY, NZ, seed=5, out_scale=2.5)
     du, df = ms.field_from(u), ms.field_from(f)
     x = ms.field_from(u)
-    used, meas = net.guess(du, df, x, rule="force")
+    used, meas = net.guess(du, df, x, rule="force", smooth=0)
     torch.cuda.synchronize()
     assert used.item() == 1
     feats, s = cnn.features(u, f)
@@ -60,6 +60,21 @@ def test_forward_guess_matches_the_oracle_network():
     mask = np.ones(got.shape, bool)
     mask[1:-1, 1:-1, 1:-1] = False
     assert np.array_equal(got[mask], u[mask])
+
+
+@pytest.mark.parametrize("smooth", [2, 4, 8])
+def test_guess_smoothing_bit_exact(smooth):
+    """The damped sweeps on the guess equal the oracle's smoother applied to
+    the device's unsmoothed guess, bit for bit (FP64, same order)."""
+    u, f = _problem(5)
+    net = wsm.WarmStart(NX, NY, NZ, seed=6, out_scale=2.0)
+    du, df = ms.field_from(u), ms.field_from(f)
+    x0, xs = ms.field_from(u), ms.field_from(u)
+    net.guess(du, df, x0, rule="force", smooth=0)
+    net.guess(du, df, xs, rule="force", smooth=smooth)
+    torch.cuda.synchronize()
+    want = cnn.smooth_guess(host(x0), f, smooth)
+    assert np.array_equal(host(xs), want)
 
 
 @pytest.mark.parametrize("beta_at", [0.0, 0.5, 3.0, None])
@@ -78,13 +93,14 @@ def test_start_selection_matches_the_oracle(beta_at):
         net.set_params(params)
     du, df = ms.field_from(u), ms.field_from(f)
     xg = ms.field_from(u)
-    net.guess(du, df, xg, rule="force")
+    smooth = 0 if beta_at is not None else 4  # constant guesses stay constant
+    net.guess(du, df, xg, rule="force", smooth=smooth)
     guess = host(xg)[1:-1, 1:-1, 1:-1]
     seen = set()
     for rule in RULES:
         note(f"case: start selection {rule}, beta {beta_at}")
         x = ms.field_from(u)
-        used, meas = net.guess(du, df, x, rule=rule)
+        used, meas = net.guess(du, df, x, rule=rule, smooth=smooth)
         torch.cuda.synchronize()
         want_use, want_meas = cnn.start_choice(u, f, guess, rule)
         assert bool(used.item()) == want_use, (rule, host(meas), want_meas)
@@ -106,8 +122,8 @@ def test_guess_written_in_place_of_u():
     net = wsm.WarmStart(NX, NY, NZ, seed=9)
     du, df = ms.field_from(u), ms.field_from(f)
     x = ms.field_from(u)
-    net.guess(du, df, x, rule="force")
-    net.guess(du, df, du, rule="force")  # x = u
+    net.guess(du, df, x, rule="force", smooth=4)
+    net.guess(du, df, du, rule="force", smooth=4)  # x = u
     torch.cuda.synchronize()
     assert np.array_equal(host(du), host(x))
 
