@@ -900,6 +900,190 @@ __global__ __launch_bounds__(kTwThreads) __attribute__((amdgpu_waves_per_eu(4)))
   }
 }
 
+// ------------------------- two-stage pass, one column per lane, no LDS
+
+// Two Jacobi sweeps per pass with every value in registers and no barrier
+// inside the march: each wave works alone. A wave owns 64 columns (one per
+// lane; its output tile is the middle 60) and kTrRows output rows, and
+// keeps the rows j0-2 .. j0+kTrRows+1 of u_k of its column, three z levels
+// deep, in registers. x neighbours come from the adjacent lanes (DPP), y
+// neighbours from the lane's own rows, z neighbours from its level queue.
+// Stage A computes h = u_{k+1} on rows j0-1 .. j0+kTrRows (lanes 1..62) at
+// level z; stage B computes u_{k+2} on the output rows (lanes 2..61) at
+// level z-1 from h at z-2, z-1, z. Blocks hold four waves stacked in y
+// (they share the L2 lines of their halo rows). The per-cell arithmetic is
+// the single sweep's, so the results are bit-identical to it; ring cells
+// that are Dirichlet halo keep their value.
+constexpr int kTrRows = 4;
+constexpr int kTrWaves = 4;
+constexpr int kTrTileX = 60;
+constexpr int kTrTileY = kTrRows * kTrWaves;
+
+template <typename T, bool HAS_F>
+__global__ __launch_bounds__(64 * kTrWaves) void sweep_tbr_kernel(SweepK<T> a) {
+  constexpr int R = kTrRows;
+  __shared__ double red[kTrWaves];
+  __shared__ int s_done;
+
+  const int64_t L = (a.ctl ? a.ctl->base : 0) + a.k_off;
+  const int64_t k0 = 2 * L;  // iterate read by this launch
+  if (blockIdx.x == 0 && L >= 1 && (a.hist || a.ctl)) {
+#pragma unroll
+    for (int d = 2; d >= 1; --d) {
+      if (!a.ctl || a.ctl->done == RUNNING) {
+        const double t = sum_partials(a.partials + ((k0 - d) & 3) * (int64_t)kMaxBlocks,
+                                      a.nblocks, red);
+        if (threadIdx.x == 0) judge(a.ctl, a.hist, k0 - d, sqrt(t));
+        __syncthreads();
+      }
+    }
+  }
+  if (a.ctl) {
+    if (threadIdx.x == 0) s_done = a.ctl->done;
+    __syncthreads();
+    if (s_done != RUNNING) return;
+  }
+
+  const int tile = xcd_tile(blockIdx.x, a.nblocks);
+  const int txi = tile % a.tiles_x;
+  const int rest = tile / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int tzi = rest / a.tiles_y;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const int z0 = tzi * a.zc;
+  const int z1 = min(z0 + a.zc, nz);
+  const int64_t sy = a.sy, sz = a.sz;
+  const T* __restrict__ src = a.buf[L % a.nbuf];
+  T* __restrict__ dst = a.buf[(L + 1) % a.nbuf];
+  const T* __restrict__ f = a.f;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = txi * kTrTileX - 2 + lane;  // this lane's column
+  const int j0 = tyi * kTrTileY + w * R;    // first output row of this wave
+  const bool colA = lane >= 1 && lane <= 62, colB = lane >= 2 && lane <= 61;
+  const bool xin = i >= 0 && i < nx;
+  const int64_t col = (int64_t)(min(max(i, -1), nx) + 1);
+  // row offsets (clamped into the field) of rows j0-2 .. j0+R+1
+  int64_t roff[R + 4];
+  bool yin[R + 4];
+#pragma unroll
+  for (int q = 0; q < R + 4; ++q) {
+    const int j = j0 - 2 + q;
+    roff[q] = (int64_t)(min(max(j, -1), ny) + 1) * sy + col;
+    yin[q] = j >= 0 && j < ny;
+  }
+  auto plane = [&](int z) { return (int64_t)(min(max(z, -1), nz) + 1) * sz; };
+  // u_k rows j0-2 .. j0+R+1 (q = 0 .. R+3) at level z
+  auto load_u = [&](T (&r)[R + 4], int z) {
+    const int64_t p = plane(z);
+#pragma unroll
+    for (int q = 0; q < R + 4; ++q) r[q] = src[p + roff[q]];
+  };
+  // f rows j0-1 .. j0+R (q = 1 .. R+2) at level z
+  auto load_f = [&](T (&r)[R + 2], int z) {
+    const int64_t p = plane(z);
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) r[q] = HAS_F ? f[p + roff[q + 1]] : T(0);
+  };
+
+  T um[R + 2];        // u_k at z-1, rows j0-1 .. j0+R
+  T uc[R + 4];        // u_k at z, rows j0-2 .. j0+R+1
+  T up[R + 4];        // u_k at z+1
+  T fa[R + 2];        // f at z, rows j0-1 .. j0+R (stage A)
+  T fb[R];            // f at z-1, rows j0 .. j0+R-1 (stage B)
+  T hm2[R], hm1[R + 2];  // h at z-2 (output rows) and z-1 (rows j0-1 .. j0+R)
+  {
+    T t[R + 4];
+    load_u(t, z0 - 2);
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) um[q] = t[q + 1];
+  }
+  load_u(uc, z0 - 1);
+  load_u(up, z0);
+  load_f(fa, z0 - 1);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    fb[q] = T(0);
+    hm2[q] = T(0);
+  }
+#pragma unroll
+  for (int q = 0; q < R + 2; ++q) hm1[q] = T(0);
+
+  double acc_a = 0.0, acc_b = 0.0;
+  const T c6 = C6<T>::v();
+  const bool wave_live = j0 < ny;
+  for (int z = z0 - 1; z <= z1 && wave_live; ++z) {
+    // next level's loads first: u_k at z+2, f at z+1
+    T un[R + 4], fn[R + 2];
+    const bool more = z + 1 <= z1;
+    if (more) {
+      load_u(un, z + 2);
+      load_f(fn, z + 1);
+    }
+    // stage A at level z: h on rows j0-1 .. j0+R
+    const bool zA = z >= 0 && z < nz, zres = z >= z0 && z < z1;
+    T hn[R + 2];
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {
+      const T c = uc[q + 1];
+      const T xp = lane_from_right(c, c), xm = lane_from_left(c, c);
+      const T yp = uc[q + 2], ym = uc[q];
+      const T zp = up[q + 1], zm = um[q];
+      const T sum = ((((xp + xm) + yp) + ym) + zp) + zm;
+      hn[q] = (colA && xin && yin[q + 1] && zA) ? (HAS_F ? (sum - fa[q]) * c6 : sum * c6) : c;
+      if (q >= 1 && q <= R && colB && xin && yin[q + 1] && zres) {
+        const double r = cell_residual(xp, xm, yp, ym, zp, zm, c, fa[q], HAS_F);
+        acc_a += r * r;
+      }
+    }
+    // stage B at level z-1: output rows j0 .. j0+R-1
+    const int zb = z - 1;
+    if (zb >= z0 && zb < z1) {
+      const int64_t pb = (int64_t)(zb + 1) * sz;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const T c = hm1[q + 1];
+        const T xp = lane_from_right(c, c), xm = lane_from_left(c, c);
+        const T yp = hm1[q + 2], ym = hm1[q];
+        const T zp = hn[q + 1], zm = hm2[q];
+        const T sum = ((((xp + xm) + yp) + ym) + zp) + zm;
+        const T v = HAS_F ? (sum - fb[q]) * c6 : sum * c6;
+        if (colB && xin && yin[q + 2]) {
+          __builtin_nontemporal_store(v, dst + pb + roff[q + 2]);
+          const double r = cell_residual(xp, xm, yp, ym, zp, zm, c, fb[q], HAS_F);
+          acc_b += r * r;
+        }
+      }
+    }
+    // shift the queues
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      hm2[q] = hm1[q + 1];
+      fb[q] = fa[q + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) {
+      hm1[q] = hn[q];
+      um[q] = uc[q + 1];
+    }
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < R + 4; ++q) {
+        uc[q] = up[q];
+        up[q] = un[q];
+      }
+#pragma unroll
+      for (int q = 0; q < R + 2; ++q) fa[q] = fn[q];
+    }
+  }
+
+  const double ta = block_sum(acc_a, red);
+  const double tb = block_sum(acc_b, red);
+  if (threadIdx.x == 0) {
+    a.partials[(int64_t)(k0 & 3) * kMaxBlocks + blockIdx.x] = ta;
+    a.partials[(int64_t)((k0 + 1) & 3) * kMaxBlocks + blockIdx.x] = tb;
+  }
+}
+
 template <typename T, bool HAS_F, bool WRITE, bool ZERO_INT>
 int launch_lds(const SweepK<T>& a, const SweepGeom& geo, hipStream_t s) {
   const dim3 grid(geo.nblocks), block(kThreads);
@@ -1011,19 +1195,24 @@ int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 // tiles against 60 x 20); FP32 16-20% faster with columns at both sizes.
 // Default: LDS tiles for FP64, columns for FP32; MS_TB_VARIANT=0 or 2
 // forces one.
-constexpr int kTbLds = 0, kTbColumns = 2;
+constexpr int kTbLds = 0, kTbColumns = 2, kTbRegisters = 3;
 
-SweepGeom tb2_geom(const ms_grid& g, int dtype) {
+SweepGeom tb2_geom(const ms_grid& g, int dtype, bool rb) {
   SweepGeom s{};
   const char* ev_var = getenv("MS_TB_VARIANT");
-  s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : kTbColumns)
+  s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : atoi(ev_var) == 3 ? kTbRegisters : kTbColumns)
                      : (dtype == MS_F64 ? kTbLds : kTbColumns);
+  if (rb && s.variant == kTbRegisters) s.variant = kTbLds;  // Jacobi only
   s.vec = 1;
   s.wx = 1;
   s.rows = 2;
-  const bool cols = s.variant == kTbColumns;
-  s.tiles_x = cols ? (g.nx + kTwTileX - 1) / kTwTileX : (g.nx + kTbX - 1) / kTbX;
-  s.tiles_y = cols ? (g.ny + kTwTileY - 1) / kTwTileY : (g.ny + kTbY - 1) / kTbY;
+  const bool cols = s.variant == kTbColumns, regs = s.variant == kTbRegisters;
+  s.tiles_x = regs   ? (g.nx + kTrTileX - 1) / kTrTileX
+              : cols ? (g.nx + kTwTileX - 1) / kTwTileX
+                     : (g.nx + kTbX - 1) / kTbX;
+  s.tiles_y = regs   ? (g.ny + kTrTileY - 1) / kTrTileY
+              : cols ? (g.ny + kTwTileY - 1) / kTwTileY
+                     : (g.ny + kTbY - 1) / kTbY;
   const int64_t tiles2d = (int64_t)s.tiles_x * s.tiles_y;
   // Block targets measured at 512^3. LDS tiles: 2048 (FP64) / 1024 (FP32)
   // blocks of 256 threads, three or four resident per CU. Columns: 4096
@@ -1047,7 +1236,7 @@ SweepGeom tb2_geom(const ms_grid& g, int dtype) {
   return s;
 }
 
-int tb2_blocks(const ms_grid& g, int dtype) { return tb2_geom(g, dtype).nblocks; }
+int tb2_blocks(const ms_grid& g, int dtype, bool rb) { return tb2_geom(g, dtype, rb).nblocks; }
 
 namespace {
 
@@ -1060,7 +1249,10 @@ void launch_tb2_typed(const ms_grid& g, const SweepGeom& geo, void* const bufs[3
   a.f = static_cast<const T*>(f);
   a.partials = partials; a.hist = hist; a.ctl = ctl; a.k_off = k_off; a.nbuf = nbuf;
   const dim3 grid(geo.nblocks);
-  if (geo.variant == kTbColumns) {
+  if (geo.variant == kTbRegisters && !RB) {
+    if (f) hipLaunchKernelGGL((sweep_tbr_kernel<T, true>), grid, dim3(64 * kTrWaves), 0, s, a);
+    else hipLaunchKernelGGL((sweep_tbr_kernel<T, false>), grid, dim3(64 * kTrWaves), 0, s, a);
+  } else if (geo.variant == kTbColumns) {
     if (f) hipLaunchKernelGGL((sweep_tbw_kernel<T, true, RB>), grid, dim3(kTwThreads), 0, s, a);
     else hipLaunchKernelGGL((sweep_tbw_kernel<T, false, RB>), grid, dim3(kTwThreads), 0, s, a);
   } else {
@@ -1072,7 +1264,7 @@ void launch_tb2_typed(const ms_grid& g, const SweepGeom& geo, void* const bufs[3
 template <bool RB>
 int launch_tb2_any(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
                    double* partials, double* hist, Ctl* ctl, int64_t k_off, hipStream_t s) {
-  const SweepGeom geo = tb2_geom(g, dtype);
+  const SweepGeom geo = tb2_geom(g, dtype, RB);
   if (geo.nblocks > kMaxBlocks || geo.nblocks < 1)
     return set_error(MS_EUNSUPPORTED, "two-stage sweep geometry with %d blocks", geo.nblocks);
   if (dtype == MS_F64)

@@ -213,7 +213,7 @@ int launch_sweep_tb2(const ms_grid& g, int dtype, void* const bufs[3], int nbuf,
 int launch_rbgs(const ms_grid& g, int dtype, void* const bufs[3], int nbuf, const void* f,
                 double* partials, double* hist, Ctl* ctl, int64_t k_off, hipStream_t s);
 // Blocks of the two-sweep kernel (for finalising its last partials).
-int tb2_blocks(const ms_grid& g, int dtype);
+int tb2_blocks(const ms_grid& g, int dtype, bool rb = false);
 
 // Standalone residual: per-block partials of sum r^2 into partials[slot];
 // zero_interior evaluates u with its interior replaced by 0. It launches

@@ -489,8 +489,8 @@ extern "C" int rbgs_sweeps(const ms_grid* g, int dtype, void* u, void* u_tmp, co
     if (int rc = launch_rbgs(*g, dtype, bufs, 2, f, partials, res_dev, nullptr, k, s)) return rc;
   if (res_dev) {
     if (n >= 1)
-      if (int rc = launch_finalize(partials, (int)((n - 1) & 3), tb2_blocks(*g, dtype), nullptr,
-                                   nullptr, res_dev, n - 1, s))
+      if (int rc = launch_finalize(partials, (int)((n - 1) & 3), tb2_blocks(*g, dtype, true),
+                                   nullptr, nullptr, res_dev, n - 1, s))
         return rc;
     void* last = (n & 1) ? u_tmp : u;
     const int slot = (int)(n & 3);  // partials[(n - 1) & 3] is final by now

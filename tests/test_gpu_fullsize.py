@@ -67,14 +67,14 @@ def test_benchmark_sweep_kernel_bit_exact_at_512cubed(problem512):
         del du, dt, out
 
 
-@pytest.mark.parametrize("variant", ["default", "columns", "lds"])
+@pytest.mark.parametrize("variant", ["default", "columns", "lds", "registers"])
 def test_two_sweep_pass_bit_exact_against_the_oracle_at_512cubed(problem512, variant,
                                                                  monkeypatch):
     """Two sweeps per pass over memory (the benchmark's temporal_block_2
     line), four sweeps in two passes and three in a pass plus a single
     sweep, compared with the oracle's plain sweeps over the whole grid."""
     if variant != "default":
-        monkeypatch.setenv("MS_TB_VARIANT", {"columns": "2", "lds": "0"}[variant])
+        monkeypatch.setenv("MS_TB_VARIANT", {"columns": "2", "lds": "0", "registers": "3"}[variant])
     u, f, traj, hist = problem512
     _, _, df = _fields(u, f)
     for n in (4, 3):

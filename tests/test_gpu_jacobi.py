@@ -172,7 +172,7 @@ def test_every_tile_geometry_is_bit_exact(geom, dtype, monkeypatch):
         np.testing.assert_allclose(host(res)[:3], hist, rtol=NORM_RTOL)
 
 
-TB_VARIANTS = {"columns": "2", "lds": "0"}
+TB_VARIANTS = {"columns": "2", "lds": "0", "registers": "3"}
 
 
 @pytest.mark.parametrize("variant", list(TB_VARIANTS))

@@ -39,7 +39,7 @@ def _run(u, f, n, dtype=np.float64, pad=(0, 0)):
     return host(out), host(res)
 
 
-TB_VARIANTS = {"columns": "2", "lds": "0"}
+TB_VARIANTS = {"columns": "2", "lds": "0", "registers": "3"}
 
 
 @pytest.mark.parametrize("variant", list(TB_VARIANTS))
