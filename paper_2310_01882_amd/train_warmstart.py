@@ -11,11 +11,13 @@ a 1e-10 relative residual by the library's solver (FP32-storage Jacobi
 sweeps inside FP64 refinement, instances on concurrent streams); the
 network trains on them with warmstart_train_step (one instance per Adam
 step). Held-out instances use seeds 20000 + i; each is solved to a 1e-8
-relative residual four ways on the same GPU:
+relative residual five ways on the same GPU:
   A plain FP64 Jacobi from the zero interior,
   B FP32-refined Jacobi from the zero interior,
-  C warmstart_forward with the slowest-mode start rule, then B's solver,
-  D warmstart_forward forcing the guess, then B's solver.
+  C warmstart_forward (four damped sweeps on the guess, slowest-mode start
+    rule), then B's solver,
+  D the same forcing the guess,
+  E the guess forced without the damped sweeps (what they contribute).
 The report gives sweeps and seconds of each, the guess's relative error
 against A's answer, its four start measures, and which start the residual
 rule would have taken (the rules differ only in the decision: the solve
@@ -113,7 +115,7 @@ def train(args):
     print(json.dumps({k: v for k, v in report.items() if k != "epoch_losses"}), flush=True)
 
 
-NAMES = ("A_fp64", "B_fp32_refined", "C_cnn_slow_modes", "D_cnn_forced")
+NAMES = ("A_fp64", "B_fp32_refined", "C_cnn_slow_modes", "D_cnn_forced", "E_cnn_unsmoothed")
 
 
 def evaluate(args):
@@ -137,8 +139,9 @@ def evaluate(args):
             x = ms.field_from(u)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            if name in ("C_cnn_slow_modes", "D_cnn_forced"):
-                used, meas = net.guess(u0, fd, x, rule="slow_modes" if name[0] == "C" else "force")
+            if name[0] in "CDE":
+                used, meas = net.guess(u0, fd, x, rule="slow_modes" if name[0] == "C" else "force",
+                                       smooth=0 if name[0] == "E" else 4)
             prec = ms.MS_SOLVE_F64 if name == "A_fp64" else F32R
             info = ms.jacobi_solve(x, fd, precision=prec, rel_tol=tol)
             torch.cuda.synchronize()
@@ -146,7 +149,7 @@ def evaluate(args):
                          "rel_final": info.rel_final, "outer": info.outer_iters}
             if name == "A_fp64":
                 xa = x
-            if name[0] in "CD":
+            if name[0] in "CDE":
                 m = [float(v) for v in meas.cpu()]
                 row[name]["guess_used"] = bool(used.item())
                 row[name]["measures"] = m

@@ -1,8 +1,11 @@
-"""Why a four-layer 3x3x3 network cannot make a good initial guess at 128^3.
+"""Why a four-layer 3x3x3 network fed only the right-hand side (and the
+boundary lift) cannot make a good initial guess at 128^3 -- the reason the
+network's input also carries cube means of the right-hand side at larger
+scales and the cell's position.
 
-The network's output at a cell depends only on the 9x9x9 patch of its input
-around that cell. Where that patch of the right-hand side is (numerically)
-zero -- far from every source -- any such network outputs one and the same
+Such a network's output at a cell depends only on the 9x9x9 patch of its
+input around that cell. Where that patch of the right-hand side is
+(numerically) zero -- far from every source -- it outputs one and the same
 value, while the exact solution there varies (the potential of a source
 decays like 1/r). The best constant over those cells therefore bounds the
 error of every such network from below. The exact discrete solution comes
