@@ -611,8 +611,9 @@ int warmstart_train_step(const ms_grid* g, const double* u, const double* f,
  * out[i] = a[i] (b NULL: one read, one write) over n doubles (n even; all
  * arrays 16-byte aligned device memory; out must not overlap a or b), in
  * 16-byte lanes with nontemporal stores, on `blocks` blocks of 256 threads,
- * grid-stride. form 0: one element per lane per stride; 1: four strides of
- * loads issued before their stores; 2: as 1 with nontemporal loads.
+ * form 0: grid-stride, one element per lane per stride; 1: four strides of
+ * loads issued before their stores; 2: as 1 with nontemporal loads; 3: each
+ * block streams its own contiguous share, two 4 KiB steps in flight.
  * Measures the achievable HBM bandwidth of the stencils' access patterns.
  * Async. */
 int ms_stream_probe(const double* a, const double* b, double* out, int64_t n,

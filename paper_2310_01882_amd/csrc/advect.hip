@@ -67,7 +67,13 @@ __global__ __launch_bounds__(64 * W) void advect_staged_kernel(AdvK a) {
   constexpr int kAdvLY = kAdvTY + 2;
   constexpr int kAdvRing = 2 * kAdvLX + 2 * kAdvTY;  // ring cells per field
   static_assert(kAdvRing <= 64 * W, "one ring cell per thread");
-  __shared__ double L[4][3][kAdvLY][kAdvLX];
+  // Up to eight waves the staging buffers are static LDS (at most 63 KB);
+  // sixteen-wave blocks take theirs (114 KB) from dynamic LDS.
+  constexpr int kStatic = W <= 8 ? 4 * 3 * kAdvLY * kAdvLX : 1;
+  __shared__ double l_static[kStatic];
+  extern __shared__ double l_dynamic[];
+  typedef double Plane[3][kAdvLY][kAdvLX];
+  Plane* L = reinterpret_cast<Plane*>(W <= 8 ? l_static : l_dynamic);
 
   const int tile = xcd_tile(blockIdx.x, a.nblocks);
   const int txi = tile % a.tiles_x;
@@ -302,8 +308,10 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   // MS_ADVECT_ROWS (1 or 2 rows per thread, four-wave blocks) and
   // MS_ADVECT_BLOCKS (target grid) select the alternatives.
   const int rows = env_int("MS_ADVECT_ROWS") == 2 ? 2 : 1;
-  const int waves = (env_int("MS_ADVECT_WAVES") == 4 || rows == 2) ? 4 : 8;
+  const int ew = env_int("MS_ADVECT_WAVES");
+  const int waves = (ew == 4 || rows == 2) ? 4 : ew == 16 ? 16 : 8;
   const int64_t want = env_int("MS_ADVECT_BLOCKS") > 0 ? env_int("MS_ADVECT_BLOCKS")
+                       : waves == 16                   ? 256
                        : waves == 8                    ? 512
                                                        : 1024;
   a.tiles_x = (g->nx + kAdvTX - 1) / kAdvTX;
@@ -323,13 +331,19 @@ extern "C" int advect_source(const ms_grid* g, const double* u, const double* v,
   // MS_ADVECT_GUARD=1: the predicated centre loads (cross-check)
   const bool guard = env_int("MS_ADVECT_GUARD") == 1;
   void (*kern)(AdvK);
-  if (waves == 8)
+  size_t dyn = 0;
+  if (waves == 16) {
+    kern = guard ? advect_staged_kernel<1, true, 16> : advect_staged_kernel<1, false, 16>;
+    dyn = sizeof(double) * 4 * 3 * (16 + 2) * kAdvLX;
+    MS_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
+  } else if (waves == 8)
     kern = guard ? advect_staged_kernel<1, true, 8> : advect_staged_kernel<1, false, 8>;
   else if (rows == 1)
     kern = guard ? advect_staged_kernel<1, true, 4> : advect_staged_kernel<1, false, 4>;
   else
     kern = guard ? advect_staged_kernel<2, true, 4> : advect_staged_kernel<2, false, 4>;
-  hipLaunchKernelGGL(kern, dim3(a.nblocks), dim3(64 * waves), 0, s, a);
+  hipLaunchKernelGGL(kern, dim3(a.nblocks), dim3(64 * waves), dyn, s, a);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

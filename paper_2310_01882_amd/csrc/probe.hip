@@ -10,9 +10,10 @@ namespace {
 
 typedef __attribute__((ext_vector_type(2))) double d2;
 
-// Three access forms: one 16-byte element per lane per grid stride (0);
-// kU grid strides of loads issued before their stores (1); the same with
-// nontemporal loads (2). The benchmark reports the best.
+// Access forms: one 16-byte element per lane per grid stride (0); kU grid
+// strides of loads issued before their stores (1); the same with
+// nontemporal loads (2); block-contiguous chunks (3, below). The benchmark
+// reports the best.
 constexpr int kU = 4;
 
 template <bool TWO, int FORM>
@@ -45,12 +46,44 @@ __global__ __launch_bounds__(256) void stream_kernel(const d2* __restrict__ a,
   }
 }
 
+// Form 3: each block streams through its own contiguous share of the
+// arrays, 4 KiB (256 lanes x 16 bytes) per step, two steps of loads in
+// flight, as a z-marching stencil block walks its planes.
+template <bool TWO>
+__global__ __launch_bounds__(256) void stream_chunk_kernel(const d2* __restrict__ a,
+                                                           const d2* __restrict__ b,
+                                                           d2* __restrict__ out, int64_t n2) {
+  const int64_t per = (n2 + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per, hi = min(lo + per, n2);
+  int64_t t = lo + threadIdx.x;
+  for (; t + blockDim.x < hi; t += 2 * (int64_t)blockDim.x) {
+    d2 v0 = a[t], v1 = a[t + blockDim.x];
+    if (TWO) {
+      v0 += b[t];
+      v1 += b[t + blockDim.x];
+    }
+    __builtin_nontemporal_store(v0, out + t);
+    __builtin_nontemporal_store(v1, out + t + blockDim.x);
+  }
+  for (; t < hi; t += blockDim.x) {
+    d2 v = a[t];
+    if (TWO) v += b[t];
+    __builtin_nontemporal_store(v, out + t);
+  }
+}
+
 template <int FORM>
 void launch_stream(const d2* a, const d2* b, d2* o, int64_t n2, int blocks, hipStream_t s) {
-  if (b)
+  if (FORM == 3) {
+    if (b)
+      hipLaunchKernelGGL(stream_chunk_kernel<true>, dim3(blocks), dim3(256), 0, s, a, b, o, n2);
+    else
+      hipLaunchKernelGGL(stream_chunk_kernel<false>, dim3(blocks), dim3(256), 0, s, a, b, o, n2);
+  } else if (b) {
     hipLaunchKernelGGL((stream_kernel<true, FORM>), dim3(blocks), dim3(256), 0, s, a, b, o, n2);
-  else
+  } else {
     hipLaunchKernelGGL((stream_kernel<false, FORM>), dim3(blocks), dim3(256), 0, s, a, b, o, n2);
+  }
 }
 
 }  // namespace
@@ -61,7 +94,7 @@ using namespace ms;
 extern "C" int ms_stream_probe(const double* a, const double* b, double* out, int64_t n,
                                int blocks, int form, void* stream) {
   clear_error();
-  if (!a || !out || n < 0 || (n & 1) || blocks < 1 || form < 0 || form > 2)
+  if (!a || !out || n < 0 || (n & 1) || blocks < 1 || form < 0 || form > 3)
     return set_error(MS_EINVAL, "ms_stream_probe: bad arguments (n must be even)");
   if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b) |
        reinterpret_cast<uintptr_t>(out)) & 15)
@@ -75,7 +108,8 @@ extern "C" int ms_stream_probe(const double* a, const double* b, double* out, in
   auto* o2 = reinterpret_cast<d2*>(out);
   if (form == 0) launch_stream<0>(a2, b2, o2, n / 2, blocks, s);
   else if (form == 1) launch_stream<1>(a2, b2, o2, n / 2, blocks, s);
-  else launch_stream<2>(a2, b2, o2, n / 2, blocks, s);
+  else if (form == 2) launch_stream<2>(a2, b2, o2, n / 2, blocks, s);
+  else launch_stream<3>(a2, b2, o2, n / 2, blocks, s);
   MS_LAUNCH_CHECK();
   return MS_OK;
 }

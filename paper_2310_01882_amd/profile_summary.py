@@ -4,6 +4,8 @@
     python -m paper_2310_01882_amd.profile_summary traffic KEY KERNEL_SUBSTR \
         FETCH_CSV WRITE_CSV COPY_FETCH_CSV COPY_WRITE_CSV COPY_MIB OUT.md "COMMANDS"
 
+    python -m paper_2310_01882_amd.profile_summary counters OUT.md "TITLE" "COMMANDS" CSV...
+
 `stats` writes the per-kernel table (calls, average and total duration) of a
 --kernel-trace --stats run. `traffic` reads FETCH_SIZE and WRITE_SIZE (KiB per
 dispatch) for the kernels whose name contains KERNEL_SUBSTR, scales each by
@@ -11,6 +13,10 @@ the factor that makes the same counter read the known size of a plain
 device copy of COPY_MIB MiB, and records bytes per launch in
 profiles/traffic.json under KEY, together with a hash of the kernel sources
 the figure was taken on (the benchmark reports null once they change).
+`counters` tabulates every counter of one or more --pmc runs per kernel
+(average per dispatch) and, where SQ_VALU_MFMA_BUSY_CYCLES and
+SQ_BUSY_CYCLES are both present, the share of the MFMA pipes kept busy
+(MFMA busy cycles over 1024 SIMDs x SQ_BUSY_CYCLES / 32 shader engines).
 """
 
 from __future__ import annotations
@@ -27,9 +33,9 @@ ROOT = os.path.dirname(HERE)
 PROFILES = os.path.join(ROOT, "profiles")
 
 SOURCES = {
-    "jacobi7": ["jacobi.hip", "ms_internal.hpp", "common.hip"],
+    "jacobi7": ["jacobi.hip", "ms_internal.hpp", "common.hip", "march.hpp"],
     "advect": ["advect.hip"],
-    "batched": ["batched.hip", "ms_internal.hpp"],
+    "batched": ["batched.hip", "ms_internal.hpp", "march.hpp"],
     "conv": ["cnn.hip"],
     "jit": ["jit.hip", "programs.py"],
 }
@@ -121,10 +127,42 @@ def traffic(key, substr, fetch_csv, write_csv, cfetch_csv, cwrite_csv, copy_mib,
     print("\n".join(lines))
 
 
+def counters(out_md: str, title: str, commands: str, *csvs: str):
+    table = defaultdict(dict)
+    names = []
+    for path in csvs:
+        agg = defaultdict(lambda: defaultdict(list))
+        for r in csv.DictReader(open(path)):
+            agg[r["Kernel_Name"]][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        for kern, per in agg.items():
+            for ctr, vals in per.items():
+                table[kern][ctr] = sum(vals) / len(vals)
+                if ctr not in names:
+                    names.append(ctr)
+    mfma = "SQ_VALU_MFMA_BUSY_CYCLES" in names and "SQ_BUSY_CYCLES" in names
+    head = names + (["MFMA busy share"] if mfma else [])
+    lines = [f"# {title}", "", "Commands (one run per line):", ""]
+    lines += [f"    {c}" for c in commands.split(";;")]
+    lines += ["", "Average per dispatch, summed over the device as rocprofv3 reports them.", "",
+              "| kernel | " + " | ".join(head) + " |", "|---|" + "---:|" * len(head)]
+    for kern in sorted(table):
+        row = table[kern]
+        cells = [f"{row[c]:.3g}" if c in row else "" for c in names]
+        if mfma:
+            busy = row.get("SQ_BUSY_CYCLES", 0.0)
+            share = row.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) / (1024 * busy / 32) if busy else 0
+            cells.append(f"{100 * share:.0f}%")
+        lines.append(f"| `{_short(kern, 60)}` | " + " | ".join(cells) + " |")
+    open(out_md, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:11])
+    elif sys.argv[1] == "counters":
+        counters(*sys.argv[2:])
     else:
         raise SystemExit(__doc__)

@@ -26,11 +26,14 @@ def _advect_gpu(u, v, w, t1, t2, tcx, tcy, pad=(0, 0)):
                                   (64, 8, 40)])
 @pytest.mark.parametrize("variant", ["staged", "direct", "staged-zc3", "staged-rows2",
                                      "staged-rows2-zc3", "staged-guard", "staged-rows2-guard",
-                                     "staged-w4", "staged-w4-zc3", "staged-w4-guard"])
+                                     "staged-w4", "staged-w4-zc3", "staged-w4-guard",
+                                     "staged-w16", "staged-w16-zc3"])
 def test_advection_bit_exact(dims, variant, monkeypatch):
     note(f"case: advect {dims} {variant}")
     if "w4" in variant:
         monkeypatch.setenv("MS_ADVECT_WAVES", "4")
+    if "w16" in variant:
+        monkeypatch.setenv("MS_ADVECT_WAVES", "16")
     if variant.endswith("guard"):
         monkeypatch.setenv("MS_ADVECT_GUARD", "1")
     if variant == "direct":
