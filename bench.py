@@ -262,8 +262,8 @@ def stream_ceiling(mib=1024, reps=20):
     res = {}
     for name, two in (("read1_write1", False), ("read2_write1", True)):
         best, how = 0.0, None
-        for form in (0, 1, 2):
-            for blocks in (1024, 2048, 4096, 8192):
+        for form in (0, 1, 2, 3):
+            for blocks in (512, 1024, 2048, 4096):
                 def step():
                     ms.stream_probe(a, out, b if two else None, blocks=blocks, form=form,
                                     stream=stream)
@@ -867,21 +867,25 @@ def bench_batched(args):
             f"{infos[i].sweeps} finished at {fin[i]:.2f} s")
     # The configuration asks for one persistent launch: that is `value`. The
     # stream-parallel run is reported beside it with its own sweep counts.
-    def work_of(inf):
+    def work_of(inf, inner_bytes):
         sw = np.array([i.sweeps for i in inf], dtype=np.float64)
         ou = np.array([i.outer_iters for i in inf], dtype=np.float64)
-        # algorithmic HBM bytes: 12 per FP32 inner update (e, rhat in; e out);
-        # per outer step 16 (norm: x, f) + 24 (rhat: x, f in; rhat, e0 out) +
-        # 20 (update: x, e in; x out) per cell; 16 per cell for the first norm
+        # algorithmic HBM bytes: inner_bytes per FP32 inner update (e, rhat in
+        # and e out once per pass: 12, or 6 with two sweeps per pass); per
+        # outer step 16 (norm: x, f) + 24 (rhat: x, f in; rhat, e0 out) + 20
+        # (update: x, e in; x out) per cell; 16 per cell for the first norm
         return (sw, ou, float((cells * sw).sum()),
-                float((cells * (12 * sw + 60 * ou + 16)).sum()))
+                float((cells * (inner_bytes * sw + 60 * ou + 16)).sum()))
 
-    sweeps, outer, lups, nbytes = work_of(infos)
+    # the persistent kernel sweeps twice per pass unless MS_BATCH_TB=1; the
+    # stream path's column kernel always does
+    per_pass = 1 if os.environ.get("MS_BATCH_TB") == "1" else 2
+    sweeps, outer, lups, nbytes = work_of(infos, 12 / per_pass)
     value_s = mean_s
     value_is = "persistent"
     glups = lups / value_s / 1e9
     achieved = nbytes / value_s / 1e9
-    _, _, s_lups, s_bytes = work_of(stream_infos[best_w])
+    _, _, s_lups, s_bytes = work_of(stream_infos[best_w], 6)
     streams_side = {"workers": best_w, "seconds": stream_s[best_w],
                     "glups": round(s_lups / stream_s[best_w] / 1e9, 3),
                     "gb_per_s_algorithmic": round(s_bytes / stream_s[best_w] / 1e9, 1),
@@ -925,11 +929,12 @@ def bench_batched(args):
                    "instances": 64, "size_seed": 4, "cells": int(cells.sum()),
                    "rhs": "8 Gaussian sources per instance (seed 1000+i)",
                    "boundary": "zero Dirichlet", "parallelism": "single GPU",
-                   "value_is": value_is},
+                   "value_is": value_is, "inner_sweeps_per_pass": per_pass},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic_for("batched_64x"),
-                     "kernel": "batched_kernel (one persistent launch per step)",
+                     "kernel": f"batched_kernel<{str(per_pass == 2).lower()}> (one persistent "
+                               "launch per step)",
                      "bytes_per_launch_algorithmic": nbytes,
                      "avg_launch_us": round(value_s * 1e6, 1)},
         "cpu_baseline": cpu,

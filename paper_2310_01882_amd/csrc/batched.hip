@@ -18,6 +18,13 @@
 // The per-cell arithmetic is the single-instance path's (same operation
 // order), so each instance's iterates are those of jacobi_solve.
 //
+// FP32 inner solves take two sweeps per team barrier: every wave runs the
+// two-sweep register march over a 60-column x 4-row tile (the second
+// sweep's inputs recomputed on a one-cell rim, so tiles need nothing from
+// each other), and both sweeps' norms come out of the same pass. A barrier
+// costs a write-back and invalidation of the XCD's L2 (agent-scope
+// release/acquire), so halving their number halves that traffic too.
+//
 // Tile shapes. A team walks its instance in tiles of tx x-cells by 16 * 64/tx
 // rows (each wave covers 64/tx rows of tx lanes), split into zs chunks along
 // z; tiles go round-robin over the team's blocks. Narrow tiles waste fewer
@@ -30,6 +37,7 @@
 // keeps each instance's fastest in a table keyed by (precision, extents,
 // team size) that jacobi_solve_batched consults.
 #include "ms_internal.hpp"
+#include "march.hpp"
 
 #include <algorithm>
 #include <atomic>
@@ -68,7 +76,7 @@ struct Inst {
   float* rhat;        // FP32 correction right-hand side
   float* e0;          // FP32 correction iterates
   float* e1;
-  double* part;       // team partials: [2][team]
+  double* part;       // team partials: [2][team], or [2][2][team] with two sweeps per pass
   unsigned* bar;      // [0] arrivals, [1] generation
   int team0, team;    // first block of the team in team order, team size
   int tx, zs;         // tile shape: lanes per row (16, 32 or 64), z chunks
@@ -334,7 +342,95 @@ __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1,
   }
 }
 
+// Two sweeps per pass over the team's wave tiles: each wave owns a tile of
+// 64 columns (60 output) x kPairRows rows x one of the instance's zs z
+// chunks and runs the two-sweep march on it (registers only, no barrier);
+// src holds u_k, dst receives u_{k+2}; a and b receive this thread's sums of
+// r(u_k)^2 and r(u_{k+1})^2.
+constexpr int kPairRows = 4;
+constexpr int kPairCols = 60;
+
+__device__ void sweep2_tiles(const Inst& q, int rank, const float* __restrict__ src,
+                             float* __restrict__ dst, const float* __restrict__ f, double& a,
+                             double& b) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tx = (q.nx + kPairCols - 1) / kPairCols;
+  const int ty = (q.ny + kPairRows - 1) / kPairRows;
+  const int ntiles = tx * ty * q.zs;
+  const float c6 = 1.0f / 6.0f;
+  for (int t = rank * kBatchWaves + w; t < ntiles; t += q.team * kBatchWaves) {
+    const int c = t / (tx * ty), r = t - c * (tx * ty);
+    const int z0 = (int)((int64_t)c * q.nz / q.zs), z1 = (int)((int64_t)(c + 1) * q.nz / q.zs);
+    two_sweep_march<float, true, kPairRows>(src, dst, f, q.nx, q.ny, q.nz, q.sy, q.sz,
+                                            (r % tx) * kPairCols - 2 + lane,
+                                            (r / tx) * kPairRows, z0, z1, c6, a, b);
+  }
+}
+
+// The inner solve of team_jacobi<float> with two sweeps per pass and one
+// team barrier per pass: pass L reads u_{2L}, writes u_{2L+2} and yields
+// the norms of u_{2L} and u_{2L+1}, which are judged in order exactly as the
+// one-sweep loop judges them (same stopping rules). When the accepted
+// iterate is odd it was never stored: one plain sweep from u_{2L} makes it.
+// Returns K and its buffer in *answer, or -1 on failure.
+__device__ int64_t team_jacobi_pairs(const BatchK& a, Inst& q, int rank, float* b0, float* b1,
+                                     const float* f, double tol_rel, int64_t cap, double* red,
+                                     double* cell, double* hist, int* s_flag, unsigned* epoch,
+                                     int* status, float** answer) {
+  double ref = 0.0;
+  for (int64_t L = 0;; ++L) {
+    float* src = (L & 1) ? b1 : b0;
+    float* dst = (L & 1) ? b0 : b1;
+    double sa = 0.0, sb = 0.0;
+    sweep2_tiles(q, rank, src, dst, f, sa, sb);
+    const double ma = block_sum(sa, red);
+    const double mb = block_sum(sb, red);
+    const int slot = 2 * (int)(L & 1);
+    if (threadIdx.x == 0) {
+      q.part[(int64_t)slot * q.team + rank] = ma;
+      q.part[(int64_t)(slot + 1) * q.team + rank] = mb;
+    }
+    if (!team_barrier(a, q, s_flag, epoch)) return -1;
+    const double na = bcast(sqrt(team_sum(q, slot, red)), cell);
+    const double nb = bcast(sqrt(team_sum(q, slot + 1, red)), cell);
+    for (int d = 0; d < 2; ++d) {
+      const int64_t j = 2 * L + d;
+      const double norm = d ? nb : na;
+      if (j == 0) ref = norm;
+      if (threadIdx.x == 0) hist[j % (kStallMax + 1)] = norm;
+      __syncthreads();
+      bool stop = false;
+      if (!isfinite(norm)) {
+        *status = MS_ENONFINITE;
+        stop = true;
+      } else if (ref == 0.0 || norm / ref <= tol_rel) {
+        stop = true;
+      } else if (j >= cap) {
+        *status = MS_NOT_CONVERGED;
+        stop = true;
+      } else if (a.stall > 0 && j >= a.stall &&
+                 norm >= hist[(j - a.stall) % (kStallMax + 1)]) {
+        stop = true;
+      }
+      if (stop) {
+        if (d == 0) {
+          *answer = src;
+          return j;
+        }
+        (void)sweep_tiles<float>(q, rank, src, dst, f);
+        if (!team_barrier(a, q, s_flag, epoch)) return -1;
+        *answer = dst;
+        return j;
+      }
+    }
+  }
+}
+
 // At most 128 VGPRs: four waves per SIMD (four resident blocks per CU).
+// PAIRS: the FP32 inner solves take two sweeps per team barrier
+// (team_jacobi_pairs); a separate instantiation, so that its register
+// demand does not weigh on the one-sweep kernel.
+template <bool PAIRS>
 __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void batched_kernel(BatchK a) {
   __shared__ double red[kBatchWaves];
@@ -417,14 +513,22 @@ void batched_kernel(BatchK a) {
     int64_t cap = a.max_inner;
     if (a.max_sweeps - total < cap) cap = a.max_sweeps - total;
     int inner_status = MS_OK;
-    const int64_t K = team_jacobi<float>(a, q, rank, q.e0, q.e1, q.rhat, eta, 0.0, true, cap,
-                                         red, &cell, hist, &s_flag, &s_epoch, &inner_status);
+    float* ans = nullptr;
+    int64_t K;
+    if (PAIRS) {
+      K = team_jacobi_pairs(a, q, rank, q.e0, q.e1, q.rhat, eta, cap, red, &cell, hist,
+                            &s_flag, &s_epoch, &inner_status, &ans);
+    } else {
+      K = team_jacobi<float>(a, q, rank, q.e0, q.e1, q.rhat, eta, 0.0, true, cap, red, &cell,
+                             hist, &s_flag, &s_epoch, &inner_status);
+      ans = (K & 1) ? q.e1 : q.e0;
+    }
     if (K < 0) return;
     if (inner_status == MS_ENONFINITE) {
       status = MS_ENONFINITE;
       break;
     }
-    update_tiles(q, rank, (K & 1) ? q.e1 : q.e0, sc);
+    update_tiles(q, rank, ans, sc);
     if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
     total += K;
     ++outer;
@@ -713,11 +817,11 @@ int resident_blocks_of(K kernel) {
   return cus * per;
 }
 
-int resident_blocks() { return resident_blocks_of(batched_kernel); }
+int resident_blocks() { return resident_blocks_of(batched_kernel<false>); }
 
 size_t inst_bytes(const ms_grid& g, int mode, int team) {
   const size_t span = (size_t)field_span(g);
-  size_t t = align_up(2 * (size_t)team * sizeof(double), 256) + 256;  // partials + barrier
+  size_t t = align_up(4 * (size_t)team * sizeof(double), 256) + 256;  // partials + barrier
   if (mode == MS_SOLVE_F64) t += align_up(span * 8, 256);
   else t += 3 * align_up(span * 4, 256);
   return t;
@@ -816,7 +920,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
     q.team = P.team[i];
     const ShapeRec sh = lookup_shape(o->precision, g, q.team);
     set_shape(q, sh.tx, sh.zs);
-    q.part = ws.take<double>(2 * (size_t)team_cap(g, G));
+    q.part = ws.take<double>(4 * (size_t)team_cap(g, G));
     q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
     const size_t span = (size_t)field_span(g);
     if (o->precision == MS_SOLVE_F64) {
@@ -855,6 +959,12 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   a.max_inner = o->max_inner;
   a.stall = o->stall_window;
   a.spin_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz real-time clock
+  // the two-sweep march indexes within a z plane with 32-bit offsets
+  // (MS_BATCH_TB=1 selects one sweep per barrier, kept as a cross-check)
+  bool pairs = !(getenv("MS_BATCH_TB") && atoi(getenv("MS_BATCH_TB")) == 1);
+  for (int i = 0; i < n; ++i) pairs = pairs && inst[i].grid.sz < INT32_MAX;
+  // every block of the grid must be resident at once (team barriers)
+  pairs = pairs && resident_blocks_of(batched_kernel<true>) >= resident_blocks();
   // One persistent launch, replayed from a captured graph.
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -862,7 +972,10 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   MS_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
   hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(batched_kernel, dim3(P.G), dim3(kBatchThreads), 0, cap, a);
+    if (pairs)
+      hipLaunchKernelGGL(batched_kernel<true>, dim3(P.G), dim3(kBatchThreads), 0, cap, a);
+    else
+      hipLaunchKernelGGL(batched_kernel<false>, dim3(P.G), dim3(kBatchThreads), 0, cap, a);
     e = hipStreamEndCapture(cap, &graph);
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

@@ -26,6 +26,7 @@
 // layouts: LDS-staged 64 x 8 tiles (sweep_tb2_kernel) and one column per
 // lane (sweep_tbw_kernel).
 #include "ms_internal.hpp"
+#include "march.hpp"
 
 // Bit-exact parity with the oracle needs every operation rounded on its own.
 #pragma clang fp contract(off)
@@ -90,33 +91,6 @@ __device__ __forceinline__ bool sweep_prologue(const SweepK<T>& a, int64_t k, do
     if (*s_done != RUNNING) return false;  // block-uniform
   }
   return true;
-}
-
-// ---------------------------------------------------------------- DPP
-
-// Lane l receives lane l-1's value (wave_shr:1); lane 0 keeps `old`.
-__device__ __forceinline__ float lane_from_left(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
-                                                    0x138, 0xf, 0xf, false));
-}
-// Lane l receives lane l+1's value (wave_shl:1); lane 63 keeps `old`.
-__device__ __forceinline__ float lane_from_right(float old, float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v),
-                                                    0x130, 0xf, 0xf, false));
-}
-__device__ __forceinline__ double lane_from_left(double old, double v) {
-  const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x138, 0xf, 0xf,
-                                             false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double lane_from_right(double old, double v) {
-  const long long o = __double_as_longlong(old), s = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp((int)o, (int)s, 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(s >> 32), 0x130, 0xf, 0xf,
-                                             false);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
 // ------------------------------------------------------- vector access
@@ -921,7 +895,6 @@ constexpr int kTrTileY = kTrRows * kTrWaves;
 
 template <typename T, bool HAS_F>
 __global__ __launch_bounds__(64 * kTrWaves) void sweep_tbr_kernel(SweepK<T> a) {
-  constexpr int R = kTrRows;
   __shared__ double red[kTrWaves];
   __shared__ int s_done;
 
@@ -949,132 +922,14 @@ __global__ __launch_bounds__(64 * kTrWaves) void sweep_tbr_kernel(SweepK<T> a) {
   const int rest = tile / a.tiles_x;
   const int tyi = rest % a.tiles_y;
   const int tzi = rest / a.tiles_y;
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
   const int z0 = tzi * a.zc;
-  const int z1 = min(z0 + a.zc, nz);
-  const int64_t sy = a.sy, sz = a.sz;
-  const T* __restrict__ src = a.buf[L % a.nbuf];
-  T* __restrict__ dst = a.buf[(L + 1) % a.nbuf];
-  const T* __restrict__ f = a.f;
+  const int z1 = min(z0 + a.zc, a.nz);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int i = txi * kTrTileX - 2 + lane;  // this lane's column
-  const int j0 = tyi * kTrTileY + w * R;    // first output row of this wave
-  const bool colA = lane >= 1 && lane <= 62, colB = lane >= 2 && lane <= 61;
-  const bool xin = i >= 0 && i < nx;
-  const int64_t col = (int64_t)(min(max(i, -1), nx) + 1);
-  // row offsets (clamped into the field) of rows j0-2 .. j0+R+1
-  int64_t roff[R + 4];
-  bool yin[R + 4];
-#pragma unroll
-  for (int q = 0; q < R + 4; ++q) {
-    const int j = j0 - 2 + q;
-    roff[q] = (int64_t)(min(max(j, -1), ny) + 1) * sy + col;
-    yin[q] = j >= 0 && j < ny;
-  }
-  auto plane = [&](int z) { return (int64_t)(min(max(z, -1), nz) + 1) * sz; };
-  // u_k rows j0-2 .. j0+R+1 (q = 0 .. R+3) at level z
-  auto load_u = [&](T (&r)[R + 4], int z) {
-    const int64_t p = plane(z);
-#pragma unroll
-    for (int q = 0; q < R + 4; ++q) r[q] = src[p + roff[q]];
-  };
-  // f rows j0-1 .. j0+R (q = 1 .. R+2) at level z
-  auto load_f = [&](T (&r)[R + 2], int z) {
-    const int64_t p = plane(z);
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) r[q] = HAS_F ? f[p + roff[q + 1]] : T(0);
-  };
-
-  T um[R + 2];        // u_k at z-1, rows j0-1 .. j0+R
-  T uc[R + 4];        // u_k at z, rows j0-2 .. j0+R+1
-  T up[R + 4];        // u_k at z+1
-  T fa[R + 2];        // f at z, rows j0-1 .. j0+R (stage A)
-  T fb[R];            // f at z-1, rows j0 .. j0+R-1 (stage B)
-  T hm2[R], hm1[R + 2];  // h at z-2 (output rows) and z-1 (rows j0-1 .. j0+R)
-  {
-    T t[R + 4];
-    load_u(t, z0 - 2);
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) um[q] = t[q + 1];
-  }
-  load_u(uc, z0 - 1);
-  load_u(up, z0);
-  load_f(fa, z0 - 1);
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    fb[q] = T(0);
-    hm2[q] = T(0);
-  }
-#pragma unroll
-  for (int q = 0; q < R + 2; ++q) hm1[q] = T(0);
-
+  const int j0 = tyi * kTrTileY + w * kTrRows;  // first output row of this wave
   double acc_a = 0.0, acc_b = 0.0;
-  const T c6 = C6<T>::v();
-  const bool wave_live = j0 < ny;
-  for (int z = z0 - 1; z <= z1 && wave_live; ++z) {
-    // next level's loads first: u_k at z+2, f at z+1
-    T un[R + 4], fn[R + 2];
-    const bool more = z + 1 <= z1;
-    if (more) {
-      load_u(un, z + 2);
-      load_f(fn, z + 1);
-    }
-    // stage A at level z: h on rows j0-1 .. j0+R
-    const bool zA = z >= 0 && z < nz, zres = z >= z0 && z < z1;
-    T hn[R + 2];
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) {
-      const T c = uc[q + 1];
-      const T xp = lane_from_right(c, c), xm = lane_from_left(c, c);
-      const T yp = uc[q + 2], ym = uc[q];
-      const T zp = up[q + 1], zm = um[q];
-      const T sum = ((((xp + xm) + yp) + ym) + zp) + zm;
-      hn[q] = (colA && xin && yin[q + 1] && zA) ? (HAS_F ? (sum - fa[q]) * c6 : sum * c6) : c;
-      if (q >= 1 && q <= R && colB && xin && yin[q + 1] && zres) {
-        const double r = cell_residual(xp, xm, yp, ym, zp, zm, c, fa[q], HAS_F);
-        acc_a += r * r;
-      }
-    }
-    // stage B at level z-1: output rows j0 .. j0+R-1
-    const int zb = z - 1;
-    if (zb >= z0 && zb < z1) {
-      const int64_t pb = (int64_t)(zb + 1) * sz;
-#pragma unroll
-      for (int q = 0; q < R; ++q) {
-        const T c = hm1[q + 1];
-        const T xp = lane_from_right(c, c), xm = lane_from_left(c, c);
-        const T yp = hm1[q + 2], ym = hm1[q];
-        const T zp = hn[q + 1], zm = hm2[q];
-        const T sum = ((((xp + xm) + yp) + ym) + zp) + zm;
-        const T v = HAS_F ? (sum - fb[q]) * c6 : sum * c6;
-        if (colB && xin && yin[q + 2]) {
-          __builtin_nontemporal_store(v, dst + pb + roff[q + 2]);
-          const double r = cell_residual(xp, xm, yp, ym, zp, zm, c, fb[q], HAS_F);
-          acc_b += r * r;
-        }
-      }
-    }
-    // shift the queues
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      hm2[q] = hm1[q + 1];
-      fb[q] = fa[q + 1];
-    }
-#pragma unroll
-    for (int q = 0; q < R + 2; ++q) {
-      hm1[q] = hn[q];
-      um[q] = uc[q + 1];
-    }
-    if (more) {
-#pragma unroll
-      for (int q = 0; q < R + 4; ++q) {
-        uc[q] = up[q];
-        up[q] = un[q];
-      }
-#pragma unroll
-      for (int q = 0; q < R + 2; ++q) fa[q] = fn[q];
-    }
-  }
+  two_sweep_march<T, HAS_F, kTrRows>(a.buf[L % a.nbuf], a.buf[(L + 1) % a.nbuf], a.f, a.nx,
+                                     a.ny, a.nz, a.sy, a.sz, txi * kTrTileX - 2 + lane, j0, z0,
+                                     z1, C6<T>::v(), acc_a, acc_b);
 
   const double ta = block_sum(acc_a, red);
   const double tb = block_sum(acc_b, red);
@@ -1203,6 +1058,9 @@ SweepGeom tb2_geom(const ms_grid& g, int dtype, bool rb) {
   s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : atoi(ev_var) == 3 ? kTbRegisters : kTbColumns)
                      : (dtype == MS_F64 ? kTbLds : kTbColumns);
   if (rb && s.variant == kTbRegisters) s.variant = kTbLds;  // Jacobi only
+  // the register march indexes within a z plane with 32-bit offsets
+  if (s.variant == kTbRegisters && g.sz >= INT32_MAX)
+    s.variant = kTbLds;
   s.vec = 1;
   s.wx = 1;
   s.rows = 2;

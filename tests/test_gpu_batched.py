@@ -115,6 +115,27 @@ def test_every_tile_shape_gives_the_same_fields(precision):
             assert np.array_equal(fa, fb), shape
 
 
+@pytest.mark.parametrize("shape", [None, (64, 4)])
+def test_two_sweeps_per_barrier_gives_the_same_fields(monkeypatch, shape):
+    """The FP32 inner solves sweep twice per team barrier by default (the
+    second sweep's norm judged after the first's); MS_BATCH_TB=1 keeps one
+    sweep per barrier. Same arithmetic per cell, so the same iterates,
+    counts and fields; extents below, at and above the 60-column and 4-row
+    wave tile, odd and even accepted iterates."""
+    note(f"case: batched two sweeps per barrier, shape {shape}")
+    dims = DIMS + [(130, 33, 20), (61, 9, 17), (60, 4, 2)]
+    probs = _instances(dims, 110, halo=True)
+    infos, got = _solve_with_shape(probs, shape, ms.MS_SOLVE_F32_REFINED)
+    monkeypatch.setenv("MS_BATCH_TB", "1")
+    ref_infos, ref = _solve_with_shape(probs, shape, ms.MS_SOLVE_F32_REFINED)
+    for (u, f), a, b, fa, fb in zip(probs, ref_infos, infos, ref, got):
+        assert b.status == ms.MS_OK
+        assert (a.sweeps, a.outer_iters) == (b.sweeps, b.outer_iters)
+        assert np.array_equal(fa, fb)
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        assert oracle.residual_norm(fb, f) <= 1e-8 * res0 * (1 + 1e-9)
+
+
 def test_autotune_picks_valid_shapes_and_leaves_x_alone():
     note("case: batched autotune 16 instances")
     dims = synth.batch_sizes(16, 4, lo=16, hi=96)
