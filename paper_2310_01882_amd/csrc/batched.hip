@@ -68,7 +68,7 @@ constexpr int kShapeZS[] = {1, 2, 4, 8};
 
 // Per-instance description and state (device memory).
 struct Inst {
-  int nx, ny, nz, pad0;
+  int nx, ny, nz, pzs;  // pzs: z chunks of the two-sweep march
   int64_t sy, sz;
   double* x;          // FP64 iterate (caller's field)
   const double* f;    // FP64 right-hand side or null
@@ -343,7 +343,7 @@ __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1,
 }
 
 // Two sweeps per pass over the team's wave tiles: each wave owns a tile of
-// 64 columns (60 output) x kPairRows rows x one of the instance's zs z
+// 64 columns (60 output) x kPairRows rows x one of the instance's pzs z
 // chunks and runs the two-sweep march on it (registers only, no barrier);
 // src holds u_k, dst receives u_{k+2}; a and b receive this thread's sums of
 // r(u_k)^2 and r(u_{k+1})^2.
@@ -356,11 +356,12 @@ __device__ void sweep2_tiles(const Inst& q, int rank, const float* __restrict__ 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int tx = (q.nx + kPairCols - 1) / kPairCols;
   const int ty = (q.ny + kPairRows - 1) / kPairRows;
-  const int ntiles = tx * ty * q.zs;
+  const int ntiles = tx * ty * q.pzs;
   const float c6 = 1.0f / 6.0f;
   for (int t = rank * kBatchWaves + w; t < ntiles; t += q.team * kBatchWaves) {
     const int c = t / (tx * ty), r = t - c * (tx * ty);
-    const int z0 = (int)((int64_t)c * q.nz / q.zs), z1 = (int)((int64_t)(c + 1) * q.nz / q.zs);
+    const int z0 = (int)((int64_t)c * q.nz / q.pzs);
+    const int z1 = (int)((int64_t)(c + 1) * q.nz / q.pzs);
     two_sweep_march<float, true, kPairRows>(src, dst, f, q.nx, q.ny, q.nz, q.sy, q.sz,
                                             (r % tx) * kPairCols - 2 + lane,
                                             (r / tx) * kPairRows, z0, z1, c6, a, b);
@@ -722,6 +723,29 @@ void set_shape(Inst& q, int tx, int zs) {
   q.tiles_y = (q.ny + ty - 1) / ty;
 }
 
+// z chunks of the two-sweep march for a team of `team` blocks: the count in
+// {1, 2, 4, 8, 16} (at most nz) that minimises rounds x levels per chunk --
+// a round gives every wave of the team one tile, a chunk marches nz/pzs + 2
+// levels -- the fewest chunks on a tie. MS_BATCH_PZS overrides it.
+int pair_zs(int nx, int ny, int nz, int team) {
+  const char* ev = getenv("MS_BATCH_PZS");
+  if (ev && atoi(ev) >= 1) return std::min(atoi(ev), nz);
+  const int64_t t2 = (int64_t)((nx + kPairCols - 1) / kPairCols) *
+                     ((ny + kPairRows - 1) / kPairRows);
+  const int64_t waves = (int64_t)team * kBatchWaves;
+  int best = 1;
+  double cost = 0.0;
+  for (int zs = 1; zs <= 16 && zs <= nz; zs *= 2) {
+    const int64_t rounds = (t2 * zs + waves - 1) / waves;
+    const double c = (double)rounds * ((double)nz / zs + 2.0);
+    if (zs == 1 || c < cost * 0.999) {
+      cost = c;
+      best = zs;
+    }
+  }
+  return best;
+}
+
 // Tuned shapes, keyed by (precision, nx, ny, nz, team size).
 using ShapeKey = std::tuple<int, int, int, int, int>;
 struct ShapeRec {
@@ -920,6 +944,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
     q.team = P.team[i];
     const ShapeRec sh = lookup_shape(o->precision, g, q.team);
     set_shape(q, sh.tx, sh.zs);
+    q.pzs = pair_zs(g.nx, g.ny, g.nz, q.team);
     q.part = ws.take<double>(4 * (size_t)team_cap(g, G));
     q.bar = reinterpret_cast<unsigned*>(ws.take<char>(256));
     const size_t span = (size_t)field_span(g);
