@@ -304,6 +304,150 @@ void conv_rows_kernel(RowK a) {
   }
 }
 
+// ------------------------------------------ lane-shifted 32-channel kernel
+//
+// The row-blocked kernel's work with a third of its L1 data: a wave's 32
+// lanes (per K half) hold input voxels x0-1 .. x0+30 and it stores the 30
+// outputs x0 .. x0+29. The dx = -1 and +1 neighbours of a loaded row are the
+// adjacent lanes' values (DPP shift of the whole wave by one lane), so the
+// rows of a z level are loaded once, both channel halves, for all three dx
+// taps. Lanes 0 and 31 of each half are halo voxels: the shift fills them
+// with a neighbour half's value or zero, and their outputs are not stored.
+// The MFMAs run in the row-blocked kernel's order (dz, dx, channel half;
+// rows; dy), so every accumulator sums the same products in the same order.
+constexpr int kShiftVox = 30;
+
+// s = +1: lane l receives lane l+1's value; s = -1: lane l-1's; 0 elsewhere.
+__device__ __forceinline__ bf16x8 shift_lanes(bf16x8 v, int s) {
+  typedef __attribute__((ext_vector_type(4))) int i32x4;
+  const i32x4 x = __builtin_bit_cast(i32x4, v);
+  i32x4 y;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    y[e] = s > 0 ? __builtin_amdgcn_update_dpp(0, x[e], 0x130, 0xf, 0xf, false)
+                 : __builtin_amdgcn_update_dpp(0, x[e], 0x138, 0xf, 0xf, false);
+  return __builtin_bit_cast(bf16x8, y);
+}
+
+template <bool kDgrad>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_shift_kernel(RowK a) {
+  constexpr int C = 32;
+  constexpr int R = kConvRows;
+  constexpr int sgn = kDgrad ? -1 : 1;
+  __shared__ bf16x8 wl[kTaps * kCo * C / 8];  // layout as in conv_rows_kernel
+  for (int gi = threadIdx.x; gi < kTaps * kCo * C / 8; gi += blockDim.x) {
+    const int t = gi / (kCo * 4), co = (gi / 4) % kCo, c8 = gi % 4;
+    wl[((t * 2 + c8 / 2) * kCo + co) * 2 + c8 % 2] = reinterpret_cast<const bf16x8*>(a.w)[gi];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + kShiftVox - 1) / kShiftVox, sy = (a.v.Y + R - 1) / R;
+  const float bj = kDgrad ? 0.0f : a.bias[m];
+  for (int seg = blockIdx.x * 4 + w; seg < a.nseg; seg += gridDim.x * 4) {
+    const int x0 = (seg % sx) * kShiftVox, y0 = ((seg / sx) % sy) * R, z = seg / (sx * sy);
+    f32x16 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = f32x16{};
+    // rows y0-1 .. y0+R of level z + sgn*dz, both channel halves, at this
+    // lane's voxel x0-1+m; coordinates clamped into the volume (halo
+    // included), unconditional loads as in conv_rows_kernel
+    auto load_level = [&](bf16x8 (&av)[2][R + 2], int dz) {
+      const int x = min(x0 - 1 + m, a.v.X);
+#pragma unroll
+      for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int k = 0; k < R + 2; ++k) {
+          const int yy = min(y0 - 1 + k, a.v.Y);
+          av[half][k] = *reinterpret_cast<const bf16x8*>(
+              a.src + a.v.vox(x, yy, z + sgn * dz) * C + half * 16 + 8 * h);
+        }
+    };
+    bf16x8 cur[2][R + 2], nxt[2][R + 2];
+    load_level(cur, -1);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      const int dz = l - 1;
+      if (l + 1 < 3) load_level(nxt, dz + 1);  // in flight while this level computes
+      // keep those loads ahead of this level's MFMAs (left to itself the
+      // scheduler sinks them to just before their first use: 175 -> 143 us
+      // forward, 203 -> 171 us input gradient at 128^3 with this barrier)
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+        const int dx = dxi - 1;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          bf16x8 rows[R + 2];
+#pragma unroll
+          for (int k = 0; k < R + 2; ++k)
+            rows[k] = dx == 0 ? cur[half][k] : shift_lanes(cur[half][k], sgn * dx);
+          bf16x8 bv[3];
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            const int t = (dx + 1) + 3 * d + 9 * (dz + 1);  // dy = d - 1
+            bv[d] = wl[((t * 2 + half) * kCo + m) * 2 + h];
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+              const int k = r + 1 + sgn * (d - 1);
+              acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rows[k], bv[d], acc[r], 0, 0, 0);
+            }
+        }
+      }
+      if (l + 1 < 3) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
+#pragma unroll
+          for (int k = 0; k < R + 2; ++k) cur[half][k] = nxt[half][k];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    bf16 mk[kDgrad ? R : 1][16];
+    if constexpr (kDgrad) {
+      if (a.mask) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int x = min(x0 - 1 + 8 * (q / 4) + 4 * h + (q % 4), a.v.X);
+            const int y = min(y0 + r, a.v.Y);
+            mk[r][q] = a.mask[a.v.vox(x, y, z) * C + m];
+          }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) mk[r][q] = (bf16)1.0f;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = y0 + r;
+      if (y >= a.v.Y) break;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = 8 * (q / 4) + 4 * h + (q % 4);  // lane voxel x0-1+i
+        const int x = x0 - 1 + i;
+        if (i < 1 || i > kShiftVox || x >= a.v.X) continue;
+        const int64_t p = a.v.vox(x, y, z);
+        if constexpr (kDgrad) {
+          const float gv = (float)mk[r][q] > 0.0f ? acc[r][q] : 0.0f;
+          a.din[p * C + m] = (bf16)gv;
+        } else {
+          float val = acc[r][q] + bj;
+          if (a.relu) val = fmaxf(val, 0.0f);
+          if (a.out) a.out[p * kCo + m] = (bf16)val;
+          if (a.out32 && m == 0) a.out32[p] = val;
+        }
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- wgrad
 
 struct WgK {
@@ -1032,6 +1176,13 @@ bool row_blocked() {
 
 bool cin_ok(int cin) { return cin == 8 || cin == 32; }
 
+// 32-channel layers: the lane-shifted row kernels; MS_CONV_SHIFT=0 keeps
+// the row-blocked ones (a cross-check: the same sums bit for bit).
+bool conv_shift() {
+  const char* e = getenv("MS_CONV_SHIFT");
+  return !(e && atoi(e) == 0);
+}
+
 }  // namespace
 }  // namespace ms
 
@@ -1051,10 +1202,15 @@ extern "C" int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, con
   if (cin == 8) {
     hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
   } else if (row_blocked()) {
-    const RowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
-                 static_cast<bf16*>(out), out32, nullptr, nullptr, relu,
-                 ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
-    hipLaunchKernelGGL(conv_rows_kernel<false>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    RowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
+           static_cast<bf16*>(out), out32, nullptr, nullptr, relu,
+           ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
+    if (conv_shift()) {
+      r.nseg = ((X + kShiftVox - 1) / kShiftVox) * ((Y + kConvRows - 1) / kConvRows) * Z;
+      hipLaunchKernelGGL(conv_shift_kernel<false>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    } else {
+      hipLaunchKernelGGL(conv_rows_kernel<false>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    }
   } else {
     hipLaunchKernelGGL(conv_fwd_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
   }
@@ -1073,11 +1229,16 @@ extern "C" int conv3d_bf16_dgrad(int X, int Y, int Z, int cin, const void* dout,
   if (cin == 8) {
     hipLaunchKernelGGL(conv_dgrad_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
   } else if (row_blocked()) {
-    const RowK r{{X, Y, Z}, static_cast<const bf16*>(dout), static_cast<const bf16*>(wd),
-                 nullptr, nullptr, nullptr, static_cast<const bf16*>(mask),
-                 static_cast<bf16*>(din), 0,
-                 ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
-    hipLaunchKernelGGL(conv_rows_kernel<true>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    RowK r{{X, Y, Z}, static_cast<const bf16*>(dout), static_cast<const bf16*>(wd),
+           nullptr, nullptr, nullptr, static_cast<const bf16*>(mask),
+           static_cast<bf16*>(din), 0,
+           ((X + 31) / 32) * ((Y + kConvRows - 1) / kConvRows) * Z};
+    if (conv_shift()) {
+      r.nseg = ((X + kShiftVox - 1) / kShiftVox) * ((Y + kConvRows - 1) / kConvRows) * Z;
+      hipLaunchKernelGGL(conv_shift_kernel<true>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    } else {
+      hipLaunchKernelGGL(conv_rows_kernel<true>, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+    }
   } else {
     hipLaunchKernelGGL(conv_dgrad_kernel<32>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
   }

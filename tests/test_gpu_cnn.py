@@ -51,13 +51,47 @@ def _close(got, want, tol=1e-2):
     assert cos >= 0.999 and rel <= tol, (cos, rel)
 
 
-@pytest.fixture(params=["row-blocked", "one-row"])
+@pytest.fixture(params=["row-blocked", "one-row", "lane-shifted"])
 def conv_kernel(request, monkeypatch):
-    """The 32-channel layers have a row-blocked kernel (default) and the
-    one-row kernels (MS_CONV_ROWS=0); both are checked."""
+    """The 32-channel layers have the lane-shifted row kernels (default),
+    the row-blocked ones (MS_CONV_SHIFT=0) and the one-row kernels
+    (MS_CONV_ROWS=0); all are checked."""
     if request.param == "one-row":
         monkeypatch.setenv("MS_CONV_ROWS", "0")
+    monkeypatch.setenv("MS_CONV_SHIFT", "1" if request.param == "lane-shifted" else "0")
     return request.param
+
+
+@pytest.mark.parametrize("shape", [(70, 9, 3), (61, 13, 4), (30, 4, 2), (31, 5, 1),
+                                   (64, 64, 40)])
+def test_lane_shifted_conv_equals_row_blocked(shape, monkeypatch):
+    """The lane-shifted kernels sum the same products in the same order as
+    the row-blocked ones: forward (bias, ReLU, BF16 and FP32 outputs) and
+    input gradient (ReLU mask) are equal bit for bit, on random BF16
+    values and extents around the 30-voxel tile."""
+    nx, ny, nz = shape
+    note(f"case: lane-shifted conv {shape}")
+    r = synth.rng(23)
+    x = cnn.round_bf16(np.maximum(r.standard_normal((32, nz, ny, nx)), 0.0))
+    g = cnn.round_bf16(r.standard_normal((32, nz, ny, nx)))
+    w, wf, wd = _weights(32, 32, 32, 24)
+    bt = torch.from_numpy((0.1 * r.standard_normal(32)).astype(np.float32)).cuda()
+    xin, gin = _bf16_act(x, 32), _bf16_act(g, 32)
+    res = []
+    for shift in ("0", "1"):
+        monkeypatch.setenv("MS_CONV_SHIFT", shift)
+        out = torch.zeros_like(xin)
+        out32 = torch.zeros((nz + 2, ny + 2, nx + 2), dtype=torch.float32, device="cuda")
+        din = torch.zeros_like(xin)
+        assert ms.lib.conv3d_bf16_fwd(nx, ny, nz, 32, ms._ptr(xin), ms._ptr(wf), ms._ptr(bt),
+                                      ms._ptr(out), ms._ptr(out32), 1, None) == 0
+        assert ms.lib.conv3d_bf16_dgrad(nx, ny, nz, 32, ms._ptr(gin), ms._ptr(wd),
+                                        ms._ptr(xin), ms._ptr(din), None) == 0
+        torch.cuda.synchronize()
+        res.append((out.cpu(), out32.cpu(), din.cpu()))
+    for a, b in zip(*res):
+        assert torch.equal(a.view(torch.int16) if a.dtype == torch.bfloat16 else a,
+                           b.view(torch.int16) if b.dtype == torch.bfloat16 else b)
 
 
 @pytest.mark.parametrize("cin,cinp,relu", [(2, 8, True), (32, 32, True), (32, 32, False)])
@@ -199,9 +233,11 @@ def test_training_reduces_the_loss_on_one_instance():
     assert losses[-1] < 0.5 * losses[0]
 
 
-def test_row_blocked_conv_on_ragged_extents():
-    """x not a multiple of 32 and y not a multiple of the 4-row block, both
-    directions, against the oracle."""
+@pytest.mark.parametrize("shift", ["0", "1"])
+def test_row_blocked_conv_on_ragged_extents(shift, monkeypatch):
+    """x not a multiple of 32 (nor of 30) and y not a multiple of the 4-row
+    block, both directions, both row-kernel forms, against the oracle."""
+    monkeypatch.setenv("MS_CONV_SHIFT", shift)
     nx, ny, nz = 70, 9, 3
     r = synth.rng(11)
     x = cnn.round_bf16(np.maximum(r.standard_normal((32, nz, ny, nx)), 0.0))
@@ -299,8 +335,8 @@ def test_wgrad_at_full_size_on_sampled_outputs(cin, cinp):
     assert np.array_equal(db.cpu().numpy()[:co].astype(np.float64), ref_db)
 
 
-@pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
-def test_forward_and_input_gradient_at_full_size(cin, cinp):
+@pytest.mark.parametrize("cin,cinp,shift", [(2, 8, "0"), (32, 32, "0"), (32, 32, "1")])
+def test_forward_and_input_gradient_at_full_size(cin, cinp, shift, monkeypatch):
     """Forward (bias, ReLU, BF16 and FP32 outputs) and input gradient (ReLU
     mask) at 128^3 in the launch the benchmarks time, against the oracle on
     every channel of the z planes 0-1, 63-64 and 126-127 (the oracle runs on
@@ -309,7 +345,8 @@ def test_forward_and_input_gradient_at_full_size(cin, cinp):
     BF16 outputs must equal the oracle's rounded values bit for bit and the
     FP32 output its exact value."""
     n = 128
-    note(f"case: forward and input gradient 128^3 cin={cinp}")
+    monkeypatch.setenv("MS_CONV_SHIFT", shift)
+    note(f"case: forward and input gradient 128^3 cin={cinp} shift={shift}")
     r = synth.rng(19)
     x = np.maximum(r.integers(-7, 8, (cin, n, n, n), dtype=np.int8), 0).astype(np.float32) / 8
     g = r.integers(-7, 8, (32, n, n, n), dtype=np.int8).astype(np.float32) / 8
