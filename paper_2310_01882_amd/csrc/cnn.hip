@@ -448,6 +448,98 @@ void conv_shift_kernel(RowK a) {
   }
 }
 
+// ------------------------------------ lane-shifted 8-channel forward
+//
+// The first layer (8 input channels) in the lane-shifted form: K = 16 is
+// two taps of 8 channels, the lane half h taking one of them. The taps of
+// an MFMA share (dx, dy) and differ in dz: pair 0 holds dz = -1 (h = 0) and
+// dz = 0 (h = 1), pair 1 dz = +1 (h = 0) and a zero weight (h = 1). A wave
+// loads, per pair, the rows y0-1 .. y0+4 of its two planes at voxels
+// x0-1 .. x0+30 (one 16-byte load per lane and row), takes dx = +-1 from
+// the neighbouring lanes and dy from the row index, and issues 3 x 3 x 2 x 4
+// MFMAs for its 4 x 30 outputs; the next task's rows are loaded while this
+// one computes. (The one-row kernel issues one load per MFMA.)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void conv_shift8_kernel(RowK a) {
+  constexpr int CIN = 8, R = kConvRows;
+  __shared__ bf16x8 wl[kTaps * kCo];  // [tap][co], 8 input channels each
+  for (int t = threadIdx.x; t < kTaps * kCo; t += blockDim.x)
+    wl[t] = reinterpret_cast<const bf16x8*>(a.w)[t];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = lane & 31, h = lane >> 5;
+  const int sx = (a.v.X + kShiftVox - 1) / kShiftVox, sy = (a.v.Y + R - 1) / R;
+  const float bj = a.bias[m];
+  // rows y0-1 .. y0+R of the task's planes for both pairs, at voxel x0-1+m
+  // (clamped into the volume, halo included; unconditional loads)
+  auto load_task = [&](bf16x8 (&av)[2][R + 2], int seg) {
+    const int x0 = (seg % sx) * kShiftVox, y0 = ((seg / sx) % sy) * R, z = seg / (sx * sy);
+    const int x = min(x0 - 1 + m, a.v.X);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int zz = p == 0 ? z - 1 + h : z + 1;
+#pragma unroll
+      for (int k = 0; k < R + 2; ++k)
+        av[p][k] = *reinterpret_cast<const bf16x8*>(
+            a.src + a.v.vox(x, min(y0 - 1 + k, a.v.Y), zz) * CIN);
+    }
+  };
+  const int stride = gridDim.x * 4;
+  int seg = blockIdx.x * 4 + w;
+  bf16x8 cur[2][R + 2], nxt[2][R + 2];
+  if (seg < a.nseg) load_task(cur, seg);
+  for (; seg < a.nseg; seg += stride) {
+    if (seg + stride < a.nseg) load_task(nxt, seg + stride);
+    __builtin_amdgcn_sched_barrier(0);  // keep those loads ahead of this task's MFMAs
+    const int x0 = (seg % sx) * kShiftVox, y0 = ((seg / sx) % sy) * R, z = seg / (sx * sy);
+    f32x16 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = f32x16{};
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int dxi = 0; dxi < 3; ++dxi) {
+        const int dx = dxi - 1;
+        bf16x8 rows[R + 2];
+#pragma unroll
+        for (int k = 0; k < R + 2; ++k) rows[k] = dx == 0 ? cur[p][k] : shift_lanes(cur[p][k], dx);
+        bf16x8 bv[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          // tap (dx, dy = d - 1, dz): pair 0 dz = h - 1, pair 1 dz = +1 (h = 0 only)
+          const int dz = p == 0 ? h - 1 : 1;
+          const int t = (dx + 1) + 3 * d + 9 * (dz + 1);
+          bv[d] = (p == 1 && h == 1) ? zero8() : wl[t * kCo + m];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(rows[r + d], bv[d], acc[r], 0, 0, 0);
+      }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = y0 + r;
+      if (y >= a.v.Y) break;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = 8 * (q / 4) + 4 * h + (q % 4);  // lane voxel x0-1+i
+        const int x = x0 - 1 + i;
+        if (i < 1 || i > kShiftVox || x >= a.v.X) continue;
+        float val = acc[r][q] + bj;
+        if (a.relu) val = fmaxf(val, 0.0f);
+        const int64_t pv = a.v.vox(x, y, z);
+        if (a.out) a.out[pv * kCo + m] = (bf16)val;
+        if (a.out32 && m == 0) a.out32[pv] = val;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int k = 0; k < R + 2; ++k) cur[p][k] = nxt[p][k];
+  }
+}
+
 // --------------------------------------------------------------- wgrad
 
 struct WgK {
@@ -1176,8 +1268,10 @@ bool row_blocked() {
 
 bool cin_ok(int cin) { return cin == 8 || cin == 32; }
 
-// 32-channel layers: the lane-shifted row kernels; MS_CONV_SHIFT=0 keeps
-// the row-blocked ones (a cross-check: the same sums bit for bit).
+// Lane-shifted kernels for the 32-channel layers and the 8-channel forward;
+// MS_CONV_SHIFT=0 keeps the row-blocked 32-channel kernels (the same sums
+// bit for bit) and the one-row 8-channel forward (the same products, summed
+// in another order).
 bool conv_shift() {
   const char* e = getenv("MS_CONV_SHIFT");
   return !(e && atoi(e) == 0);
@@ -1199,7 +1293,12 @@ extern "C" int conv3d_bf16_fwd(int X, int Y, int Z, int cin, const void* in, con
   FwdK a{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
          static_cast<bf16*>(out), out32, relu, ((X + 31) / 32) * Y * Z};
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (cin == 8) {
+  if (cin == 8 && conv_shift()) {
+    const RowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,
+                 static_cast<bf16*>(out), out32, nullptr, nullptr, relu,
+                 ((X + kShiftVox - 1) / kShiftVox) * ((Y + kConvRows - 1) / kConvRows) * Z};
+    hipLaunchKernelGGL(conv_shift8_kernel, dim3(conv_grid_blocks()), dim3(256), 0, s, r);
+  } else if (cin == 8) {
     hipLaunchKernelGGL(conv_fwd_kernel<8>, dim3(conv_grid_blocks()), dim3(256), 0, s, a);
   } else if (row_blocked()) {
     RowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(w), bias,

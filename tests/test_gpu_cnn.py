@@ -233,6 +233,37 @@ def test_training_reduces_the_loss_on_one_instance():
     assert losses[-1] < 0.5 * losses[0]
 
 
+@pytest.mark.parametrize("shape", [(70, 9, 3), (61, 13, 4), (31, 5, 1), (30, 4, 2)])
+def test_first_layer_lane_shifted_forward_on_ragged_extents(shape, monkeypatch):
+    """The 8-channel forward in its lane-shifted form (pairs of z taps per
+    MFMA, dx from the neighbouring lanes) on extents around its 30 x 4
+    tile, against the oracle; inputs, weights and bias are k/8, so every
+    sum is exact in FP32 and the BF16 outputs equal the oracle's rounded
+    values bit for bit."""
+    nx, ny, nz = shape
+    monkeypatch.setenv("MS_CONV_SHIFT", "1")
+    note(f"case: first-layer lane-shifted forward {shape}")
+    r = synth.rng(29)
+    x = r.integers(-7, 8, (8, nz, ny, nx)).astype(np.float32) / 8
+    w = r.integers(-7, 8, (27, 32, 8)).astype(np.float32) / 8
+    b = r.integers(-7, 8, 32).astype(np.float32) / 8
+    wt = torch.from_numpy(w).cuda()
+    wf = torch.empty(27 * 32 * 8, dtype=torch.bfloat16, device="cuda")
+    wd = torch.empty_like(wf)
+    assert ms.lib.cnn_pack_weights(8, ms._ptr(wt), ms._ptr(wf), ms._ptr(wd), None) == 0
+    bt = torch.from_numpy(b).cuda()
+    xin = _bf16_act(x, 8)
+    out = torch.zeros((nz + 2) * (ny + 2) * (nx + 2) * 32, dtype=torch.bfloat16, device="cuda")
+    assert ms.lib.conv3d_bf16_fwd(nx, ny, nz, 8, ms._ptr(xin), ms._ptr(wf), ms._ptr(bt),
+                                  ms._ptr(out), None, 1, None) == 0
+    torch.cuda.synchronize()
+    wo = wsm.to_oracle_weights(w, 8, 32)
+    ref = np.maximum(cnn.conv3d(x.astype(np.float64), wo, b.astype(np.float64)), 0.0)
+    assert np.array_equal(_act_np(out, 32, 32, (nx, ny, nz)), cnn.round_bf16(ref))
+    o = out.float().view(nz + 2, ny + 2, nx + 2, 32)
+    assert torch.all(o[:, -1] == 0) and torch.all(o[:, :, -1] == 0) and torch.all(o[-1] == 0)
+
+
 @pytest.mark.parametrize("shift", ["0", "1"])
 def test_row_blocked_conv_on_ragged_extents(shift, monkeypatch):
     """x not a multiple of 32 (nor of 30) and y not a multiple of the 4-row
@@ -335,7 +366,8 @@ def test_wgrad_at_full_size_on_sampled_outputs(cin, cinp):
     assert np.array_equal(db.cpu().numpy()[:co].astype(np.float64), ref_db)
 
 
-@pytest.mark.parametrize("cin,cinp,shift", [(2, 8, "0"), (32, 32, "0"), (32, 32, "1")])
+@pytest.mark.parametrize("cin,cinp,shift", [(2, 8, "0"), (8, 8, "1"), (32, 32, "0"),
+                                            (32, 32, "1")])
 def test_forward_and_input_gradient_at_full_size(cin, cinp, shift, monkeypatch):
     """Forward (bias, ReLU, BF16 and FP32 outputs) and input gradient (ReLU
     mask) at 128^3 in the launch the benchmarks time, against the oracle on
