@@ -715,6 +715,29 @@ struct WgRowK {
   int ntask;         // (X/32 rounded up) * (Y/kWgRows rounded up) * Z
 };
 
+// Two transposing LDS reads (ds_read_b64_tr_b16) giving a lane the 8
+// values an MFMA operand needs along K from a channels-last tile (all 64
+// lanes must take part: a lane's result comes from other lanes' fetches):
+// within each 16-lane group, lane 4a + b receives element b of the 8-byte
+// chunks fetched by lanes a, a + 4, a + 8 and a + 12 (checked on the
+// device). So
+// if lane l fetches channels 16((l/16)%2) + 4((l%16)%4) .. +3 of voxel
+// v0 + 8(l/32) + (l%16)/4 (p0) and of the voxel 4 further on (p1), lane
+// m + 32h receives channel m of voxels v0 + 8h .. v0 + 8h + 7.
+typedef __attribute__((ext_vector_type(4))) short i16x4;
+typedef __attribute__((ext_vector_type(8))) short i16x8;
+__device__ __forceinline__ bf16x8 lds_tr8(const bf16* p0, const bf16* p1) {
+  typedef __attribute__((address_space(3))) i16x4 lds_i16x4;
+  const i16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)const_cast<bf16*>(p0));
+  const i16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_i16x4*)const_cast<bf16*>(p1));
+  const i16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+  return __builtin_bit_cast(bf16x8, v);
+}
+
+// kTr: operands through transposing LDS reads (2 per operand) instead of
+// one 2-byte read per element (8 for A, 10 per row for B); the same values,
+// so the same sums.
+template <bool kTr>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv_wgrad_rows_kernel(WgRowK a) {
   constexpr int C = 32, R = kWgRows;
@@ -794,32 +817,52 @@ void conv_wgrad_rows_kernel(WgRowK a) {
 #pragma unroll 1
       for (int kk = 0; kk < 2; ++kk) {
         const int vb = 16 * kk + 8 * h;  // first voxel of the lane's K-slice
+        // transposing reads: this lane fetches channels tc .. tc+3 of voxel
+        // tv (+ shift) and tv + 4 (+ shift)
+        const int tv = 16 * kk + 8 * (lane >> 5) + ((lane & 15) >> 2);
+        const int tc = 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
         bf16x8 av;
+        if constexpr (kTr) {
+          av = lds_tr8(&dp[r * kWgDpRow + wg_slot(tv) + tc], &dp[r * kWgDpRow + wg_slot(tv + 4) + tc]);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
+          for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
+        }
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           const int row = half ? rowB : rowA;
           const int dz = row / 3 - 1, dy = row % 3 - 1;
-          const bf16* src = &inr[((dz + 1) * (R + 2) + r + 1 + dy) * kWgInRow + m];
+          const int rbase = ((dz + 1) * (R + 2) + r + 1 + dy) * kWgInRow;
+          const bf16* src = &inr[rbase + m];
           bf16 s[10];
+          if constexpr (!kTr) {
 #pragma unroll
-          for (int j = 0; j < 10; ++j) s[j] = src[wg_slot(vb + j)];
+            for (int j = 0; j < 10; ++j) s[j] = src[wg_slot(vb + j)];
+          }
 #pragma unroll
           for (int d = 0; d < 3; ++d) {
             bf16x8 bv;
+            if constexpr (kTr) {
+              bv = lds_tr8(&inr[rbase + wg_slot(tv + d) + tc], &inr[rbase + wg_slot(tv + d + 4) + tc]);
+            } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) bv[e] = s[e + d];
+              for (int e = 0; e < 8; ++e) bv[e] = s[e + d];
+            }
             acc[3 * half + d] =
                 __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[3 * half + d], 0, 0, 0);
           }
         }
         if (extra) {
           // row 8: dz = dy = +1, dx = w - 1
-          const bf16* src = &inr[(2 * (R + 2) + r + 2) * kWgInRow + m];
+          const int rbase = (2 * (R + 2) + r + 2) * kWgInRow;
           bf16x8 bv;
+          if constexpr (kTr) {
+            bv = lds_tr8(&inr[rbase + wg_slot(tv + w) + tc], &inr[rbase + wg_slot(tv + w + 4) + tc]);
+          } else {
+            const bf16* src = &inr[rbase + m];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) bv[e] = src[wg_slot(vb + e + w)];
+            for (int e = 0; e < 8; ++e) bv[e] = src[wg_slot(vb + e + w)];
+          }
           acc[6] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[6], 0, 0, 0);
         } else {
           // wave 3 (six taps) sums dPre over the voxels: A times a ones column
@@ -871,6 +914,12 @@ constexpr int kWg8Chunks = kWg8DpChunks + kWg8InChunks;
 constexpr int kWg8PerThread = (kWg8Chunks + 255) / 256;
 static_assert(kWg8DpChunks % 256 == 0 && kWg8Rows % 4 == 0, "whole load rounds and row sets");
 
+// kTr: operands through transposing LDS reads (as in the 32-channel
+// kernel); lane (n, h) of B receives channel n & 7 of voxels shifted by
+// dx + 1 = n >> 3, the ones column (n = 24 of row 0) from the ones slot, the
+// other spare columns from dx + 1 = 0. The same values in every stored
+// column, so the same sums.
+template <bool kTr>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 void conv_wgrad_rows8_kernel(WgRowK a) {
   constexpr int C = 8, R = kWg8Rows;
@@ -944,18 +993,40 @@ void conv_wgrad_rows8_kernel(WgRowK a) {
     for (int rk = 0; rk < 2 * R / 4; ++rk) {
       const int r = w + 4 * (rk >> 1);        // the wave's dPre row
       const int vb = 16 * (rk & 1) + 8 * h;  // first voxel of the lane's K-slice
+      // transposing reads (see lds_tr8): voxel tv (+ 4), channels tc (A) or
+      // 4 (ta & 1) at shift tdx1 (B)
+      const int tv = 16 * (rk & 1) + 8 * (lane >> 5) + ((lane & 15) >> 2);
+      const int tc = 16 * ((lane >> 4) & 1) + 4 * (lane & 3);
+      const int ta = lane & 3, todd = (lane >> 4) & 1;
+      const int tdx1 = todd ? (ta >= 2 ? 0 : 2) : (ta >> 1);
+      const bool tones = todd && ta == 2;
       bf16x8 av;
+      if constexpr (kTr) {
+        av = lds_tr8(&dp[r * kWgDpRow + wg_slot(tv) + tc], &dp[r * kWgDpRow + wg_slot(tv + 4) + tc]);
+      } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
+        for (int e = 0; e < 8; ++e) av[e] = dp[r * kWgDpRow + wg_slot(vb + e) + m];
+      }
 #pragma unroll
       for (int row = 0; row < 9; ++row) {
         const int dz = row / 3 - 1, dy = row % 3 - 1;
         const int ri = (dz + 1) * (R + 2) + r + 1 + dy;
-        const bool ones = row == 0 && m == 24;
         bf16x8 bv;
+        if constexpr (kTr) {
+          // one read for every lane (a transposing read takes its values from
+          // the other lanes of its group, so it must not run under a branch):
+          // the ones lanes select their address instead
+          const int rb = ri * kWg8InRow + 4 * (ta & 1);
+          const bool one = row == 0 && tones;
+          const int q0 = one ? kOnes : rb + wg8_slot(tv + tdx1);
+          const int q1 = one ? kOnes + 4 : rb + wg8_slot(tv + tdx1 + 4);
+          bv = lds_tr8(&inr[q0], &inr[q1]);
+        } else {
+          const bool ones = row == 0 && m == 24;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          bv[e] = inr[ones ? kOnes : ri * kWg8InRow + wg8_slot(vb + e + dx1) + ci];
+          for (int e = 0; e < 8; ++e)
+            bv[e] = inr[ones ? kOnes : ri * kWg8InRow + wg8_slot(vb + e + dx1) + ci];
+        }
         acc[row] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[row], 0, 0, 0);
       }
     }
@@ -1268,6 +1339,13 @@ bool row_blocked() {
 
 bool cin_ok(int cin) { return cin == 8 || cin == 32; }
 
+// Weight gradients: operands through transposing LDS reads; MS_WGRAD_TR=0
+// keeps the element-wise reads (the same values).
+bool wgrad_tr() {
+  const char* e = getenv("MS_WGRAD_TR");
+  return !(e && atoi(e) == 0);
+}
+
 // Lane-shifted kernels for the 32-channel layers and the 8-channel forward;
 // MS_CONV_SHIFT=0 keeps the row-blocked 32-channel kernels (the same sums
 // bit for bit) and the one-row 8-channel forward (the same products, summed
@@ -1370,9 +1448,15 @@ extern "C" int conv3d_bf16_wgrad(int X, int Y, int Z, int cin, const void* in, c
     const WgRowK r{{X, Y, Z}, static_cast<const bf16*>(in), static_cast<const bf16*>(dpre),
                    static_cast<float*>(work), ntask};
     if (cin == 8)
-      hipLaunchKernelGGL(conv_wgrad_rows8_kernel, dim3(nb), dim3(256), 0, s, r);
+      if (wgrad_tr())
+        hipLaunchKernelGGL(conv_wgrad_rows8_kernel<true>, dim3(nb), dim3(256), 0, s, r);
+      else
+        hipLaunchKernelGGL(conv_wgrad_rows8_kernel<false>, dim3(nb), dim3(256), 0, s, r);
     else
-      hipLaunchKernelGGL(conv_wgrad_rows_kernel, dim3(nb), dim3(256), 0, s, r);
+      if (wgrad_tr())
+        hipLaunchKernelGGL(conv_wgrad_rows_kernel<true>, dim3(nb), dim3(256), 0, s, r);
+      else
+        hipLaunchKernelGGL(conv_wgrad_rows_kernel<false>, dim3(nb), dim3(256), 0, s, r);
   } else if (cin == 8) {
     hipLaunchKernelGGL(conv_wgrad_kernel<8>, dim3(nb), dim3(256), 0, s, a);
   } else {

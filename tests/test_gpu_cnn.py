@@ -297,13 +297,15 @@ def test_row_blocked_conv_on_ragged_extents(shift, monkeypatch):
 
 @pytest.mark.parametrize("cin,cinp", [(2, 8), (32, 32)])
 @pytest.mark.parametrize("shape", [(70, 9, 3), (64, 64, 40)])
-def test_row_blocked_wgrad(shape, cin, cinp):
+def test_row_blocked_wgrad(shape, cin, cinp, monkeypatch):
     """Weight gradient of the first layer (2 channels padded to 8) and of a
     32-channel layer: x past a 32-voxel task and y past a 4-row task
     (70 x 9 x 3), and a volume with several tasks per block (64 x 64 x 40:
     1280 tasks over 512 blocks), against the oracle. The output-gradient halo
     holds nonzero values, which must not enter the sums. A second call gives
-    the same bits (fixed reduction order)."""
+    the same bits (fixed reduction order), also when the 32-channel kernel
+    reads its operands element by element instead of through the
+    transposing LDS reads (MS_WGRAD_TR=0: the same operand values)."""
     nx, ny, nz = shape
     r = synth.rng(13)
     x = cnn.round_bf16(np.maximum(r.standard_normal((cin, nz, ny, nx)), 0.0))
@@ -315,7 +317,8 @@ def test_row_blocked_wgrad(shape, cin, cinp):
     work = torch.empty(ms.lib.conv3d_bf16_wgrad_workspace_bytes(cinp), dtype=torch.uint8,
                        device="cuda")
     res = []
-    for _ in range(2):
+    for tr in ("1", "0"):
+        monkeypatch.setenv("MS_WGRAD_TR", tr)
         dw = torch.zeros(27 * 32 * cinp, dtype=torch.float32, device="cuda")
         db = torch.zeros(32, dtype=torch.float32, device="cuda")
         assert ms.lib.conv3d_bf16_wgrad(nx, ny, nz, cinp, ms._ptr(xin), ms._ptr(gin),
