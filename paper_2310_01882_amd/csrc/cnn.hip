@@ -26,6 +26,8 @@
 
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 namespace ms {
 namespace {
 
@@ -1300,6 +1302,79 @@ __global__ void box_z_kernel(int nx, int ny, int nz, int h, const double* in, Vo
   }
 }
 
+// Box sums through LDS: a block stages the lines it sums along (the x
+// kernel dividing by the scale once per element instead of once per use),
+// then each output adds its window from LDS in increasing offset -- the
+// same additions in the same order as the kernels above, which stay for
+// lines longer than kBoxLds.
+constexpr int kBoxLds = 8192;  // doubles of LDS per block (64 KiB)
+
+// x: T = max(1, 256 / nx) rows of x per round.
+__global__ __launch_bounds__(256) void box_x_lds_kernel(ms_grid g, const double* f,
+                                                        const double* scale, int h,
+                                                        double* out) {
+  extern __shared__ double lds_line[];
+  const int nx = g.nx, T = max(1, 256 / nx);
+  const int64_t nrows = (int64_t)g.ny * g.nz;
+  const double s = *scale;
+  for (int64_t r0 = (int64_t)blockIdx.x * T; r0 < nrows; r0 += (int64_t)gridDim.x * T) {
+    const int rows = (int)min((int64_t)T, nrows - r0);
+    __syncthreads();  // the previous round's reads are done
+    for (int e = threadIdx.x; e < rows * nx; e += blockDim.x) {
+      const int64_t row = r0 + e / nx;
+      const int i = e % nx, j = (int)(row % g.ny), k = (int)(row / g.ny);
+      lds_line[e] = f ? f[(int64_t)(k + 1) * g.sz + (int64_t)(j + 1) * g.sy + (i + 1)] / s : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows * nx; e += blockDim.x) {
+      const int rr = e / nx, i = e % nx;
+      const int lo = max(-h, -i), hi = min(h, nx - 1 - i);
+      double acc = 0.0;
+      if (f)
+        for (int d = lo; d <= hi; ++d) acc = acc + lds_line[rr * nx + i + d];
+      out[(r0 + rr) * nx + i] = acc;
+    }
+  }
+}
+
+// y (kZ false: out) or z (kZ true: the feature channel): tiles of W
+// consecutive x by the whole line, at one position of the third axis.
+template <bool kZ>
+__global__ __launch_bounds__(256) void box_line_lds_kernel(int nx, int ny, int nz, int h, int W,
+                                                           const double* in, double* out, Vol v,
+                                                           int ch, bf16* feat) {
+  extern __shared__ double lds_line[];
+  const int n = kZ ? nz : ny;
+  const int64_t S = kZ ? (int64_t)nx * ny : nx;  // stride along the line
+  const int other = kZ ? ny : nz;
+  const int cx = (nx + W - 1) / W;
+  const int64_t ntiles = (int64_t)cx * other;
+  const double vol = (double)((2 * h + 1) * (2 * h + 1) * (2 * h + 1));
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int x0 = (int)(tile % cx) * W, o = (int)(tile / cx);
+    const int w = min(W, nx - x0);
+    // element (x0, 0, o) for y lines, (x0, o, 0) for z lines
+    const int64_t base = kZ ? (int64_t)o * nx + x0 : (int64_t)o * nx * ny + x0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * W; e += blockDim.x) {
+      const int q = e / W, x = e % W;
+      lds_line[e] = x < w ? in[base + q * S + x] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * W; e += blockDim.x) {
+      const int q = e / W, x = e % W;
+      if (x >= w) continue;
+      const int lo = max(-h, -q), hi = min(h, n - 1 - q);
+      double acc = 0.0;
+      for (int d = lo; d <= hi; ++d) acc = acc + lds_line[(q + d) * W + x];
+      if constexpr (kZ)
+        feat[v.vox(x0 + x, o, q) * 8 + ch] = (bf16)(float)(acc / vol);
+      else
+        out[base + q * S + x] = acc;
+    }
+  }
+}
+
 // guess: x interior = s * lambda * uhat (FP64), halo untouched.
 __global__ void guess_kernel(ms_grid g, const float* uhat, Vol v, const double* scale,
                              double lambda, double* x) {
@@ -1555,15 +1630,39 @@ extern "C" int cnn_features(const ms_grid* g, const double* u, const double* f, 
   MS_LAUNCH_CHECK();
   hipLaunchKernelGGL(feat_write_kernel, dim3(1024), dim3(256), 0, s, *g, u, f, scale, v, fb);
   MS_LAUNCH_CHECK();
+  // LDS forms where a line fits (MS_BOX_LDS=0: the global-memory forms)
+  const char* ev = getenv("MS_BOX_LDS");
+  const bool lds = !(ev && atoi(ev) == 0);
+  const int nx = g->nx, ny = g->ny, nz = g->nz;
+  // tiles of at most 16 x by 2048 doubles: many small blocks, since each
+  // output's sum is a chain of dependent adds and latency wants many waves
+  const int wy = std::max(1, std::min(16, 2048 / ny)), wz = std::max(1, std::min(16, 2048 / nz));
+  const int64_t ty = (int64_t)((nx + wy - 1) / wy) * nz, tz = (int64_t)((nx + wz - 1) / wz) * ny;
   for (int b = 0; b < 5; ++b) {
     const int h = kBoxHalf[b];
-    hipLaunchKernelGGL(box_x_kernel, dim3(2048), dim3(256), 0, s, *g, f, scale, h, t1);
+    if (lds && nx <= kBoxLds) {
+      const size_t bytes = (size_t)std::max(256, nx) * sizeof(double);
+      hipLaunchKernelGGL(box_x_lds_kernel, dim3(2048), dim3(256), bytes, s, *g, f, scale, h, t1);
+    } else {
+      hipLaunchKernelGGL(box_x_kernel, dim3(2048), dim3(256), 0, s, *g, f, scale, h, t1);
+    }
     MS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(box_y_kernel, dim3(2048), dim3(256), 0, s, g->nx, g->ny, g->nz, h, t1,
-                       t2);
+    if (lds && ny <= kBoxLds) {
+      hipLaunchKernelGGL(box_line_lds_kernel<false>, dim3((unsigned)std::min<int64_t>(ty, 2048)),
+                         dim3(256), (size_t)ny * wy * sizeof(double), s, nx, ny, nz, h, wy, t1,
+                         t2, v, 0, fb);
+    } else {
+      hipLaunchKernelGGL(box_y_kernel, dim3(2048), dim3(256), 0, s, nx, ny, nz, h, t1, t2);
+    }
     MS_LAUNCH_CHECK();
-    hipLaunchKernelGGL(box_z_kernel, dim3(2048), dim3(256), 0, s, g->nx, g->ny, g->nz, h, t2, v,
-                       kBoxChannel[b], fb);
+    if (lds && nz <= kBoxLds) {
+      hipLaunchKernelGGL(box_line_lds_kernel<true>, dim3((unsigned)std::min<int64_t>(tz, 2048)),
+                         dim3(256), (size_t)nz * wz * sizeof(double), s, nx, ny, nz, h, wz, t2,
+                         nullptr, v, kBoxChannel[b], fb);
+    } else {
+      hipLaunchKernelGGL(box_z_kernel, dim3(2048), dim3(256), 0, s, nx, ny, nz, h, t2, v,
+                         kBoxChannel[b], fb);
+    }
     MS_LAUNCH_CHECK();
   }
   return MS_OK;

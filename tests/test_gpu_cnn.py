@@ -171,8 +171,16 @@ def test_adam_matches_oracle():
     assert np.array_equal(np.transpose(wdn, (0, 2, 1)), cnn.round_bf16(wt.cpu().numpy()))
 
 
-def test_features_match_oracle():
-    nx, ny, nz = 20, 12, 9
+@pytest.mark.parametrize("lds", ["1", "0"])
+@pytest.mark.parametrize("shape", [(20, 12, 9), (70, 130, 3), (257, 5, 40)])
+def test_features_match_oracle(shape, lds, monkeypatch):
+    """The eight input channels against the oracle, with the box sums staged
+    in LDS (default) and in global-memory form (MS_BOX_LDS=0); extents
+    shorter than the largest half-width, rows past 256 (one row per round)
+    and lines of other lengths per axis."""
+    monkeypatch.setenv("MS_BOX_LDS", lds)
+    nx, ny, nz = shape
+    note(f"case: features {shape} lds={lds}")
     u = synth.dirichlet_uniform(nx, ny, nz, 3)
     f = synth.gaussian_sources(nx, ny, nz, 3, 4)
     net = wsm.WarmStart(nx, ny, nz, seed=1)
