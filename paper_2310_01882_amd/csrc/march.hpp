@@ -112,13 +112,13 @@ __device__ __forceinline__ void two_sweep_march(const T* __restrict__ src, T* __
 
   const bool wave_live = j0 < ny;
   for (int z = z0 - 1; z <= z1 && wave_live; ++z) {
-    // next level's loads first: u_k at z+2, f at z+1
+    // next level's loads first: u_k at z+2, f at z+1. Unconditional (past
+    // the chunk they read clamped levels whose values are never used): a
+    // load under a branch makes the wait after the join count as if the
+    // branch had not been taken, i.e. wait for the loads just issued.
     T un[R + 4], fn[R + 2];
-    const bool more = z + 1 <= z1;
-    if (more) {
-      load_u(un, z + 2);
-      load_f(fn, z + 1);
-    }
+    load_u(un, z + 2);
+    load_f(fn, z + 1);
     // stage A at level z: h on rows j0-1 .. j0+R
     const bool zA = z >= 0 && z < nz, zres = z >= z0 && z < z1;
     T hn[R + 2];
@@ -165,15 +165,13 @@ __device__ __forceinline__ void two_sweep_march(const T* __restrict__ src, T* __
       hm1[q] = hn[q];
       um[q] = uc[q + 1];
     }
-    if (more) {
 #pragma unroll
-      for (int q = 0; q < R + 4; ++q) {
-        uc[q] = up[q];
-        up[q] = un[q];
-      }
-#pragma unroll
-      for (int q = 0; q < R + 2; ++q) fa[q] = fn[q];
+    for (int q = 0; q < R + 4; ++q) {
+      uc[q] = up[q];
+      up[q] = un[q];
     }
+#pragma unroll
+    for (int q = 0; q < R + 2; ++q) fa[q] = fn[q];
   }
 
 }
