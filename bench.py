@@ -226,7 +226,7 @@ def slab_share(n, tdt, f_full, ranks=8, sweeps=200):
     (n x n x n/ranks interior, the same sources cut to the slab), swept alone:
     the kernel time a multi-GPU sweep would overlap its halo exchange with.
     A z-slab's halo is one contiguous plane (plane pitch sz), so no pack or
-    unpack kernel is needed; the exchange itself is not part of this build."""
+    unpack kernel is needed; the exchange itself is not implemented here."""
     import torch
     import paper_2310_01882_amd as ms
     import synth
@@ -1061,8 +1061,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU halo-exchange path is "
-              "a design (no collectives are built), so --gpus must be 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only; the multi-GPU halo-exchange path is a design "
+              "(no collectives are implemented), so --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
