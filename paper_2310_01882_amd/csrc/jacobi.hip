@@ -1048,15 +1048,18 @@ int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 // kTbColumns (one column per lane). Measured: FP64 within 1% of each other
 // at 512^3 and the LDS tiles 15% faster at 128^3 (less padding: 64 x 8
 // tiles against 60 x 20); FP32 16-20% faster with columns at both sizes.
-// Default: LDS tiles for FP64, columns for FP32; MS_TB_VARIANT=0 or 2
-// forces one.
+// Default: LDS tiles for FP64; for FP32 the register march on grids of at
+// most 2^22 cells (128^3: 16.5 against 18.3 us per pass with columns, where
+// a pass is short and latency-bound) and columns above; MS_TB_VARIANT=0, 2
+// or 3 forces one.
 constexpr int kTbLds = 0, kTbColumns = 2, kTbRegisters = 3;
 
 SweepGeom tb2_geom(const ms_grid& g, int dtype, bool rb) {
   SweepGeom s{};
   const char* ev_var = getenv("MS_TB_VARIANT");
+  const bool small = (int64_t)g.nx * g.ny * g.nz <= ((int64_t)1 << 22);
   s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : atoi(ev_var) == 3 ? kTbRegisters : kTbColumns)
-                     : (dtype == MS_F64 ? kTbLds : kTbColumns);
+                     : (dtype == MS_F64 ? kTbLds : (small && !rb ? kTbRegisters : kTbColumns));
   if (rb && s.variant == kTbRegisters) s.variant = kTbLds;  // Jacobi only
   // the register march indexes within a z plane with 32-bit offsets
   if (s.variant == kTbRegisters && g.sz >= INT32_MAX)

@@ -1,7 +1,7 @@
 """Train and evaluate the learned warm start on Jacobi-generated data.
 
     python -m paper_2310_01882_amd.train_warmstart train --n 128 --train 2000 \
-        --epochs 6 --out weights.npz --report train_report.json
+        --epochs 24 --out weights.npz --report train_report.json
     python -m paper_2310_01882_amd.train_warmstart eval --n 128 --eval 200 \
         --weights weights.npz --report eval_report.json
 
@@ -199,7 +199,7 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--train", type=int, default=2000)
     ap.add_argument("--eval", type=int, default=200)
-    ap.add_argument("--epochs", type=int, default=6)
+    ap.add_argument("--epochs", type=int, default=24)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
