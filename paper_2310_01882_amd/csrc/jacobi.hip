@@ -1049,15 +1049,15 @@ int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 // at 512^3 and the LDS tiles 15% faster at 128^3 (less padding: 64 x 8
 // tiles against 60 x 20); FP32 16-20% faster with columns at both sizes.
 // Default: LDS tiles for FP64; for FP32 the register march on grids of at
-// most 2^22 cells (128^3: 16.5 against 18.3 us per pass with columns, where
-// a pass is short and latency-bound) and columns above; MS_TB_VARIANT=0, 2
-// or 3 forces one.
+// most 2^25 cells (128^3: 16.5 against 18.3 us per pass with columns, where
+// a pass is short and latency-bound; 256^3: 76.0 against 80.2) and columns
+// above (512^3: even with 4096 blocks); MS_TB_VARIANT=0, 2 or 3 forces one.
 constexpr int kTbLds = 0, kTbColumns = 2, kTbRegisters = 3;
 
 SweepGeom tb2_geom(const ms_grid& g, int dtype, bool rb) {
   SweepGeom s{};
   const char* ev_var = getenv("MS_TB_VARIANT");
-  const bool small = (int64_t)g.nx * g.ny * g.nz <= ((int64_t)1 << 22);
+  const bool small = (int64_t)g.nx * g.ny * g.nz <= ((int64_t)1 << 25);
   s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : atoi(ev_var) == 3 ? kTbRegisters : kTbColumns)
                      : (dtype == MS_F64 ? kTbLds : (small && !rb ? kTbRegisters : kTbColumns));
   if (rb && s.variant == kTbRegisters) s.variant = kTbLds;  // Jacobi only
