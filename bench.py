@@ -185,7 +185,7 @@ def bench_jacobi(args, dtype_name="f64"):
             "note": "two sweeps per pass over memory: 12 B/LUP (FP64) algorithmic",
         },
         "red_black_gauss_seidel": {
-            "kernel": "sweep_tb2_kernel<%s, true, true>" % ("double" if dtype_name == "f64"
+            "kernel": "sweep_tbw_kernel<%s, true, true>" % ("double" if dtype_name == "f64"
                                                            else "float"),
             "glups": round(cells * sweeps * args.steps / gs_secs / 1e9, 3),
             "ms_per_step": round(gs_secs / args.steps * 1e3, 4),

@@ -708,9 +708,12 @@ __global__ __launch_bounds__(kThreads) void sweep_tb2_kernel(SweepK<T> a) {
 // tile), one level behind stage A. f is loaded once per cell and kept for
 // stage B. The per-cell arithmetic is the single sweep's, so the results
 // are bit-identical to the other kernels.
+// Blocks of 8 waves: region 64 x 24, output tile 60 x 20. (16-wave blocks,
+// 60 x 44 output tiles with fewer re-read halo rows, measured 3-9% slower:
+// the per-level barrier then waits on twice as many waves.)
 constexpr int kTwWaves = 8, kTwRows = 3;  // 121 VGPRs (FP64): four waves per SIMD
 constexpr int kTwThreads = 64 * kTwWaves;
-constexpr int kTwRegionY = kTwWaves * kTwRows;  // 32 rows
+constexpr int kTwRegionY = kTwWaves * kTwRows;  // 24 rows
 constexpr int kTwTileX = 60, kTwTileY = kTwRegionY - 4;
 
 template <typename T, bool HAS_F, bool RB>
@@ -1044,22 +1047,28 @@ int launch_residual(const ms_grid& g, int dtype, const void* u, const void* f,
 
 int residual_blocks(const ms_grid& g) { return sweep_geom_lds(g).nblocks; }
 
-// Variants of the two-stage pass: kTbLds (LDS-staged 64 x 8 tiles) and
-// kTbColumns (one column per lane). Measured: FP64 within 1% of each other
-// at 512^3 and the LDS tiles 15% faster at 128^3 (less padding: 64 x 8
-// tiles against 60 x 20); FP32 16-20% faster with columns at both sizes.
-// Default: LDS tiles for FP64; for FP32 the register march on grids of at
-// most 2^25 cells (128^3: 16.5 against 18.3 us per pass with columns, where
-// a pass is short and latency-bound; 256^3: 76.0 against 80.2) and columns
-// above (512^3: even with 4096 blocks); MS_TB_VARIANT=0, 2 or 3 forces one.
+// Variants of the two-stage pass: kTbLds (LDS-staged 64 x 8 tiles),
+// kTbColumns (one column per lane) and kTbRegisters (one wave per tile, no
+// barrier). Measured kernel times per pass, FP64: 512^3 columns 776 us,
+// LDS 825, registers 810 (red-black: columns 772, LDS 827); 256^3 columns
+// 106.5, LDS 118.7, registers 117.3; 128^3 LDS 15% faster than columns
+// (less padding: 64 x 8 tiles against 60 x 20). FP32: 128^3 registers 16.5
+// against 18.3 with columns (a pass is short and latency-bound), 256^3 76.0
+// against 80.2, 512^3 even.
+// Default: FP64 LDS tiles up to 2^22 cells and columns above; FP32 the
+// register march up to 2^25 cells and columns above (red-black sweeps have
+// no register form and take columns for FP32, the FP64 rule otherwise);
+// MS_TB_VARIANT=0, 2 or 3 forces one.
 constexpr int kTbLds = 0, kTbColumns = 2, kTbRegisters = 3;
 
 SweepGeom tb2_geom(const ms_grid& g, int dtype, bool rb) {
   SweepGeom s{};
   const char* ev_var = getenv("MS_TB_VARIANT");
-  const bool small = (int64_t)g.nx * g.ny * g.nz <= ((int64_t)1 << 25);
+  const int64_t cells = (int64_t)g.nx * g.ny * g.nz;
+  const int def = dtype == MS_F64 ? (cells <= ((int64_t)1 << 22) ? kTbLds : kTbColumns)
+                                  : (cells <= ((int64_t)1 << 25) && !rb ? kTbRegisters : kTbColumns);
   s.variant = ev_var ? (atoi(ev_var) == 0 ? kTbLds : atoi(ev_var) == 3 ? kTbRegisters : kTbColumns)
-                     : (dtype == MS_F64 ? kTbLds : (small && !rb ? kTbRegisters : kTbColumns));
+                     : def;
   if (rb && s.variant == kTbRegisters) s.variant = kTbLds;  // Jacobi only
   // the register march indexes within a z plane with 32-bit offsets
   if (s.variant == kTbRegisters && g.sz >= INT32_MAX)

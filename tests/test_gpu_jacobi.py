@@ -178,7 +178,8 @@ TB_VARIANTS = {"columns": "2", "lds": "0", "registers": "3"}
 @pytest.mark.parametrize("variant", list(TB_VARIANTS))
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("dims", [(64, 8, 9), (130, 37, 11), (5, 3, 2), (1, 1, 1), (65, 17, 40),
-                                  (200, 9, 3), (61, 21, 10), (121, 41, 17)])
+                                  (200, 9, 3), (61, 21, 10), (121, 41, 17),
+                                  (70, 95, 6)])
 def test_temporal_blocking_is_bit_identical_to_plain_sweeps(dims, dtype, variant, monkeypatch):
     """Two sweeps fused per pass, in both kernel layouts: the same fields and
     norms as the oracle's plain sweeps, for even and odd sweep counts."""

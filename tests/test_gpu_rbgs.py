@@ -44,7 +44,8 @@ TB_VARIANTS = {"columns": "2", "lds": "0", "registers": "3"}
 
 @pytest.mark.parametrize("variant", list(TB_VARIANTS))
 @pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 4), (64, 8, 8), (65, 17, 9), (130, 9, 20),
-                                  (63, 15, 7), (200, 3, 70), (3, 2, 41), (61, 21, 10)])
+                                  (63, 15, 7), (200, 3, 70), (3, 2, 41), (61, 21, 10),
+                                  (61, 90, 9)])
 @pytest.mark.parametrize("with_f", [True, False])
 def test_sweeps_bit_exact_on_ragged_grids(dims, with_f, variant, monkeypatch):
     monkeypatch.setenv("MS_TB_VARIANT", TB_VARIANTS[variant])
