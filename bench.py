@@ -870,7 +870,14 @@ def bench_batched(args):
     best_w = min(stream_s, key=stream_s.get)
     # per-team finish times (device clock): the batch ends with its slowest team
     fin = np.array([i.seconds for i in infos])
-    teams, grid_blocks, planned = ms.batched_plan(xs, fs, with_estimates=True, **opts)
+    teams, grid_blocks, planned, groups = ms.batched_plan(xs, fs, with_estimates=True,
+                                                          with_groups=True, **opts)
+    # a team runs its chain of instances one after the other: it is busy
+    # until its last instance finishes
+    team_end, team_size = {}, {}
+    for e, t, k in zip(fin, teams, groups):
+        team_end[k] = max(team_end.get(k, 0.0), float(e))
+        team_size[k] = t
     order = np.argsort(-fin)
     for i in order[:4]:
         log(f"[bench]   slowest: instance {i} dims {dims[i]} team {teams[i]} sweeps "
@@ -955,18 +962,21 @@ def bench_batched(args):
                   "seconds_one_by_one": seq, "total_inner_sweeps": int(sweeps.sum()),
                   "max_sweeps": int(sweeps.max()), "outer_max": int(outer.max()),
                   "worst_rel_final": max(i.rel_final for i in infos),
-                  "grid_blocks": grid_blocks,
-                  "team_finish_seconds": {"min": round(float(fin.min()), 3),
-                                          "median": round(float(np.median(fin)), 3),
-                                          "max": round(float(fin.max()), 3)},
-                  "block_seconds_busy_fraction": round(float(
-                      (fin * np.array(teams)).sum() / (fin.max() * grid_blocks)), 3),
-                  "instances": [{"dims": list(d), "team": t, "shape": [b["tx"], b["zsplit"]],
+                  "grid_blocks": grid_blocks, "teams": len(team_size),
+                  "team_finish_seconds": {"min": round(min(team_end.values()), 3),
+                                          "median": round(float(np.median(
+                                              list(team_end.values()))), 3),
+                                          "max": round(max(team_end.values()), 3)},
+                  "block_seconds_busy_fraction": round(
+                      sum(team_end[k] * team_size[k] for k in team_end) /
+                      (max(team_end.values()) * grid_blocks), 3),
+                  "instances": [{"dims": list(d), "team": t, "group": k,
+                                 "shape": [b["tx"], b["zsplit"]],
                                  "sweeps": i.sweeps, "est_sweeps": round(pe),
                                  "est_sweeps_slowest_mode_bound": round(est_sweeps(d)),
                                  "finish_s": round(float(e), 3)}
-                                for d, t, b, i, e, pe in zip(dims, teams, best, infos, fin,
-                                                             planned)],
+                                for d, t, k, b, i, e, pe in zip(dims, teams, groups, best,
+                                                                infos, fin, planned)],
                   "plan_estimate_error": {
                       "mean_abs": round(float(np.mean([abs(pe / i.sweeps - 1)
                                                        for pe, i in zip(planned, infos)])), 4),

@@ -358,21 +358,23 @@ void ms_tuning_clear(void);
 /* ---- batched solves ---------------------------------------------------------
  * Many independent instances of jacobi_solve, each with its own grid,
  * solved in ONE persistent kernel launch (captured in a hipGraph). The
- * device's resident blocks are split into teams, one per instance, so that
- * the longest estimated finish time is as short as possible (estimate:
- * cells x Jacobi sweeps to rel_tol, from the spectral radius and the
- * reference residual's component along the slowest mode (one device pass
- * before planning; see jacobi_batched_plan), split over the team, plus a
- * per-sweep barrier cost for teams of more than one block); a
- * team runs its instance's whole solve with team barriers and never waits
- * for another team. precision: MS_SOLVE_F64 or
+ * device's resident blocks are split into teams, and each team runs a
+ * chain of instances one after the other (a large instance alone, small
+ * ones several in turn), so that the longest estimated chain time is as
+ * short as possible (an instance's estimate: cells x Jacobi sweeps to
+ * rel_tol, from the spectral radius and the reference residual's component
+ * along the slowest mode (one device pass before planning; see
+ * jacobi_batched_plan), split over the team, plus a per-sweep barrier cost
+ * for teams of more than one block); a team runs each instance's whole
+ * solve with team barriers and never waits for another team. Any number of
+ * instances (n >= 1). precision: MS_SOLVE_F64 or
  * MS_SOLVE_F32_REFINED with the refinement rules of jacobi_solve (same
  * per-cell arithmetic, same stopping rules; norms are summed per team, so an
  * iteration count may differ from jacobi_solve's by one only when a norm
  * sits within rounding of its threshold). method must be MS_METHOD_JACOBI
  * (else MS_EUNSUPPORTED). Options used: rel_tol,
  * max_sweeps, precision, inner_eta, max_outer, max_inner, stall_window
- * (<= 1024). Instances must not overlap; n <= resident blocks of the device.
+ * (<= 1024). Instances must not overlap.
  * res: host array of n results. Blocks until done. Returns MS_OK,
  * MS_NOT_CONVERGED or MS_ENONFINITE (worst over instances), or an error;
  * MS_EHIP if a team barrier exceeds its time limit (20 s). */
@@ -387,8 +389,13 @@ size_t jacobi_batched_workspace_bytes(int n, const ms_instance* inst,
 int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
                          void* work, size_t work_bytes, ms_solve_result* res,
                          void* stream);
-/* The team sizes (n ints), the grid size and the per-instance sweep
- * estimates (n doubles) the batched solve would use; any output may be NULL.
+/* The plan the batched solve would use; any output may be NULL. team_sizes
+ * (n ints): the size of the team that runs each instance; groups (n ints):
+ * the index of that team (instances of one team run one after the other,
+ * in increasing order of their position in the team's chain, longest
+ * estimate first); grid_blocks: the blocks of the launch (the sum of the
+ * team sizes over distinct teams); est_sweeps (n doubles): the
+ * per-instance sweep estimates.
  * The estimates come from one device pass over the instances (the same
  * probe the solve runs): ||r(u^0)|| and the component c1 of r(u^0) along
  * the slowest Jacobi mode give about ln(tol ||r(u^0)|| / c1) / ln(rho)
@@ -397,8 +404,31 @@ int jacobi_solve_batched(int n, const ms_instance* inst, const ms_solve_opts* o,
  * jacobi_batched_plan_workspace_bytes(n) bytes. Synchronises `stream`. */
 size_t jacobi_batched_plan_workspace_bytes(int n);
 int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
-                        int* team_sizes, int* grid_blocks, double* est_sweeps,
+                        int* team_sizes, int* groups, int* grid_blocks, double* est_sweeps,
                         void* work, size_t work_bytes, void* stream);
+
+/* The planner alone, on the host (no device work): teams and chains for n
+ * grids with the given sweep estimates (each finite, >= 1) on `blocks`
+ * resident blocks, for `precision` (MS_SOLVE_F64 or MS_SOLVE_F32_REFINED),
+ * with the outputs of jacobi_batched_plan. Estimated time of an instance of
+ * extents nx x ny x nz and S sweeps on a team of t blocks: with one sweep
+ * per team barrier (MS_SOLVE_F64, or MS_BATCH_TB=1), C S / t for C cells,
+ * plus 8192 S when t > 1; with two sweeps per barrier (MS_SOLVE_F32_REFINED
+ * by default), S / 2 x (R x (nz / p + 2) + 15 [t > 1]), where p in {1, 2, 4,
+ * 8, 16} (at most nz; the fewest on a tie) minimises R x (nz / p + 2) and R
+ * = ceil(ceil(nx / 60) ceil(ny / 4) p / (16 t)) is the number of rounds in
+ * which the team's 16 t waves take the 60 x 4 x nz / p tiles. For a target
+ * makespan M each instance takes the
+ * smallest team (at most min(blocks, 8 x its 64 x 16 tiles)) whose time is
+ * at most M; instances wanting the same team size go into chains of total
+ * time at most M (longest first, first chain with room); the smallest M
+ * that fits is found by bisection from the makespan of one team per
+ * instance (or, with more instances than blocks, of one block running them
+ * all), and left-over blocks then go to the longest chain that some of
+ * them shorten, the fewest blocks that do, until none does. */
+int jacobi_batched_plan_from_estimates(int n, const ms_grid* grids, const double* est_sweeps,
+                                       int blocks, int precision, int* team_sizes,
+                                       int* groups, int* grid_blocks);
 
 /* ---- batched solves on concurrent streams -----------------------------------
  * The same batch as jacobi_solve_batched, run instead by `workers` (1..64)

@@ -133,9 +133,14 @@ SIGNATURES = {
                                                      ctypes.POINTER(SolveOpts), _I]),
     "jacobi_solve_batched_streams": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
                                           _I, _P, _SZ, ctypes.POINTER(SolveResult), _P]),
+    "jacobi_batched_plan_from_estimates": (_I, [_I, ctypes.POINTER(Grid), ctypes.POINTER(_D),
+                                                _I, _I, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]),
     "jacobi_batched_plan": (_I, [_I, ctypes.POINTER(Instance), ctypes.POINTER(SolveOpts),
                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                 ctypes.POINTER(_D), _P, _SZ, _P]),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_D), _P, _SZ,
+                                 _P]),
     "ms_autotune_sweeps": (_I, [ctypes.POINTER(Grid), _I, _P, _P, _P, _I, _P, _SZ,
                                 ctypes.POINTER(Tuning), _P]),
     "ms_sweep_shape": (_I, [ctypes.POINTER(Grid), _I, ctypes.POINTER(ctypes.c_void_p), _I,
@@ -548,21 +553,43 @@ def jacobi_solve_batched_streams(xs, fs, workers=4, work=None, stream=None, **op
                       r.seconds) for r in res]
 
 
-def batched_plan(xs, fs, stream=None, with_estimates=False, **opts):
-    """(team sizes, grid blocks) the batched solve would use, and with
-    ``with_estimates`` the per-instance sweep estimates it plans with (from
-    one device pass over the instances)."""
+def batched_plan_from_estimates(dims, est_sweeps, blocks, precision=MS_SOLVE_F32_REFINED):
+    """The batched planner alone, on the host: (team sizes, groups, grid
+    blocks) for instances of interior extents ``dims`` ((nx, ny, nz) each)
+    with the given sweep estimates on ``blocks`` resident blocks."""
+    n = len(dims)
+    grids = (Grid * n)(*[Grid(nx, ny, nz, 0, nx + 2, (nx + 2) * (ny + 2)) for nx, ny, nz in dims])
+    est = (_D * n)(*[float(e) for e in est_sweeps])
+    teams = (ctypes.c_int * n)()
+    groups = (ctypes.c_int * n)()
+    g = ctypes.c_int(0)
+    _check(lib.jacobi_batched_plan_from_estimates(n, grids, est, int(blocks), int(precision),
+                                                  teams, groups, ctypes.byref(g)))
+    return list(teams), list(groups), g.value
+
+
+def batched_plan(xs, fs, stream=None, with_estimates=False, with_groups=False, **opts):
+    """(team sizes, grid blocks) the batched solve would use; with
+    ``with_estimates`` also the per-instance sweep estimates it plans with
+    (from one device pass over the instances), and with ``with_groups`` the
+    index of the team that runs each instance (a team runs its instances one
+    after the other)."""
     arr = _instances(xs, fs)
     o = solve_opts(**opts)
     teams = (ctypes.c_int * len(xs))()
+    groups = (ctypes.c_int * len(xs))()
     est = (_D * len(xs))()
     g = ctypes.c_int(0)
     work = _workspace(lib.jacobi_batched_plan_workspace_bytes(len(xs)), xs[0].device)
-    _check(lib.jacobi_batched_plan(len(xs), arr, ctypes.byref(o), teams, ctypes.byref(g), est,
-                                   _ptr(work), work.numel(), _stream(stream)))
+    _check(lib.jacobi_batched_plan(len(xs), arr, ctypes.byref(o), teams, groups,
+                                   ctypes.byref(g), est, _ptr(work), work.numel(),
+                                   _stream(stream)))
+    out = [list(teams), g.value]
     if with_estimates:
-        return list(teams), g.value, list(est)
-    return list(teams), g.value
+        out.append(list(est))
+    if with_groups:
+        out.append(list(groups))
+    return tuple(out)
 
 
 def jacobi_solve_batched(xs, fs, work=None, stream=None, **opts):

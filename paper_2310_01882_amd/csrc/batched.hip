@@ -2,15 +2,17 @@
 // persistent launch.
 //
 // The grid holds G blocks, no more than can be resident at once. Blocks are
-// split into teams, one per instance, balancing the instances' estimated
-// finish times (cells x Jacobi sweeps to the tolerance, from the spectral
+// split into teams, and each team runs a chain of instances, one after the
+// other (a big instance alone, several small ones in turn), so that the
+// longest estimated chain time is as short as possible (an instance's
+// estimate: cells x Jacobi sweeps to the tolerance, from the spectral
 // radius and a device probe of the reference residual's slowest-mode
-// component, over the team size, plus a barrier cost per sweep), and placed
-// XCD by XCD so that a team shares an L2 where it can. A team
-// runs its instance's whole solve -- FP64 Jacobi, or FP32-storage Jacobi
-// inside FP64 iterative refinement -- with team barriers (a counter and a
-// generation word in device memory) between dependent steps; it never waits
-// for another team. Every block of a team sums the team's per-block partial
+// component, over the team size, plus a barrier cost per sweep). Teams are
+// placed XCD by XCD so that a team shares an L2 where it can. For each
+// instance of its chain a team runs the whole solve -- FP64 Jacobi, or
+// FP32-storage Jacobi inside FP64 iterative refinement -- with team barriers
+// (a counter and a generation word in device memory, one pair per
+// instance) between dependent steps; it never waits for another team. Every block of a team sums the team's per-block partial
 // norms in the same fixed order, so all of them take the same decisions
 // without a broadcast. Waits are bounded: a barrier that does not complete
 // within a time limit raises the batch's error flag and every block leaves.
@@ -91,8 +93,10 @@ struct Inst {
 
 struct BatchK {
   Inst* inst;
-  const int* block_team;  // per block: instance index
+  const int* block_off;   // per block: first entry of its team's chain in `chain`
+  const int* block_len;   // per block: length of that chain
   const int* block_rank;  // per block: rank inside its team
+  const int* chain;       // instance indices, chain after chain
   int* error;             // batch-wide error flag
   int ninst;
   int mode;  // MS_SOLVE_F64 or MS_SOLVE_F32_REFINED
@@ -427,22 +431,15 @@ __device__ int64_t team_jacobi_pairs(const BatchK& a, Inst& q, int rank, float* 
   }
 }
 
-// At most 128 VGPRs: four waves per SIMD (four resident blocks per CU).
-// PAIRS: the FP32 inner solves take two sweeps per team barrier
-// (team_jacobi_pairs); a separate instantiation, so that its register
-// demand does not weigh on the one-sweep kernel.
+// One instance's whole solve on its team; false if the batch failed (a
+// barrier's time limit or another team's error), and the block then leaves.
 template <bool PAIRS>
-__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
-void batched_kernel(BatchK a) {
-  __shared__ double red[kBatchWaves];
-  __shared__ double cell;
-  __shared__ double hist[kStallMax + 1];
-  __shared__ int s_flag;
-  __shared__ unsigned s_epoch;  // barriers passed (thread 0 only)
-  if (threadIdx.x == 0) s_epoch = 0;
-  const int qi = a.block_team[blockIdx.x];
-  const int rank = a.block_rank[blockIdx.x];
-  Inst& q = a.inst[qi];
+__device__ bool solve_instance(const BatchK& a, Inst& q, int rank, double* red, double* cellp,
+                               double* hist, int* sflag, unsigned* sepoch) {
+  double& cell = *cellp;
+  int& s_flag = *sflag;
+  unsigned& s_epoch = *sepoch;
+  if (threadIdx.x == 0) s_epoch = 0;  // the instance's barrier words start at zero
   const double ncells = (double)q.nx * q.ny * q.nz;
   int status = MS_OK;
   if (rank == 0 && threadIdx.x == 0) q.t_start = (int64_t)__builtin_amdgcn_s_memrealtime();
@@ -456,15 +453,15 @@ void batched_kernel(BatchK a) {
       zero_span<float>(q, rank, q.e0);
       zero_span<float>(q, rank, q.e1);
     }
-    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;
   }
   const double res0 = bcast(sqrt(team_sum(q, 0, red)), &cell);
-  if (!team_barrier(a, q, &s_flag, &s_epoch)) return;  // partial slot 0 is reused below
+  if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;  // partial slot 0 is reused below
 
   if (a.mode == MS_SOLVE_F64) {
     int64_t K = team_jacobi<double>(a, q, rank, q.x, q.xb, q.f, a.tol, res0, false,
                                     a.max_sweeps, red, &cell, hist, &s_flag, &s_epoch, &status);
-    if (K < 0) return;
+    if (K < 0) return false;
     // the answer is buffer K % 2; bring it into x
     if (K & 1) {
       const int ntiles = num_tiles(q);
@@ -485,7 +482,7 @@ void batched_kernel(BatchK a) {
       q.status = status;
       q.t_end = (int64_t)__builtin_amdgcn_s_memrealtime();
     }
-    return;
+    return true;
   }
 
   int64_t total = 0;
@@ -494,10 +491,10 @@ void batched_kernel(BatchK a) {
   for (;;) {
     const double mine = block_sum(residual_tiles(q, rank, false, nullptr, 0.0), red);
     if (threadIdx.x == 0) q.part[rank] = mine;
-    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;
     nr = bcast(sqrt(team_sum(q, 0, red)), &cell);
     rel = res0 > 0.0 ? nr / res0 : 0.0;
-    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;  // slot 0 is rewritten below
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;  // slot 0 is rewritten below
     if (!isfinite(nr)) {
       status = MS_ENONFINITE;
       break;
@@ -509,7 +506,7 @@ void batched_kernel(BatchK a) {
     }
     const double sc = pow2_scale_dev(nr, ncells);
     residual_tiles(q, rank, false, q.rhat, 1.0 / sc);
-    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;
     const double eta = fmax(a.eta, 0.5 * a.tol / rel);
     int64_t cap = a.max_inner;
     if (a.max_sweeps - total < cap) cap = a.max_sweeps - total;
@@ -524,13 +521,13 @@ void batched_kernel(BatchK a) {
                              hist, &s_flag, &s_epoch, &inner_status);
       ans = (K & 1) ? q.e1 : q.e0;
     }
-    if (K < 0) return;
+    if (K < 0) return false;
     if (inner_status == MS_ENONFINITE) {
       status = MS_ENONFINITE;
       break;
     }
     update_tiles(q, rank, ans, sc);
-    if (!team_barrier(a, q, &s_flag, &s_epoch)) return;
+    if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;
     total += K;
     ++outer;
   }
@@ -543,11 +540,34 @@ void batched_kernel(BatchK a) {
     q.status = status;
     q.t_end = (int64_t)__builtin_amdgcn_s_memrealtime();
   }
+  return true;
 }
 
-// Autotuning trial: every team runs `nsweeps` sweeps of its instance with
-// the real loop's per-sweep norm and team barrier, on scratch buffers, and
-// its rank-0 block records the elapsed real-time clock ticks.
+// At most 128 VGPRs: four waves per SIMD (four resident blocks per CU).
+// PAIRS: the FP32 inner solves take two sweeps per team barrier
+// (team_jacobi_pairs); a separate instantiation, so that its register
+// demand does not weigh on the one-sweep kernel. A block runs its team's
+// chain in order.
+template <bool PAIRS>
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void batched_kernel(BatchK a) {
+  __shared__ double red[kBatchWaves];
+  __shared__ double cell;
+  __shared__ double hist[kStallMax + 1];
+  __shared__ int s_flag;
+  __shared__ unsigned s_epoch;  // barriers passed in the current instance (thread 0 only)
+  const int off = a.block_off[blockIdx.x], len = a.block_len[blockIdx.x];
+  const int rank = a.block_rank[blockIdx.x];
+  for (int c = 0; c < len; ++c)
+    if (!solve_instance<PAIRS>(a, a.inst[a.chain[off + c]], rank, red, &cell, hist, &s_flag,
+                               &s_epoch))
+      return;
+}
+
+// Autotuning trial: every team runs `nsweeps` sweeps of each instance of
+// its chain with the real loop's per-sweep norm and team barrier, on
+// scratch buffers, and its rank-0 block records the elapsed real-time clock
+// ticks.
 template <typename T>
 __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
                           int nsweeps, double* red, int* s_flag, unsigned* epoch) {
@@ -573,21 +593,27 @@ void batched_tune_kernel(BatchK a, int nsweeps) {
   __shared__ double red[kBatchWaves];
   __shared__ int s_flag;
   __shared__ unsigned s_epoch;
-  if (threadIdx.x == 0) s_epoch = 0;
-  Inst& q = a.inst[a.block_team[blockIdx.x]];
+  const int off = a.block_off[blockIdx.x], len = a.block_len[blockIdx.x];
   const int rank = a.block_rank[blockIdx.x];
-  if (a.mode == MS_SOLVE_F64)
-    tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag, &s_epoch);
-  else
-    tune_team<float>(a, q, rank, q.e0, q.e1, q.rhat, nsweeps, red, &s_flag, &s_epoch);
+  for (int c = 0; c < len; ++c) {
+    Inst& q = a.inst[a.chain[off + c]];
+    if (threadIdx.x == 0) s_epoch = 0;
+    if (a.mode == MS_SOLVE_F64)
+      tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag, &s_epoch);
+    else
+      tune_team<float>(a, q, rank, q.e0, q.e1, q.rhat, nsweeps, red, &s_flag, &s_epoch);
+  }
 }
 
 // ------------------------------------------------------------------ host
 
 struct Plan {
   int G = 0;
-  std::vector<int> team, first, block_team, block_rank;
-  size_t bytes = 0;
+  std::vector<int> team;   // per instance: the size of the team that runs it
+  std::vector<int> group;  // per instance: index of that team
+  std::vector<int> first;  // per instance: the team's first block in team order
+  std::vector<int> chain;  // instance indices, team after team, each team's in run order
+  std::vector<int> block_off, block_len, block_rank;  // per block
 };
 
 // Estimated Jacobi sweeps to the tolerance. The slowest mode
@@ -698,10 +724,11 @@ int batch_estimates(int n, const ms_instance* inst, double tol, char* area, hipS
   return MS_OK;
 }
 
-// Estimated solve time on a team of t blocks, in units of one block's time
-// per cell update: the sweeps split over the team, plus one team barrier per
-// sweep when t > 1, worth kBarrierCells cell updates (measured: about 5 us
-// against about 1.3e9 FP32 updates per second for one block).
+// Estimated solve time on a team of t blocks with one sweep per team
+// barrier, in units of one block's time per cell update: the sweeps split
+// over the team, plus one team barrier per sweep when t > 1, worth
+// kBarrierCells cell updates (measured: about 5 us against about 1.3e9 FP32
+// updates per second for one block).
 constexpr double kBarrierCells = 8192.0;
 double est_time(double cells, double sweeps, int t) {
   return cells * sweeps / t + (t > 1 ? sweeps * kBarrierCells : 0.0);
@@ -746,6 +773,38 @@ int pair_zs(int nx, int ny, int nz, int team) {
   return best;
 }
 
+// Estimated solve time on a team of t blocks with two sweeps per team
+// barrier, in units of one wave's time per tile level: per pass, the rounds
+// of wave tiles (each of the team's 16 t waves takes one 60 x 4 tile of one
+// of the pzs z chunks per round) times the levels a tile marches
+// (nz / pzs + 2), plus kPairBarrierLevels per team barrier when t > 1.
+// Fitted on the finish times of the 64 teams of a measured batch (a tile
+// level about 2.7 us, a barrier about 41 us): within 8% for most teams,
+// where cells / t alone is off by up to 36% (it sees neither the lanes a
+// narrow instance leaves idle nor the last, partial round).
+constexpr double kPairBarrierLevels = 15.0;
+double pair_time(const ms_grid& g, double sweeps, int t) {
+  const int zs = pair_zs(g.nx, g.ny, g.nz, t);
+  const int64_t t2 = (int64_t)((g.nx + kPairCols - 1) / kPairCols) *
+                     ((g.ny + kPairRows - 1) / kPairRows);
+  const int64_t waves = (int64_t)t * kBatchWaves;
+  const int64_t rounds = (t2 * zs + waves - 1) / waves;
+  return 0.5 * sweeps *
+         ((double)rounds * ((double)g.nz / zs + 2.0) + (t > 1 ? kPairBarrierLevels : 0.0));
+}
+
+// Whether the FP32 inner solves take two sweeps per team barrier: the
+// default for MS_SOLVE_F32_REFINED (MS_BATCH_TB=1 keeps one sweep per
+// barrier), when every z plane indexes with 32-bit offsets.
+bool two_sweep_inner(int n, const ms_instance* inst, int precision) {
+  if (precision != MS_SOLVE_F32_REFINED) return false;
+  const char* ev = getenv("MS_BATCH_TB");
+  if (ev && atoi(ev) == 1) return false;
+  for (int i = 0; i < n; ++i)
+    if (inst[i].grid.sz >= INT32_MAX) return false;
+  return true;
+}
+
 // Tuned shapes, keyed by (precision, nx, ny, nz, team size).
 using ShapeKey = std::tuple<int, int, int, int, int>;
 struct ShapeRec {
@@ -777,35 +836,115 @@ ShapeRec lookup_shape(int prec, const ms_grid& g, int team) {
 // the per-team tables, so a workspace does not depend on the plan).
 int team_cap(const ms_grid& g, int G) { return std::min(G, tiles_of(g) * kShapeZS[3]); }
 
-// Splits up to G blocks into teams, one block at a time to the instance
-// whose estimated finish time (est_time) is the longest and would shrink
-// with one more block -- greedy makespan balancing; every team has at least
-// one block and at most one per default tile split into the most z chunks.
-// Then lays the teams out XCD by XCD.
+// Teams and chains. For a target makespan M every instance takes the
+// smallest team whose estimated time (est_time) is at most M; instances
+// wanting the same team size are packed into chains of total estimate at
+// most M, longest first, each into the first chain with room. The smallest
+// M whose teams fit in G blocks is found by bisection, starting from the
+// makespan of one team per instance (blocks handed out one at a time to
+// the instance whose estimate is the longest and would shrink: a plan the
+// packing can only improve on) or, with more instances than blocks, of one
+// block running them all. Blocks left over then go one at a time to the
+// team with the longest chain estimate that one more block would shorten.
+// No team is larger than one block per default tile split into the most z
+// chunks. Teams are laid out XCD by XCD, largest first.
 void plan_teams(int n, const ms_instance* inst, const std::vector<double>& sweeps, int G,
-                Plan& P) {
-  std::vector<double> cells(n);
+                bool pairs, Plan& P) {
+  std::vector<int> cap(n);
+  std::vector<std::vector<double>> cost(n);  // cost[i][t - 1]: estimate on t blocks
   for (int i = 0; i < n; ++i) {
     const ms_grid& g = inst[i].grid;
-    cells[i] = (double)g.nx * g.ny * g.nz;
+    cap[i] = std::max(1, std::min(G, tiles_of(g) * kShapeZS[3]));
+    const double cells = (double)g.nx * g.ny * g.nz;
+    cost[i].resize(cap[i]);
+    for (int t = 1; t <= cap[i]; ++t)
+      cost[i][t - 1] = pairs ? pair_time(g, sweeps[i], t) : est_time(cells, sweeps[i], t);
   }
-  P.team.assign(n, 1);
-  int used = n;
-  while (used < G) {
-    int best = -1;
-    double bt = 0.0;
+  auto est = [&](int i, int t) { return cost[i][t - 1]; };
+  struct Team {
+    int t;
+    double load;
+    std::vector<int> inst;
+  };
+  // teams for makespan M (false if an instance cannot meet it); blocks in *need
+  auto pack = [&](double M, std::vector<Team>* out, int64_t* need) {
+    std::map<int, std::vector<int>> by;  // team size -> instances
     for (int i = 0; i < n; ++i) {
-      if (P.team[i] >= tiles_of(inst[i].grid) * kShapeZS[3]) continue;
-      const double cur = est_time(cells[i], sweeps[i], P.team[i]);
-      if (est_time(cells[i], sweeps[i], P.team[i] + 1) >= cur) continue;
-      if (best < 0 || cur > bt) {
-        best = i;
-        bt = cur;
+      int t = 1;
+      while (t <= cap[i] && est(i, t) > M) ++t;
+      if (t > cap[i]) return false;
+      by[t].push_back(i);
+    }
+    *need = 0;
+    for (auto& kv : by) {
+      const int t = kv.first;
+      std::vector<int>& v = kv.second;
+      std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return est(x, t) > est(y, t); });
+      std::vector<Team> bins;
+      for (int i : v) {
+        size_t b = 0;
+        while (b < bins.size() && bins[b].load + est(i, t) > M) ++b;
+        if (b == bins.size()) bins.push_back(Team{t, 0.0, {}});
+        bins[b].load += est(i, t);
+        bins[b].inst.push_back(i);
+      }
+      *need += (int64_t)bins.size() * t;
+      if (out) out->insert(out->end(), bins.begin(), bins.end());
+    }
+    return true;
+  };
+  double hi = 0.0;
+  if (n <= G) {
+    std::vector<int> team(n, 1);
+    for (int used = n; used < G; ++used) {
+      int best = -1;
+      for (int i = 0; i < n; ++i) {
+        if (team[i] >= cap[i] || est(i, team[i] + 1) >= est(i, team[i])) continue;
+        if (best < 0 || est(i, team[i]) > est(best, team[best])) best = i;
+      }
+      if (best < 0) break;
+      ++team[best];
+    }
+    for (int i = 0; i < n; ++i) hi = std::max(hi, est(i, team[i]));
+  } else {
+    for (int i = 0; i < n; ++i) hi += est(i, 1);
+  }
+  double lo = 0.0;
+  int64_t need = 0;
+  for (int it = 0; it < 60 && hi - lo > 1e-9 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (pack(mid, nullptr, &need) && need <= G) hi = mid;
+    else lo = mid;
+  }
+  std::vector<Team> teams;
+  pack(hi, &teams, &need);
+  int used = (int)need;
+  while (used < G) {
+    // the longest team that some of the remaining blocks would shorten, and
+    // the fewest blocks that do (estimates can stay flat from one team size
+    // to the next while the last round of tiles fills up)
+    int best = -1, add = 0;
+    for (size_t k = 0; k < teams.size(); ++k) {
+      const Team& T = teams[k];
+      if (best >= 0 && T.load <= teams[best].load) continue;
+      int lim = G - used;
+      for (int i : T.inst) lim = std::min(lim, cap[i] - T.t);
+      for (int d = 1; d <= lim; ++d) {
+        double next = 0.0;
+        for (int i : T.inst) next += est(i, T.t + d);
+        if (next < T.load) {
+          best = (int)k;
+          add = d;
+          break;
+        }
       }
     }
     if (best < 0) break;
-    ++P.team[best];
-    ++used;
+    Team& T = teams[best];
+    T.t += add;
+    T.load = 0.0;
+    for (int i : T.inst) T.load += est(i, T.t);
+    used += add;
   }
   P.G = used;
   // block ids in XCD-major order: x, x+8, x+16, ... for x = 0..7
@@ -813,18 +952,30 @@ void plan_teams(int n, const ms_instance* inst, const std::vector<double>& sweep
   order.reserve(P.G);
   for (int x = 0; x < 8; ++x)
     for (int b = x; b < P.G; b += 8) order.push_back(b);
-  P.block_team.assign(P.G, 0);
-  P.block_rank.assign(P.G, 0);
-  P.first.assign(n, 0);
   // biggest teams first so they stay within as few XCDs as possible
-  std::vector<int> idx(n);
-  std::iota(idx.begin(), idx.end(), 0);
-  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return P.team[x] > P.team[y]; });
+  std::stable_sort(teams.begin(), teams.end(), [](const Team& x, const Team& y) {
+    return x.t > y.t;
+  });
+  P.team.assign(n, 1);
+  P.group.assign(n, 0);
+  P.first.assign(n, 0);
+  P.chain.clear();
+  P.block_off.assign(P.G, 0);
+  P.block_len.assign(P.G, 0);
+  P.block_rank.assign(P.G, 0);
   int pos = 0;
-  for (int i : idx) {
-    P.first[i] = pos;
-    for (int r = 0; r < P.team[i]; ++r, ++pos) {
-      P.block_team[order[pos]] = i;
+  for (size_t k = 0; k < teams.size(); ++k) {
+    const Team& T = teams[k];
+    const int off = (int)P.chain.size();
+    for (int i : T.inst) {
+      P.chain.push_back(i);
+      P.team[i] = T.t;
+      P.group[i] = (int)k;
+      P.first[i] = pos;
+    }
+    for (int r = 0; r < T.t; ++r, ++pos) {
+      P.block_off[order[pos]] = off;
+      P.block_len[order[pos]] = (int)T.inst.size();
       P.block_rank[order[pos]] = r;
     }
   }
@@ -843,6 +994,27 @@ int resident_blocks_of(K kernel) {
 
 int resident_blocks() { return resident_blocks_of(batched_kernel<false>); }
 
+// The block map on the device: per block its chain offset, chain length and
+// rank (3 G ints), then the chains (n ints).
+size_t map_ints(int n, int G) { return 3 * (size_t)G + (size_t)n; }
+
+std::vector<int> block_map(const Plan& P) {
+  std::vector<int> m;
+  m.reserve(map_ints((int)P.chain.size(), P.G));
+  m.insert(m.end(), P.block_off.begin(), P.block_off.end());
+  m.insert(m.end(), P.block_len.begin(), P.block_len.end());
+  m.insert(m.end(), P.block_rank.begin(), P.block_rank.end());
+  m.insert(m.end(), P.chain.begin(), P.chain.end());
+  return m;
+}
+
+void set_map(BatchK& a, const int* dmap, int G) {
+  a.block_off = dmap;
+  a.block_len = dmap + G;
+  a.block_rank = dmap + 2 * (size_t)G;
+  a.chain = dmap + 3 * (size_t)G;
+}
+
 size_t inst_bytes(const ms_grid& g, int mode, int team) {
   const size_t span = (size_t)field_span(g);
   size_t t = align_up(4 * (size_t)team * sizeof(double), 256) + 256;  // partials + barrier
@@ -855,7 +1027,7 @@ size_t inst_bytes(const ms_grid& g, int mode, int team) {
 // table, the block map and every instance's buffers with its largest team.
 size_t batch_bytes(int n, const ms_instance* inst, int mode, int G) {
   size_t t = probe_bytes(n) + align_up(sizeof(Inst) * n, 256) +
-             align_up(sizeof(int) * 2 * (size_t)G, 256) + 256;
+             align_up(map_ints(n, G) * sizeof(int), 256) + 256;
   for (int i = 0; i < n; ++i) t += inst_bytes(inst[i].grid, mode, team_cap(inst[i].grid, G));
   return t;
 }
@@ -915,9 +1087,6 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   if (!res) return set_error(MS_EINVAL, "jacobi_solve_batched: res is NULL");
   const int G = resident_blocks();
   if (G <= 0) return set_error(MS_EHIP, "jacobi_solve_batched: occupancy query failed");
-  if (G < n)
-    return set_error(MS_EUNSUPPORTED, "jacobi_solve_batched: %d instances need %d resident "
-                     "blocks, the device holds %d", n, n, G);
   const size_t need = batch_bytes(n, inst, o->precision, G);
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "jacobi_solve_batched: workspace needs %zu bytes", need);
@@ -926,10 +1095,14 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   std::vector<double> est;
   if (int rc = batch_estimates(n, inst, o->rel_tol, ws.take<char>(probe_bytes(n)), s, est))
     return rc;
+  // the FP32 inner solves sweep twice per team barrier (every block of the
+  // grid must be resident at once for the team barriers)
+  const bool pairs = two_sweep_inner(n, inst, o->precision) &&
+                     resident_blocks_of(batched_kernel<true>) >= G;
   Plan P;
-  plan_teams(n, inst, est, G, P);
+  plan_teams(n, inst, est, G, pairs, P);
   Inst* dinst = ws.take<Inst>(n);
-  int* dmap = ws.take<int>(2 * (size_t)P.G);
+  int* dmap = ws.take<int>(map_ints(n, P.G));
   int* derr = ws.take<int>(64);
   std::vector<Inst> h(n);
   for (int i = 0; i < n; ++i) {
@@ -958,9 +1131,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
     if (!q.part || !q.bar || (o->precision == MS_SOLVE_F64 ? !q.xb : !q.e1))
       return set_error(MS_EWORKSPACE, "jacobi_solve_batched: workspace carve failed");
   }
-  std::vector<int> map(2 * (size_t)P.G);
-  std::copy(P.block_team.begin(), P.block_team.end(), map.begin());
-  std::copy(P.block_rank.begin(), P.block_rank.end(), map.begin() + P.G);
+  const std::vector<int> map = block_map(P);
   MS_HIP_TRY(hipMemcpyAsync(dinst, h.data(), sizeof(Inst) * n, hipMemcpyHostToDevice, s));
   MS_HIP_TRY(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, s));
   MS_HIP_TRY(hipMemsetAsync(derr, 0, 256, s));
@@ -972,8 +1143,7 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
                                 hipMemcpyDeviceToDevice, s));
   BatchK a{};
   a.inst = dinst;
-  a.block_team = dmap;
-  a.block_rank = dmap + P.G;
+  set_map(a, dmap, P.G);
   a.error = derr;
   a.ninst = n;
   a.mode = o->precision;
@@ -984,12 +1154,6 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   a.max_inner = o->max_inner;
   a.stall = o->stall_window;
   a.spin_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz real-time clock
-  // the two-sweep march indexes within a z plane with 32-bit offsets
-  // (MS_BATCH_TB=1 selects one sweep per barrier, kept as a cross-check)
-  bool pairs = !(getenv("MS_BATCH_TB") && atoi(getenv("MS_BATCH_TB")) == 1);
-  for (int i = 0; i < n; ++i) pairs = pairs && inst[i].grid.sz < INT32_MAX;
-  // every block of the grid must be resident at once (team barriers)
-  pairs = pairs && resident_blocks_of(batched_kernel<true>) >= resident_blocks();
   // One persistent launch, replayed from a captured graph.
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -1042,9 +1206,39 @@ extern "C" size_t jacobi_batched_plan_workspace_bytes(int n) {
   return n < 1 ? 0 : probe_bytes(n);
 }
 
+extern "C" int jacobi_batched_plan_from_estimates(int n, const ms_grid* grids,
+                                                  const double* est_sweeps, int blocks,
+                                                  int precision, int* team_sizes,
+                                                  int* groups, int* grid_blocks) {
+  clear_error();
+  if (n < 1 || !grids || !est_sweeps)
+    return set_error(MS_EINVAL, "jacobi_batched_plan_from_estimates: no instances");
+  if (blocks < 1)
+    return set_error(MS_EINVAL, "jacobi_batched_plan_from_estimates: blocks must be >= 1");
+  std::vector<ms_instance> inst(n);
+  std::vector<double> est(est_sweeps, est_sweeps + n);
+  for (int i = 0; i < n; ++i) {
+    if (int rc = check_grid(&grids[i], "jacobi_batched_plan_from_estimates")) return rc;
+    if (!(est[i] >= 1.0) || !std::isfinite(est[i]))
+      return set_error(MS_EINVAL, "jacobi_batched_plan_from_estimates: estimate %d must be "
+                       "finite and >= 1", i);
+    inst[i] = ms_instance{grids[i], nullptr, nullptr};
+  }
+  Plan P;
+  if (precision != MS_SOLVE_F64 && precision != MS_SOLVE_F32_REFINED)
+    return set_error(MS_EUNSUPPORTED, "jacobi_batched_plan_from_estimates: precision %d",
+                     precision);
+  plan_teams(n, inst.data(), est, blocks, two_sweep_inner(n, inst.data(), precision), P);
+  if (team_sizes) std::copy(P.team.begin(), P.team.end(), team_sizes);
+  if (groups) std::copy(P.group.begin(), P.group.end(), groups);
+  if (grid_blocks) *grid_blocks = P.G;
+  return MS_OK;
+}
+
 extern "C" int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solve_opts* o,
-                                   int* team_sizes, int* grid_blocks, double* est_sweeps,
-                                   void* work, size_t work_bytes, void* stream) {
+                                   int* team_sizes, int* groups, int* grid_blocks,
+                                   double* est_sweeps, void* work, size_t work_bytes,
+                                   void* stream) {
   clear_error();
   if (int rc = check_batch(n, inst, o)) return rc;
   const int G = resident_blocks();
@@ -1057,8 +1251,12 @@ extern "C" int jacobi_batched_plan(int n, const ms_instance* inst, const ms_solv
                                static_cast<hipStream_t>(stream), est))
     return rc;
   Plan P;
-  plan_teams(n, inst, est, std::max(G, n), P);
+  plan_teams(n, inst, est, G,
+             two_sweep_inner(n, inst, o->precision) &&
+                 resident_blocks_of(batched_kernel<true>) >= G,
+             P);
   if (team_sizes) std::copy(P.team.begin(), P.team.end(), team_sizes);
+  if (groups) std::copy(P.group.begin(), P.group.end(), groups);
   if (grid_blocks) *grid_blocks = P.G;
   if (est_sweeps) std::copy(est.begin(), est.end(), est_sweeps);
   return MS_OK;
@@ -1192,7 +1390,7 @@ size_t tune_inst_bytes(const ms_grid& g, int team) {
 
 size_t tune_bytes(int n, const ms_instance* inst, int G) {
   size_t t = probe_bytes(n) + align_up(sizeof(Inst) * n, 256) +
-             align_up(sizeof(int) * 2 * (size_t)G, 256) + 256;
+             align_up(map_ints(n, G) * sizeof(int), 256) + 256;
   for (int i = 0; i < n; ++i) t += tune_inst_bytes(inst[i].grid, team_cap(inst[i].grid, G));
   return t;
 }
@@ -1218,9 +1416,6 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
   const int Gt = resident_blocks_of(batched_tune_kernel);
   if (G <= 0 || Gt <= 0)
     return set_error(MS_EHIP, "jacobi_batched_autotune: occupancy query failed");
-  if (G < n)
-    return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: %d instances need %d resident "
-                     "blocks, the device holds %d", n, n, G);
   const size_t need = tune_bytes(n, inst, G);
   if (!work || work_bytes < need)
     return set_error(MS_EWORKSPACE, "jacobi_batched_autotune: workspace needs %zu bytes", need);
@@ -1230,12 +1425,15 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
   if (int rc = batch_estimates(n, inst, o->rel_tol, ws.take<char>(probe_bytes(n)), s, est))
     return rc;
   Plan P;
-  plan_teams(n, inst, est, G, P);
+  plan_teams(n, inst, est, G,
+             two_sweep_inner(n, inst, o->precision) &&
+                 resident_blocks_of(batched_kernel<true>) >= G,
+             P);
   if (P.G > Gt)
     return set_error(MS_EUNSUPPORTED, "jacobi_batched_autotune: the timing kernel holds only %d "
                      "resident blocks, the plan has %d", Gt, P.G);
   Inst* dinst = ws.take<Inst>(n);
-  int* dmap = ws.take<int>(2 * (size_t)P.G);
+  int* dmap = ws.take<int>(map_ints(n, P.G));
   int* derr = ws.take<int>(64);
   std::vector<Inst> h(n);
   for (int i = 0; i < n; ++i) {
@@ -1263,14 +1461,11 @@ extern "C" int jacobi_batched_autotune(int n, const ms_instance* inst, const ms_
     MS_HIP_TRY(hipMemsetAsync(A, 0, span * 8, s));
     MS_HIP_TRY(hipMemsetAsync(B, 0, span * 8, s));
   }
-  std::vector<int> map(2 * (size_t)P.G);
-  std::copy(P.block_team.begin(), P.block_team.end(), map.begin());
-  std::copy(P.block_rank.begin(), P.block_rank.end(), map.begin() + P.G);
+  const std::vector<int> map = block_map(P);
   MS_HIP_TRY(hipMemcpyAsync(dmap, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, s));
   BatchK a{};
   a.inst = dinst;
-  a.block_team = dmap;
-  a.block_rank = dmap + P.G;
+  set_map(a, dmap, P.G);
   a.error = derr;
   a.ninst = n;
   a.mode = o->precision;

@@ -77,12 +77,41 @@ def test_many_small_instances_and_determinism():
 def test_plan_gives_every_instance_a_team():
     dims = synth.batch_sizes(64, 4)
     xs = [ms.alloc_field(*d) for d in dims[:8]]
-    teams, g = ms.batched_plan(xs, [None] * 8, precision=ms.MS_SOLVE_F32_REFINED)
-    assert all(t >= 1 for t in teams) and sum(teams) == g
+    teams, g, groups = ms.batched_plan(xs, [None] * 8, precision=ms.MS_SOLVE_F32_REFINED,
+                                       with_groups=True)
+    size = {}
+    for t, k in zip(teams, groups):
+        assert t >= 1 and size.setdefault(k, t) == t
+    assert sum(size.values()) == g
     # bigger instances (more cells x more sweeps) get at least as many blocks
     work = [np.prod(d) * max(d) ** 2 for d in dims[:8]]
     order = np.argsort(work)
     assert teams[order[-1]] >= teams[order[0]]
+
+
+def test_more_instances_than_resident_blocks():
+    """Teams run chains of instances, so a batch may hold more instances
+    than the device has resident blocks; each still reaches the tolerance
+    as the oracle measures it, and matches its single solve."""
+    note("case: batched, 600 tiny instances")
+    dims = synth.batch_sizes(600, 21, lo=2, hi=9)
+    probs = _instances(dims, 700)
+    xs = [dev(u) for u, _ in probs]
+    fs = [dev(f) for _, f in probs]
+    teams, g, groups = ms.batched_plan(xs, fs, precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8,
+                                       with_groups=True)
+    assert len(set(groups)) <= g < len(xs)
+    infos = ms.jacobi_solve_batched(xs, fs, precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8)
+    for (u, f), x, info in zip(probs, xs, infos):
+        assert info.status == ms.MS_OK
+        res0 = oracle.residual_norm(oracle.zero_interior(u), f)
+        assert oracle.residual_norm(host(x), f) <= 1e-8 * res0 * (1 + 1e-9)
+    for k in (0, 299, 599):
+        u, f = probs[k]
+        y = dev(u)
+        one = ms.jacobi_solve(y, dev(f), precision=ms.MS_SOLVE_F32_REFINED, rel_tol=1e-8)
+        assert (one.sweeps, one.outer_iters) == (infos[k].sweeps, infos[k].outer_iters)
+        assert np.array_equal(host(y), host(xs[k]))
 
 
 def _solve_with_shape(probs, shape, precision):
