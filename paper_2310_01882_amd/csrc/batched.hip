@@ -104,6 +104,7 @@ struct BatchK {
   int64_t max_sweeps;
   int max_outer, max_inner, stall;
   int64_t spin_ticks;  // barrier time limit in s_memrealtime ticks
+  int xcd_barriers;    // teams on one XCD synchronise through its L2 only
 };
 
 __device__ __forceinline__ int64_t off3(const Inst& q, int i, int j, int k) {
@@ -141,22 +142,49 @@ __device__ __forceinline__ int num_tiles(const Inst& q) { return q.tiles_x * q.t
 // generation is the block's own barrier count (`epoch`, thread 0 only), so
 // the generation word is never read before the arrival. A one-block team
 // needs only the workgroup barrier.
-__device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag, unsigned* epoch) {
+//
+// A team whose blocks all run on one XCD (epoch->local, decided at the
+// instance's first barrier from the blocks' XCC ids) shares that XCD's L2,
+// which then holds every write of the team: a release only has to wait
+// until the block's stores have reached it (every wave waits for its own
+// vector memory operations before the workgroup barrier) and an acquire
+// only has to drop the CU's L1, instead of writing back and invalidating
+// the whole L2, which every other team on the XCD pays for too. These are
+// the sequences the compiler itself emits for workgroup scope when a
+// workgroup's waves may run on different CUs of an XCD (s_waitcnt vmcnt(0)
+// to release; s_waitcnt vmcnt(0) and buffer_inv sc0 to acquire).
+struct TeamSync {
+  unsigned epoch;  // barriers passed in the current instance (thread 0 only)
+  int local;       // the team's blocks share one XCD
+};
+
+__device__ __forceinline__ void wait_vector_memory() {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+}
+
+__device__ __forceinline__ void invalidate_l1() {
+  asm volatile("buffer_inv sc0\n\ts_waitcnt vmcnt(0)" ::: "memory");
+}
+
+__device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag, TeamSync* epoch) {
   if (q.team == 1) {
     __syncthreads();
     return true;
   }
+  const bool local = epoch->local != 0;
+  if (local) wait_vector_memory();
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
     unsigned* cnt = q.bar;
     unsigned* gen = q.bar + 1;
-    const unsigned e = ++*epoch;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned e = ++epoch->epoch;
+    if (!local) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned arrived = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
     if (arrived == (unsigned)q.team - 1) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+      if (local) invalidate_l1();
+      else __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
       __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(gen, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
@@ -173,12 +201,20 @@ __device__ bool team_barrier(const BatchK& a, Inst& q, int* s_flag, unsigned* ep
         }
         __builtin_amdgcn_s_sleep(2);
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      if (local) invalidate_l1();
+      else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     *s_flag = ok;
   }
   __syncthreads();
   return *s_flag != 0;
+}
+
+// This block's XCD (the XCC id hardware register).
+__device__ __forceinline__ unsigned xcc_id() {
+  unsigned v;
+  asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+  return v;
 }
 
 // Sum of the team's partials in slot `slot` (fixed order, every block alike).
@@ -321,7 +357,7 @@ template <typename T>
 __device__ int64_t team_jacobi(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
                                double tol_rel, double ref_fixed, bool ref_from_first,
                                int64_t cap, double* red, double* cell, double* hist,
-                               int* s_flag, unsigned* epoch, int* status) {
+                               int* s_flag, TeamSync* epoch, int* status) {
   double ref = ref_fixed;
   for (int64_t j = 0;; ++j) {
     const T* src = (j & 1) ? b1 : b0;
@@ -380,7 +416,7 @@ __device__ void sweep2_tiles(const Inst& q, int rank, const float* __restrict__ 
 // Returns K and its buffer in *answer, or -1 on failure.
 __device__ int64_t team_jacobi_pairs(const BatchK& a, Inst& q, int rank, float* b0, float* b1,
                                      const float* f, double tol_rel, int64_t cap, double* red,
-                                     double* cell, double* hist, int* s_flag, unsigned* epoch,
+                                     double* cell, double* hist, int* s_flag, TeamSync* epoch,
                                      int* status, float** answer) {
   double ref = 0.0;
   for (int64_t L = 0;; ++L) {
@@ -435,19 +471,24 @@ __device__ int64_t team_jacobi_pairs(const BatchK& a, Inst& q, int rank, float* 
 // barrier's time limit or another team's error), and the block then leaves.
 template <bool PAIRS>
 __device__ bool solve_instance(const BatchK& a, Inst& q, int rank, double* red, double* cellp,
-                               double* hist, int* sflag, unsigned* sepoch) {
+                               double* hist, int* sflag, TeamSync* sepoch) {
   double& cell = *cellp;
   int& s_flag = *sflag;
-  unsigned& s_epoch = *sepoch;
-  if (threadIdx.x == 0) s_epoch = 0;  // the instance's barrier words start at zero
+  TeamSync& s_epoch = *sepoch;
+  if (threadIdx.x == 0) s_epoch = TeamSync{0, 0};  // the instance's barrier words start at zero
   const double ncells = (double)q.nx * q.ny * q.nz;
   int status = MS_OK;
   if (rank == 0 && threadIdx.x == 0) q.t_start = (int64_t)__builtin_amdgcn_s_memrealtime();
 
-  // reference norm ||r(u^0)|| (interior zeroed)
+  // reference norm ||r(u^0)|| (interior zeroed); each block also posts its
+  // XCD in slot 3 of the partials, unused until the second barrier
   {
     const double mine = block_sum(residual_tiles(q, rank, true, nullptr, 0.0), red);
-    if (threadIdx.x == 0) q.part[rank] = mine;
+    if (threadIdx.x == 0) {
+      q.part[rank] = mine;
+      __hip_atomic_store(q.part + 3 * (int64_t)q.team + rank, (double)xcc_id(),
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (a.mode == MS_SOLVE_F32_REFINED) {
       zero_span<float>(q, rank, q.rhat);
       zero_span<float>(q, rank, q.e0);
@@ -455,6 +496,16 @@ __device__ bool solve_instance(const BatchK& a, Inst& q, int rank, double* red, 
     }
     if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;
   }
+  // every block reads the same table, so the team takes the same decision
+  if (threadIdx.x == 0 && a.xcd_barriers && q.team > 1) {
+    const double* x = q.part + 3 * (int64_t)q.team;
+    const double first = __hip_atomic_load(x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int same = 1;
+    for (int r = 1; r < q.team; ++r)
+      same &= __hip_atomic_load(x + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == first;
+    s_epoch.local = same;
+  }
+  __syncthreads();
   const double res0 = bcast(sqrt(team_sum(q, 0, red)), &cell);
   if (!team_barrier(a, q, &s_flag, &s_epoch)) return false;  // partial slot 0 is reused below
 
@@ -555,7 +606,7 @@ void batched_kernel(BatchK a) {
   __shared__ double cell;
   __shared__ double hist[kStallMax + 1];
   __shared__ int s_flag;
-  __shared__ unsigned s_epoch;  // barriers passed in the current instance (thread 0 only)
+  __shared__ TeamSync s_epoch;  // barriers passed in the current instance, barrier kind
   const int off = a.block_off[blockIdx.x], len = a.block_len[blockIdx.x];
   const int rank = a.block_rank[blockIdx.x];
   for (int c = 0; c < len; ++c)
@@ -570,7 +621,7 @@ void batched_kernel(BatchK a) {
 // ticks.
 template <typename T>
 __device__ void tune_team(const BatchK& a, Inst& q, int rank, T* b0, T* b1, const T* f,
-                          int nsweeps, double* red, int* s_flag, unsigned* epoch) {
+                          int nsweeps, double* red, int* s_flag, TeamSync* epoch) {
   if (!team_barrier(a, q, s_flag, epoch)) return;
   const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
   double chk = 0.0;
@@ -592,12 +643,12 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
 void batched_tune_kernel(BatchK a, int nsweeps) {
   __shared__ double red[kBatchWaves];
   __shared__ int s_flag;
-  __shared__ unsigned s_epoch;
+  __shared__ TeamSync s_epoch;
   const int off = a.block_off[blockIdx.x], len = a.block_len[blockIdx.x];
   const int rank = a.block_rank[blockIdx.x];
   for (int c = 0; c < len; ++c) {
     Inst& q = a.inst[a.chain[off + c]];
-    if (threadIdx.x == 0) s_epoch = 0;
+    if (threadIdx.x == 0) s_epoch = TeamSync{0, 0};
     if (a.mode == MS_SOLVE_F64)
       tune_team<double>(a, q, rank, q.x, q.xb, q.f, nsweeps, red, &s_flag, &s_epoch);
     else
@@ -1154,6 +1205,9 @@ extern "C" int jacobi_solve_batched(int n, const ms_instance* inst, const ms_sol
   a.max_inner = o->max_inner;
   a.stall = o->stall_window;
   a.spin_ticks = (int64_t)100000000 * 20;  // 20 s at the 100 MHz real-time clock
+  // MS_BATCH_XCD_BARRIER=0 keeps agent-scope barriers for every team
+  const char* xb = getenv("MS_BATCH_XCD_BARRIER");
+  a.xcd_barriers = !(xb && atoi(xb) == 0);
   // One persistent launch, replayed from a captured graph.
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
