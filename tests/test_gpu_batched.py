@@ -165,6 +165,26 @@ def test_two_sweeps_per_barrier_gives_the_same_fields(monkeypatch, shape):
         assert oracle.residual_norm(fb, f) <= 1e-8 * res0 * (1 + 1e-9)
 
 
+@pytest.mark.parametrize("precision", [ms.MS_SOLVE_F32_REFINED, ms.MS_SOLVE_F64])
+def test_xcd_local_barriers_give_the_same_fields(monkeypatch, precision):
+    """Teams whose blocks share an XCD synchronise through its L2 by default;
+    MS_BATCH_XCD_BARRIER=0 keeps agent-scope fences for every team. Same
+    counts and fields, on a batch big enough for multi-block teams."""
+    note(f"case: batched XCD-local barriers precision={precision}")
+    dims = [(200, 120, 60), (130, 64, 40), (64, 64, 64)] + DIMS
+    probs = _instances(dims, 130, halo=True)
+    teams, _ = ms.batched_plan([dev(u) for u, _ in probs], [dev(f) for _, f in probs],
+                               precision=precision, rel_tol=1e-8)
+    assert max(teams) > 1
+    infos, got = _solve_with_shape(probs, None, precision)
+    monkeypatch.setenv("MS_BATCH_XCD_BARRIER", "0")
+    ref_infos, ref = _solve_with_shape(probs, None, precision)
+    for a, b, fa, fb in zip(ref_infos, infos, ref, got):
+        assert b.status == ms.MS_OK
+        assert (a.sweeps, a.outer_iters) == (b.sweeps, b.outer_iters)
+        assert np.array_equal(fa, fb)
+
+
 def test_autotune_picks_valid_shapes_and_leaves_x_alone():
     note("case: batched autotune 16 instances")
     dims = synth.batch_sizes(16, 4, lo=16, hi=96)
