@@ -54,11 +54,21 @@ __device__ __forceinline__ double march_residual(double xp, double xm, double yp
 // (the lane shifts read neighbours). Per-cell arithmetic is the single
 // sweep's: (S - f) * c6 with S in the order x+, x-, y+, y-, z+, z-.
 // Offsets within a z plane are 32-bit: the caller guarantees sz < 2^31.
+// The fields are device (global) memory: the pointers are taken as such, so
+// that loads and stores are global rather than flat instructions even when
+// the caller read the pointers from memory (flat ones also count against
+// the LDS counter, and need a 64-bit address per lane).
 template <typename T, bool HAS_F, int R>
-__device__ __forceinline__ void two_sweep_march(const T* __restrict__ src, T* __restrict__ dst,
-                                                const T* __restrict__ f, int nx, int ny, int nz,
-                                                int64_t sy, int64_t sz, int i, int j0, int z0,
-                                                int z1, T c6, double& acc_a, double& acc_b) {
+__device__ __forceinline__ void two_sweep_march(const T* __restrict__ src_any,
+                                                T* __restrict__ dst_any,
+                                                const T* __restrict__ f_any, int nx, int ny,
+                                                int nz, int64_t sy, int64_t sz, int i, int j0,
+                                                int z0, int z1, T c6, double& acc_a,
+                                                double& acc_b) {
+  using GT = __attribute__((address_space(1))) T;
+  const GT* __restrict__ src = (const GT*)src_any;
+  GT* __restrict__ dst = (GT*)dst_any;
+  const GT* __restrict__ f = (const GT*)f_any;
   const int lane = threadIdx.x & 63;
   const bool colA = lane >= 1 && lane <= 62, colB = lane >= 2 && lane <= 61;
   const bool xin = i >= 0 && i < nx;
@@ -76,13 +86,13 @@ __device__ __forceinline__ void two_sweep_march(const T* __restrict__ src, T* __
   auto plane = [&](int z) { return (int64_t)(min(max(z, -1), nz) + 1) * sz; };
   // u_k rows j0-2 .. j0+R+1 (q = 0 .. R+3) at level z
   auto load_u = [&](T (&r)[R + 4], int z) {
-    const T* pl = src + plane(z);
+    const GT* pl = src + plane(z);
 #pragma unroll
     for (int q = 0; q < R + 4; ++q) r[q] = pl[roff[q]];
   };
   // f rows j0-1 .. j0+R (q = 1 .. R+2) at level z
   auto load_f = [&](T (&r)[R + 2], int z) {
-    const T* pl = HAS_F ? f + plane(z) : f;
+    const GT* pl = HAS_F ? f + plane(z) : f;
 #pragma unroll
     for (int q = 0; q < R + 2; ++q) r[q] = HAS_F ? pl[roff[q + 1]] : T(0);
   };
