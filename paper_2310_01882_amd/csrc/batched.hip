@@ -968,7 +968,16 @@ void plan_teams(int n, const ms_instance* inst, const std::vector<double>& sweep
     else lo = mid;
   }
   std::vector<Team> teams;
-  pack(hi, &teams, &need);
+  if (!pack(hi, &teams, &need) || need > G) {
+    // not reached (hi is feasible by construction); one block running every
+    // instance in turn is always a valid plan
+    teams.assign(1, Team{1, 0.0, {}});
+    for (int i = 0; i < n; ++i) {
+      teams[0].inst.push_back(i);
+      teams[0].load += est(i, 1);
+    }
+    need = 1;
+  }
   int used = (int)need;
   while (used < G) {
     // the longest team that some of the remaining blocks would shorten, and

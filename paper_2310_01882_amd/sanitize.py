@@ -30,7 +30,8 @@ SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined
        "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer",
        "-Xarch_host", "-g"]
 TESTS = [os.path.join(ROOT, "tests", "test_abi_host.py"),
-         os.path.join(ROOT, "tests", "test_jit_host.py")]
+         os.path.join(ROOT, "tests", "test_jit_host.py"),
+         os.path.join(ROOT, "tests", "test_batch_plan_host.py")]
 
 
 def _compile(src):
